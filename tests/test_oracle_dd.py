@@ -1,0 +1,113 @@
+"""Pins of the oracle's domain-decomposition iteration (section 2.3, Alg. 1, App. A)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dd, dense, solve
+
+
+def _dense_blocks(p, st, zb):
+    """Dense A of eq. (8) and the index sets of the z-slab blocks (component-major ordering)."""
+    A = dense.system_matrix(p.n, p.h, p.origin, st.k0, p.sigma0, st.dsig)
+    nx, ny, nz = p.n
+    N = nx * ny * nz
+    cell = np.arange(N).reshape(nz, ny, nx)
+    idx = []
+    for z0, z1 in zip(zb[:-1], zb[1:]):
+        c = cell[z0:z1].ravel()
+        idx.append(np.concatenate([c + q * N for q in range(3)]))
+    return A, idx
+
+
+def test_single_block_equals_full_domain_gmres():
+    p = synth.random_problem((6, 6, 6), seed=21, contrast=2.0)
+    st = solve.setup(p)
+    E_full, inf_full = solve.solve_full(st, form="conventional", tol=1e-9)
+    E_dd, inf_dd = dd.dd_solve(st, (0, 6), scheme="gs", adaptive=False, inner_tol_fixed=1e-9,
+                               tol=1e-9)
+    assert inf_dd["sweeps"] == 1
+    assert inf_dd["total_its"] == inf_full["its"]
+    assert np.linalg.norm(E_dd - E_full) / np.linalg.norm(E_full) < 1e-12
+
+
+def test_gauss_seidel_sweep_equals_app_a_forward_substitution():
+    """App. A: one GS sweep is E^{k+1} = (D + L)^-1 [E0 - U E^k]; with (near-)exact inner solves
+    the oracle's sweep equals this dense block forward substitution, sweep by sweep."""
+    p = synth.random_problem((6, 6, 6), seed=22, contrast=1.5)
+    st = solve.setup(p)
+    zb = (0, 2, 4, 6)
+    A, idx = _dense_blocks(p, st, zb)
+    M = len(idx)
+    D_L = np.zeros_like(A)
+    U = np.zeros_like(A)
+    for i in range(M):
+        for j in range(M):
+            blk = np.ix_(idx[i], idx[j])
+            if j <= i:
+                D_L[blk] = A[blk]
+            else:
+                U[blk] = A[blk]
+    e0 = st.E0.ravel()
+    Ek = e0.copy()
+    E_prev = st.E0.copy()
+    for sweep in range(3):
+        Ek = np.linalg.solve(D_L, e0 - U @ Ek)
+        E_or, _ = dd.dd_solve(st, zb, scheme="gs", adaptive=False, inner_tol_fixed=1e-13,
+                              tol=0.0, max_sweeps=1, E_init=E_prev)
+        assert np.linalg.norm(E_or.ravel() - Ek) / np.linalg.norm(Ek) < 1e-11
+        E_prev = E_or
+
+
+def test_jacobi_sweep_equals_block_diagonal_step():
+    """Eq. (23): E^{k+1} = D^-1 [E0 - (L + U) E^k]."""
+    p = synth.random_problem((6, 6, 6), seed=23, contrast=1.5)
+    st = solve.setup(p)
+    zb = (0, 3, 6)
+    A, idx = _dense_blocks(p, st, zb)
+    D = np.zeros_like(A)
+    for i in range(len(idx)):
+        blk = np.ix_(idx[i], idx[i])
+        D[blk] = A[blk]
+    LU = A - D
+    e0 = st.E0.ravel()
+    Ek = np.linalg.solve(D, e0 - LU @ e0)
+    E_or, _ = dd.dd_solve(st, zb, scheme="jacobi", adaptive=False, inner_tol_fixed=1e-13,
+                          tol=0.0, max_sweeps=1)
+    assert np.linalg.norm(E_or.ravel() - Ek) / np.linalg.norm(Ek) < 1e-11
+
+
+@pytest.mark.parametrize("scheme", ["gs", "jacobi"])
+@pytest.mark.parametrize("adaptive", [True, False])
+def test_dd_converges_to_dense_solution(scheme, adaptive):
+    p = synth.random_problem((8, 8, 8), seed=24, contrast=1.0)
+    st = solve.setup(p)
+    Ed = dense.dense_solve(p.n, p.h, p.origin, st.k0, p.sigma0, st.dsig, st.E0)
+    E, info = dd.dd_solve(st, (0, 4, 8), scheme=scheme, adaptive=adaptive, tol=1e-8,
+                          inner_tol_fixed=1e-9)
+    assert info["converged"]
+    assert info["relres"][-1] <= 1e-8
+    Ea, Ead = E - st.E0, Ed - st.E0
+    assert np.linalg.norm(Ea - Ead) / np.linalg.norm(Ead) < 1e-6
+    # the full residual decreases monotonically for this weakly coupled case
+    assert all(b < a for a, b in zip(info["relres"], info["relres"][1:]))
+
+
+def test_zero_contrast_block_takes_no_inner_iterations():
+    p = synth.random_problem((6, 6, 6), seed=25, contrast=1.0)
+    p.sigma6[:, 3:] = 0.0
+    p.sigma6[:3, 3:] = p.sigma0
+    st = solve.setup(p)
+    E, info = dd.dd_solve(st, (0, 3, 6), scheme="gs", tol=1e-9)
+    assert info["converged"]
+    assert all(its[1] == 0 for its in info["block_its"])
+    Ed = dense.dense_solve(p.n, p.h, p.origin, st.k0, p.sigma0, st.dsig, st.E0)
+    assert np.linalg.norm(E - Ed) / np.linalg.norm(Ed) < 1e-8
+
+
+def test_cie_inner_solves_reach_same_fixed_point():
+    p = synth.random_problem((6, 6, 6), seed=26, contrast=4.0)
+    st = solve.setup(p)
+    E1, i1 = dd.dd_solve(st, (0, 3, 6), form="conventional", tol=1e-9)
+    E2, i2 = dd.dd_solve(st, (0, 3, 6), form="cie", tol=1e-9)
+    assert i1["converged"] and i2["converged"]
+    assert np.linalg.norm(E1 - E2) / np.linalg.norm(E1) < 1e-8
