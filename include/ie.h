@@ -1,0 +1,230 @@
+/*
+ * ie.h - C ABI of the MI355X (gfx950) integral-equation solver for 3-D induction-log
+ * modelling with domain-decomposition preconditioning (Saputera et al., GJI).
+ *
+ * The library solves the discretised electric-field integral equation of eq. (8),
+ *     (I - G dsigma) E = E0,
+ * on a regular voxel grid, with G the whole-space electric Green's tensor of eqs. (5)-(7)
+ * discretised as in section 2.2 and applied by zero-padded FFT convolution (eq. 10),
+ * either directly (restarted GMRES, section 2.2) or by block Gauss-Seidel / Jacobi over
+ * z-slab sub-domains (section 2.3, eqs. 19-24, Alg. 1).
+ *
+ * Conventions for every entry point:
+ *  - Return value: IE_OK (0) on success; IE_ENOCONV (1) when an iteration hit its limit
+ *    (outputs then hold the best iterate and statistics are filled); a negative code on
+ *    error.  Nothing aborts, exits or throws across this boundary.  ie_last_error()
+ *    returns a thread-local description of the last non-zero status.
+ *  - Complex arrays are interleaved (re, im).  Fields use the layout [3][nz][ny][nx]
+ *    (component-major, x fastest); component order x, y, z.
+ *  - Conductivity tensors use the layout [6][nz][ny][nx] of real float64 in the order
+ *    xx, yy, zz, xy, xz, yz (S/m); the tensor is symmetric (App. C) and must be positive
+ *    definite in every cell.
+ *  - Array pointers are DEVICE pointers unless stated otherwise; they are owned by the
+ *    caller and must stay valid until the work queued on `stream` has finished.  The
+ *    library never frees caller memory.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Entry points queue their work
+ *    on it and synchronise with it only where stated.
+ *  - A context owns the precomputed FFT of the discretised Green's tensor for one grid and
+ *    medium (and, when a partition is given, for each distinct sub-domain shape) plus the
+ *    work buffers.  A context may be used by one thread at a time.
+ */
+#ifndef IE_H
+#define IE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define IE_OK          0
+#define IE_ENOCONV     1
+#define IE_EINVAL    (-1)
+#define IE_ENOMEM    (-2)
+#define IE_EDEVICE   (-3)
+#define IE_ESTATE    (-4)
+
+/* precision of the internal arithmetic */
+#define IE_FP64   1   /* complex128 throughout */
+#define IE_MIXED  2   /* complex64 convolutions and inner Krylov vectors; float64 residuals,
+                         Arnoldi scalars, Givens rotations and solution accumulation */
+
+/* form of the operator handed to the Krylov solver (both give the same E, eq. 8) */
+#define IE_CONVENTIONAL  0   /* (I - G dsigma) E = E0, the paper's choice (end of section 2.3) */
+#define IE_CIE           1   /* contraction form: (I - b - 2 sigma0 G b) e = sqrt(sigma0) E0,
+                                b = dsigma (2 sigma0 I + dsigma)^-1, E = 2 sqrt(sigma0)
+                                (2 sigma0 I + dsigma)^-1 e (introduction; end of section 2.3) */
+#define IE_GREEN_ONLY    2   /* ie_matvec only: y = G x, the bare convolution of eq. (10) */
+#define IE_SCATTER       3   /* ie_matvec only: y = G (dsigma x), the scattered field of eq. (3) */
+
+/* outer schemes (section 2.3) */
+#define IE_GS      0   /* block Gauss-Seidel, eqs. (19)-(22) */
+#define IE_JACOBI  1   /* block Jacobi, eqs. (23)-(24) */
+
+/* initial guess of ie_dd_solve */
+#define IE_INIT_BACKGROUND 0  /* E := E0, as Alg. 1 */
+#define IE_INIT_USER       1  /* E_total holds the initial guess on entry (resume) */
+#define IE_INIT_LEARNED    2  /* first-sweep block guesses from a trained network (ie_nn_*) */
+
+/* source kinds */
+#define IE_MAG_DIPOLE   0   /* magnetic dipole, J^H = i omega mu0 m delta (eq. 1) */
+#define IE_ELEC_DIPOLE  1   /* electric dipole, E0 = G^E p */
+
+typedef struct {
+    int32_t nx, ny, nz;   /* cells per axis (each 1..512) */
+    double  h;            /* cubic cell size (m), > 0 */
+    double  origin[3];    /* corner of cell (0,0,0); cell (i,j,k) centre = origin + (i+.5,j+.5,k+.5) h */
+} ie_grid;
+
+typedef struct {
+    double sigma0;    /* homogeneous isotropic background conductivity (S/m), > 0 (section 2.1) */
+    double freq_hz;   /* frequency (Hz), > 0 */
+    double mu0;       /* magnetic permeability (H/m); 0 selects 4e-7 pi */
+} ie_medium;
+
+typedef struct {
+    double  pos[3];     /* position (m); must not coincide with a cell centre */
+    double  moment[3];  /* dipole moment (A m^2 for magnetic, A m for electric) */
+    int32_t kind;       /* IE_MAG_DIPOLE or IE_ELEC_DIPOLE */
+} ie_source;
+
+typedef struct {
+    int32_t        nblocks;   /* M >= 1 */
+    const int32_t* z_bounds;  /* HOST array of M+1 strictly increasing z cell indices, 0 .. nz */
+} ie_partition;
+
+typedef struct {
+    double  tol;         /* stop when ||b - A x|| / ||b|| <= tol (eq. 9 for the full domain) */
+    int32_t restart;     /* Krylov dimension per cycle (section 3.1 uses 10); 1..16 */
+    int32_t max_its;     /* limit on Arnoldi steps (operator applications); > 0 */
+    int32_t precision;   /* IE_FP64 or IE_MIXED */
+    int32_t form;        /* IE_CONVENTIONAL or IE_CIE */
+} ie_gmres_opts;
+
+typedef struct {
+    int32_t its;          /* Arnoldi steps (the paper's "GMRES iterations") */
+    int32_t restarts;     /* restart cycles after the first */
+    int32_t refinements;  /* IE_MIXED: float64 residual corrections */
+    int32_t matvecs64;    /* float64 operator applications */
+    int32_t matvecs32;    /* complex64 operator applications */
+    double  relres;       /* final relative residual, recomputed in float64 */
+    double  seconds;      /* wall time measured on the host around the call */
+} ie_gmres_stats;
+
+#define IE_MAX_SWEEPS 128
+#define IE_MAX_BLOCKS 16
+
+typedef struct {
+    int32_t scheme;           /* IE_GS or IE_JACOBI */
+    int32_t adaptive;         /* 1: inner tol = e/10 (Alg. 1); 0: inner tol = inner_tol_fixed */
+    int32_t max_sweeps;       /* outer sweeps limit (<= IE_MAX_SWEEPS) */
+    int32_t init;             /* IE_INIT_* */
+    double  tol;              /* outer stop: full-domain relative residual (eq. 9) <= tol */
+    double  inner_tol_fixed;  /* used when adaptive == 0 (section 3.2 uses 1e-6) */
+    ie_gmres_opts inner;      /* inner block solves (tol field ignored) */
+    const void* nn;           /* ie_nn handle for IE_INIT_LEARNED, else NULL */
+} ie_dd_opts;
+
+typedef struct {
+    int32_t sweeps;
+    int32_t total_its;                               /* sum of inner Arnoldi steps */
+    int32_t nblocks;
+    int32_t block_its[IE_MAX_SWEEPS][IE_MAX_BLOCKS];
+    double  relres[IE_MAX_SWEEPS + 1];               /* full-domain e before sweep 1 and after each sweep */
+    int32_t matvecs64, matvecs32;                    /* operator applications, all grids */
+    int32_t full_matvecs;                            /* full-domain convolutions (coupling + residual) */
+    int32_t learned_used;                            /* blocks whose learned guess was accepted */
+    double  seconds;
+} ie_dd_stats;
+
+typedef struct {
+    const ie_grid*   grid;      /* must equal the context's grid */
+    const double*    sigma6;    /* DEVICE [6][nz][ny][nx] */
+    const ie_source* sources;   /* HOST array */
+    int32_t          nsources;
+    void*            E_total;   /* DEVICE complex128 [3][nz][ny][nx]: output (input for IE_INIT_USER) */
+    void*            E_anom;    /* DEVICE complex128 or NULL: output E - E0 */
+} ie_problem;
+
+typedef struct ie_ctx ie_ctx;
+
+/*
+ * ie_green_setup - precompute FFT[G] for a grid and medium (text after eq. 10: the FFT of
+ * Green's tensor is computed once before the iterative solvers run).
+ *   grid, medium  : host structs; validated (IE_EINVAL on bad sizes or non-positive values).
+ *   partition     : NULL, or the z-slab partition used by ie_dd_solve; one additional
+ *                   spectrum is built per distinct slab thickness.
+ *   precision_mask: IE_FP64 | IE_MIXED - which spectra to keep (complex128, complex64).
+ *   stream        : work is queued on it; the call synchronises before returning.
+ *   out           : receives the new context (NULL on error).
+ * Memory: about 6 (nx+1)(ny+1)(nz+1) complex values per spectrum (octant storage) plus
+ * padded work buffers of about 30 nx ny nz complex values per precision.
+ */
+int ie_green_setup(const ie_grid* grid, const ie_medium* medium, const ie_partition* partition,
+                   int32_t precision_mask, void* stream, ie_ctx** out);
+
+/* Release a context and all device memory it owns (synchronises the device first). */
+int ie_ctx_destroy(ie_ctx* ctx);
+
+/*
+ * ie_background_field - E0 on the cell centres for point dipoles in the background medium
+ * (the E^(0) of eq. 3; source term of eq. 1).
+ *   sources : HOST array of nsources >= 1 entries.
+ *   E0      : DEVICE complex128 [3][nz][ny][nx], written.
+ */
+int ie_background_field(ie_ctx* ctx, const ie_source* sources, int32_t nsources, void* E0,
+                        void* stream);
+
+/*
+ * ie_matvec - one application of the discretised operator on the full grid of the context.
+ *   sigma6    : DEVICE float64 [6][nz][ny][nx] (ignored for IE_GREEN_ONLY).
+ *   x, y      : DEVICE [3][nz][ny][nx] complex128 (precision IE_FP64) or complex64
+ *               (IE_MIXED); x and y must not overlap.
+ *   form      : IE_CONVENTIONAL  y = x - G (dsigma x)                     (eq. 8)
+ *               IE_CIE           y = (I - b) x - 2 sigma0 G (b x)
+ *               IE_GREEN_ONLY    y = G x                                  (eq. 10)
+ *               IE_SCATTER       y = G (dsigma x)                         (eq. 3)
+ * Asynchronous on `stream`.
+ */
+int ie_matvec(ie_ctx* ctx, const double* sigma6, const void* x, void* y, int32_t form,
+              int32_t precision, void* stream);
+
+/*
+ * ie_gmres - solve (I - G dsigma) x = b on the context's full grid by restarted GMRES
+ * (section 2.2; restart length from opts, section 3.1 uses 10).
+ *   b : DEVICE complex128 [3][nz][ny][nx] right-hand side.
+ *   x : DEVICE complex128, initial guess on entry, solution on exit.
+ * With opts->form == IE_CIE the contraction form is iterated internally; x is always E.
+ * With opts->precision == IE_MIXED the Krylov solve runs in complex64 on corrections of a
+ * float64 residual until the float64 relative residual reaches opts->tol.
+ * Returns IE_ENOCONV if max_its is reached first.  Synchronises with `stream`.
+ */
+int ie_gmres(ie_ctx* ctx, const double* sigma6, const void* b, void* x,
+             const ie_gmres_opts* opts, ie_gmres_stats* stats, void* stream);
+
+/*
+ * ie_dd_solve - Alg. 1 for one or more problems: E0 from the sources, then block
+ * Gauss-Seidel or Jacobi sweeps over the context's partition until the full-domain
+ * relative residual of eq. (9) is <= opts->tol.  Each block solve is restarted GMRES on
+ * (I - G(ii) dsigma(i)) warm-started from the previous sweep; the coupling terms
+ * sum_{j != i} G(ij) dsigma(j) E(j) use the latest (GS) or previous-sweep (Jacobi) fields.
+ * Sub-domains without contrast take E(i) = right-hand side with no inner iterations.
+ *   ctxs[p], problems[p], stats[p] for p < nproblems (problems may have different grids;
+ *   each context must have been set up with a partition).  Problems are advanced together.
+ * Returns IE_ENOCONV if any problem hit max_sweeps.  Synchronises with `stream`.
+ */
+int ie_dd_solve(ie_ctx* const* ctxs, int32_t nproblems, const ie_problem* problems,
+                const ie_dd_opts* opts, ie_dd_stats* stats, void* stream);
+
+/* Description of the last error on this thread (never NULL). */
+const char* ie_last_error(void);
+
+/* Library version string. */
+const char* ie_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IE_H */

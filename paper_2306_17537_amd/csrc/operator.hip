@@ -1,0 +1,482 @@
+// Operator-level launches: the five-pass FFT convolution (eq. 10), the precomputed spectrum of
+// the discretised Green's tensor (eqs. 5-7, section 2.2), the background field of point dipoles
+// and the per-cell contrast tensors (eq. 3 and the contraction form).
+#include <cmath>
+#include <complex>
+
+#include "ctx.hpp"
+
+namespace ie {
+
+int fft_len(int n) {
+  int L = 2;
+  while (L < 2 * n - 1) L *= 2;
+  return L;
+}
+
+// Calls F<T, L>::run(args...) for the power-of-two length L.
+#define IE_LEN_CASES(F, T, L, ...)                      \
+  switch (L) {                                          \
+    case 2: return F<T, 2>::run(__VA_ARGS__);           \
+    case 4: return F<T, 4>::run(__VA_ARGS__);           \
+    case 8: return F<T, 8>::run(__VA_ARGS__);           \
+    case 16: return F<T, 16>::run(__VA_ARGS__);         \
+    case 32: return F<T, 32>::run(__VA_ARGS__);         \
+    case 64: return F<T, 64>::run(__VA_ARGS__);         \
+    case 128: return F<T, 128>::run(__VA_ARGS__);       \
+    case 256: return F<T, 256>::run(__VA_ARGS__);       \
+    case 512: return F<T, 512>::run(__VA_ARGS__);       \
+    case 1024: return F<T, 1024>::run(__VA_ARGS__);     \
+    default: return fail(IE_EINVAL, "unsupported FFT length %d", L); \
+  }
+
+template <typename T, int L>
+struct XfwdL {
+  static int run(const MvArgs<T>& a, int batch, hipStream_t s) {
+    using G = Geo<T, L>;
+    const long rows = long(a.nz) * a.ny;
+    dim3 grid(ceil_div(rows, G::NL), 1, batch);
+    hipLaunchKernelGGL((k_xfwd<T, L>), grid, dim3(G::NL * G::TL), 0, s, a);
+    IE_LAUNCH_CHECK();
+    return IE_OK;
+  }
+};
+template <typename T, int L>
+struct XinvL {
+  static int run(const MvArgs<T>& a, int batch, hipStream_t s) {
+    using G = Geo<T, L>;
+    const long rows = long(a.out_z1 - a.out_z0) * a.ny;
+    dim3 grid(ceil_div(rows, G::NL), 1, batch);
+    hipLaunchKernelGGL((k_xinv<T, L>), grid, dim3(G::NL * G::TL), 0, s, a);
+    IE_LAUNCH_CHECK();
+    return IE_OK;
+  }
+};
+template <typename T, int L>
+struct ZconvL {
+  static int run(const MvArgs<T>& a, int batch, hipStream_t s) {
+    using G = Geo<T, L>;
+    dim3 grid(ceil_div(a.LX, G::W), a.LY, batch);
+    hipLaunchKernelGGL((k_zconv<T, L>), grid, dim3(G::W * G::TL), 0, s, a);
+    IE_LAUNCH_CHECK();
+    return IE_OK;
+  }
+};
+template <typename T, int L>
+struct ColL {
+  static int run(const cx<T>* in, cx<T>* out, const ColArgs& c, int nplanes, int batch, bool inv,
+                 hipStream_t s, const cx<T>* tw) {
+    using G = Geo<T, L>;
+    dim3 grid(ceil_div(c.ncols, G::W), nplanes, batch);
+    if (inv)
+      hipLaunchKernelGGL((k_colfft<T, L, true>), grid, dim3(G::W * G::TL), 0, s, in, out, c, tw);
+    else
+      hipLaunchKernelGGL((k_colfft<T, L, false>), grid, dim3(G::W * G::TL), 0, s, in, out, c, tw);
+    IE_LAUNCH_CHECK();
+    return IE_OK;
+  }
+};
+
+int Plan::work(int prec, int batch) {
+  if (prec == IE_FP64) {
+    if (batch > cap64) {
+      IE_TRY(t1_64.ensure(sizeof(c128) * t1_elems() * batch));
+      IE_TRY(t2_64.ensure(sizeof(c128) * t2_elems() * batch));
+      cap64 = batch;
+    }
+  } else {
+    if (batch > cap32) {
+      IE_TRY(t1_32.ensure(sizeof(c64) * t1_elems() * batch));
+      IE_TRY(t2_32.ensure(sizeof(c64) * t2_elems() * batch));
+      cap32 = batch;
+    }
+  }
+  return IE_OK;
+}
+
+template <typename T>
+int launch_matvec(Plan& p, MvArgs<T> a, int batch, hipStream_t s, const cx<T>* tw) {
+  constexpr bool dbl = sizeof(T) == 8;
+  IE_TRY(p.work(dbl ? IE_FP64 : IE_MIXED, batch));
+  a.nx = p.nx;
+  a.ny = p.ny;
+  a.nz = p.nz;
+  a.LX = p.LX;
+  a.LY = p.LY;
+  a.LZ = p.LZ;
+  a.T1 = dbl ? (cx<T>*)p.t1_64.p : (cx<T>*)p.t1_32.p;
+  a.T2 = dbl ? (cx<T>*)p.t2_64.p : (cx<T>*)p.t2_32.p;
+  a.T1_bs = p.t1_elems();
+  a.T2_bs = p.t2_elems();
+  a.ghat = dbl ? (const cx<T>*)p.ghat64.p : (const cx<T>*)p.ghat32.p;
+  a.ghat_bs = 0;
+  a.tw = tw;
+  if (a.ghat == nullptr) return fail(IE_ESTATE, "spectrum for this precision was not built");
+  if (a.out_z0 < 0 || a.out_z1 > p.nz || a.out_z0 >= a.out_z1)
+    return fail(IE_EINVAL, "bad output plane range [%d, %d)", a.out_z0, a.out_z1);
+  if (batch < 1 || batch > 65535) return fail(IE_EINVAL, "bad batch %d", batch);
+
+  // pass 1: contrast, pad, FFT along x
+  auto xf = [&]() -> int { IE_LEN_CASES(XfwdL, T, p.LX, a, batch, s); };
+  IE_TRY(xf());
+  // pass 2: FFT along y (ny non-zero rows -> LY)
+  ColArgs c{};
+  c.ncols = p.LX;
+  c.nzp = p.nz;
+  c.z0 = 0;
+  c.in_cs = long(p.nz) * p.ny * p.LX;
+  c.in_zs = long(p.ny) * p.LX;
+  c.in_ls = p.LX;
+  c.out_cs = long(p.nz) * p.LY * p.LX;
+  c.out_zs = long(p.LY) * p.LX;
+  c.out_ls = p.LX;
+  c.rows_in = p.ny;
+  c.rows_out = p.LY;
+  c.in_bs = a.T1_bs;
+  c.out_bs = a.T2_bs;
+  c.active = a.active;
+  c.active_bs = a.active_bs;
+  auto col = [&](const cx<T>* in, cx<T>* out, const ColArgs& cc, int np, bool inv) -> int {
+    IE_LEN_CASES(ColL, T, p.LY, in, out, cc, np, batch, inv, s, tw);
+  };
+  IE_TRY(col(a.T1, a.T2, c, 3 * p.nz, false));
+  // pass 3: FFT along z, tensor multiply with G^, inverse FFT along z
+  auto zc = [&]() -> int { IE_LEN_CASES(ZconvL, T, p.LZ, a, batch, s); };
+  IE_TRY(zc());
+  // pass 4: inverse FFT along y on the kept planes (LY -> ny rows)
+  const int nzo = a.out_z1 - a.out_z0;
+  ColArgs d = c;
+  d.nzp = nzo;
+  d.z0 = a.out_z0;
+  d.in_cs = c.out_cs;
+  d.in_zs = c.out_zs;
+  d.in_ls = c.out_ls;
+  d.out_cs = c.in_cs;
+  d.out_zs = c.in_zs;
+  d.out_ls = c.in_ls;
+  d.rows_in = p.LY;
+  d.rows_out = p.ny;
+  d.in_bs = a.T2_bs;
+  d.out_bs = a.T1_bs;
+  IE_TRY(col(a.T2, a.T1, d, 3 * nzo, true));
+  // pass 5: inverse FFT along x, crop, combine
+  auto xi = [&]() -> int { IE_LEN_CASES(XinvL, T, p.LX, a, batch, s); };
+  return xi();
+}
+
+template int launch_matvec<double>(Plan&, MvArgs<double>, int, hipStream_t, const c128*);
+template int launch_matvec<float>(Plan&, MvArgs<float>, int, hipStream_t, const c64*);
+
+// ---------------------------------------------------------------------------------------
+// Green setup
+// ---------------------------------------------------------------------------------------
+
+// Discretised G on the padded grid: offset d (per axis d in [-(n-1), n-1], stored at d mod L),
+// G^E(d h) h^3 off the self cell (eq. 5 with grad grad g expanded), the ball integral on it.
+__global__ void k_green_eval(c128* __restrict__ out, int nx, int ny, int nz, int LX, int LY, int LZ,
+                             double h, double k0re, double k0im, double sigma0, c128 gself) {
+  const long Lt = long(LX) * LY * LZ;
+  const long idx = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= Lt) return;
+  const int kx = int(idx % LX);
+  const int ky = int((idx / LX) % LY);
+  const int kz = int(idx / (long(LX) * LY));
+  auto off = [](int k, int n, int L, bool& ok) {
+    if (k <= n - 1) return k;
+    if (k >= L - n + 1) return k - L;
+    ok = false;
+    return 0;
+  };
+  bool ok = true;
+  const int dx = off(kx, nx, LX, ok), dy = off(ky, ny, LY, ok), dz = off(kz, nz, LZ, ok);
+  c128 g[6] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  if (ok) {
+    if (dx == 0 && dy == 0 && dz == 0) {
+      g[0] = g[1] = g[2] = gself;
+    } else {
+      const double rx = dx * h, ry = dy * h, rz = dz * h;
+      const double R = sqrt(rx * rx + ry * ry + rz * rz);
+      const double u[3] = {rx / R, ry / R, rz / R};
+      // exp(i k0 R) = exp(-k0im R) (cos(k0re R) + i sin(k0re R))
+      double sn, cs;
+      sincos(k0re * R, &sn, &cs);
+      const double mag = exp(-k0im * R);
+      const c128 eikr = {mag * cs, mag * sn};
+      const double inv = h * h * h / (4.0 * M_PI * sigma0 * R * R * R);
+      const c128 pref = inv * eikr;
+      const c128 kR = {k0re * R, k0im * R};
+      const c128 kR2 = kR * kR;
+      const c128 ikR = {-kR.im, kR.re};
+      const c128 A = {kR2.re + ikR.re - 1.0, kR2.im + ikR.im};
+      const c128 B = {3.0 - 3.0 * ikR.re - kR2.re, -3.0 * ikR.im - kR2.im};
+      const c128 pa = pref * A, pb = pref * B;
+      g[0] = pa + (u[0] * u[0]) * pb;
+      g[1] = pa + (u[1] * u[1]) * pb;
+      g[2] = pa + (u[2] * u[2]) * pb;
+      g[3] = (u[0] * u[1]) * pb;
+      g[4] = (u[0] * u[2]) * pb;
+      g[5] = (u[1] * u[2]) * pb;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) out[c * Lt + idx] = g[c];
+}
+
+// Row FFT (contiguous lines of length L), in place, full length.
+template <typename T, int L, bool INV>
+__global__ void __launch_bounds__((Geo<T, L>::NL * Geo<T, L>::TL))
+    k_rowfft(cx<T>* buf, long nrows, const cx<T>* __restrict__ tw) {
+  using G = Geo<T, L>;
+  constexpr int E = G::E, TL = G::TL, NL = G::NL;
+  __shared__ cx<T> lds[NL * G::LP];
+  const int t = threadIdx.x % TL;
+  const int line = threadIdx.x / TL;
+  const long row = long(blockIdx.x) * NL + line;
+  const bool live = row < nrows;
+  cx<T>* p = buf + (live ? row : 0) * L;
+  cx<T> v[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) v[m] = live ? p[t + m * TL] : cx<T>{0, 0};
+  fft_line<T, L, E, INV>(v, lds, LdsPadded{line * G::LP}, t, tw);
+  if (live) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) p[t + m * TL] = v[m];
+  }
+}
+
+template <typename T, int L>
+struct RowL {
+  static int run(cx<T>* buf, long nrows, hipStream_t s, const cx<T>* tw) {
+    using G = Geo<T, L>;
+    hipLaunchKernelGGL((k_rowfft<T, L, false>), dim3(ceil_div(nrows, G::NL)), dim3(G::NL * G::TL),
+                       0, s, buf, nrows, tw);
+    IE_LAUNCH_CHECK();
+    return IE_OK;
+  }
+};
+
+__global__ void k_octant(const c128* __restrict__ full, c128* __restrict__ o64, c64* __restrict__ o32,
+                         int LX, int LY, int LZ, double scale) {
+  const int hx = LX / 2 + 1, hy = LY / 2 + 1, hz = LZ / 2 + 1;
+  const long n = 6L * hx * hy * hz;
+  const long idx = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  const int ox = int(idx % hx);
+  const int oy = int((idx / hx) % hy);
+  const int oz = int((idx / (long(hx) * hy)) % hz);
+  const int c = int(idx / (long(hx) * hy * hz));
+  const long Lt = long(LX) * LY * LZ;
+  const c128 v = scale * full[c * Lt + (long(oz) * LY + oy) * LX + ox];
+  if (o64) o64[idx] = v;
+  if (o32) o32[idx] = c64{float(v.re), float(v.im)};
+}
+
+int build_green(Plan& p, double h, const Medium& m, int prec_mask, const c128* tw64, const c64*,
+                hipStream_t s) {
+  const long Lt = long(p.LX) * p.LY * p.LZ;
+  DevBuf full;
+  IE_TRY(full.ensure(sizeof(c128) * 6 * Lt));
+  // self-cell ball integral [2 (1 - i k0 a) e^{i k0 a} - 3] / (3 sigma0), a^3 = 3 h^3 / (4 pi)
+  const std::complex<double> k0(m.k0re, m.k0im), I(0.0, 1.0);
+  const double arad = std::cbrt(3.0 * h * h * h / (4.0 * M_PI));
+  const std::complex<double> gs =
+      (2.0 * (1.0 - I * k0 * arad) * std::exp(I * k0 * arad) - 3.0) / (3.0 * m.sigma0);
+  hipLaunchKernelGGL(k_green_eval, dim3(ceil_div(Lt, 256)), dim3(256), 0, s, full.as<c128>(), p.nx,
+                     p.ny, p.nz, p.LX, p.LY, p.LZ, h, m.k0re, m.k0im, m.sigma0,
+                     c128{gs.real(), gs.imag()});
+  IE_LAUNCH_CHECK();
+  for (int c = 0; c < 6; ++c) {
+    c128* b = full.as<c128>() + c * Lt;
+    {
+      auto f = [&]() -> int { IE_LEN_CASES(RowL, double, p.LX, b, Lt / p.LX, s, tw64); };
+      IE_TRY(f());
+    }
+    ColArgs ca{};
+    ca.ncols = p.LX;
+    ca.active = nullptr;
+    // y axis: planes = z
+    ca.nzp = p.LZ;
+    ca.z0 = 0;
+    ca.in_cs = ca.out_cs = 0;
+    ca.in_zs = ca.out_zs = long(p.LY) * p.LX;
+    ca.in_ls = ca.out_ls = p.LX;
+    ca.rows_in = ca.rows_out = p.LY;
+    {
+      auto f = [&]() -> int { IE_LEN_CASES(ColL, double, p.LY, b, b, ca, p.LZ, 1, false, s, tw64); };
+      IE_TRY(f());
+    }
+    // z axis: planes = y
+    ca.nzp = p.LY;
+    ca.in_zs = ca.out_zs = p.LX;
+    ca.in_ls = ca.out_ls = long(p.LY) * p.LX;
+    ca.rows_in = ca.rows_out = p.LZ;
+    {
+      auto f = [&]() -> int { IE_LEN_CASES(ColL, double, p.LZ, b, b, ca, p.LY, 1, false, s, tw64); };
+      IE_TRY(f());
+    }
+  }
+  const long no = p.oct_elems();
+  c128* o64 = nullptr;
+  c64* o32 = nullptr;
+  if (prec_mask & IE_FP64) {
+    IE_TRY(p.ghat64.ensure(sizeof(c128) * no));
+    o64 = p.ghat64.as<c128>();
+  }
+  if (prec_mask & IE_MIXED) {
+    IE_TRY(p.ghat32.ensure(sizeof(c64) * no));
+    o32 = p.ghat32.as<c64>();
+  }
+  hipLaunchKernelGGL(k_octant, dim3(ceil_div(no, 256)), dim3(256), 0, s, full.as<c128>(), o64, o32,
+                     p.LX, p.LY, p.LZ, 1.0 / double(Lt));
+  IE_LAUNCH_CHECK();
+  IE_HIP(hipStreamSynchronize(s));  // `full` is released on return
+  return IE_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// background field of point dipoles
+// ---------------------------------------------------------------------------------------
+constexpr int kSrcPerLaunch = 8;
+struct SrcPack {
+  int n;
+  double pos[kSrcPerLaunch][3];
+  double mom[kSrcPerLaunch][3];
+  int kind[kSrcPerLaunch];
+};
+
+__global__ void k_background(c128* __restrict__ E0, int nx, int ny, int nz, double h, double ox,
+                             double oy, double oz, double omu, double k0re, double k0im,
+                             double sigma0, SrcPack sp, int accumulate) {
+  const long N = long(nx) * ny * nz;
+  const long idx = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= N) return;
+  const int i = int(idx % nx), j = int((idx / nx) % ny), k = int(idx / (long(nx) * ny));
+  const double r[3] = {ox + (i + 0.5) * h, oy + (j + 0.5) * h, oz + (k + 0.5) * h};
+  c128 E[3] = {{0, 0}, {0, 0}, {0, 0}};
+  for (int s = 0; s < sp.n; ++s) {
+    const double Rv[3] = {r[0] - sp.pos[s][0], r[1] - sp.pos[s][1], r[2] - sp.pos[s][2]};
+    const double R = sqrt(Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2]);
+    const double u[3] = {Rv[0] / R, Rv[1] / R, Rv[2] / R};
+    double sn, cs;
+    sincos(k0re * R, &sn, &cs);
+    const double mag = exp(-k0im * R);
+    const c128 eikr = {mag * cs, mag * sn};
+    const c128 kR = {k0re * R, k0im * R};
+    const double* mm = sp.mom[s];
+    if (sp.kind[s] == IE_MAG_DIPOLE) {
+      // i omega mu0 (1 - i k0 R) e^{i k0 R} / (4 pi R^2) (m x Rhat)
+      const c128 one_m_ikR = {1.0 + kR.im, -kR.re};
+      const c128 amp = (omu / (4.0 * M_PI * R * R)) * (c128{0.0, 1.0} * (one_m_ikR * eikr));
+      const double cr[3] = {mm[1] * u[2] - mm[2] * u[1], mm[2] * u[0] - mm[0] * u[2],
+                            mm[0] * u[1] - mm[1] * u[0]};
+      for (int c = 0; c < 3; ++c) E[c] = E[c] + cr[c] * amp;
+    } else {
+      // G^E(R) p
+      const c128 pref = (1.0 / (4.0 * M_PI * sigma0 * R * R * R)) * eikr;
+      const c128 kR2 = kR * kR;
+      const c128 ikR = {-kR.im, kR.re};
+      const c128 A = {kR2.re + ikR.re - 1.0, kR2.im + ikR.im};
+      const c128 B = {3.0 - 3.0 * ikR.re - kR2.re, -3.0 * ikR.im - kR2.im};
+      const double up = u[0] * mm[0] + u[1] * mm[1] + u[2] * mm[2];
+      for (int c = 0; c < 3; ++c) E[c] = E[c] + pref * (mm[c] * A + (u[c] * up) * B);
+    }
+  }
+  for (int c = 0; c < 3; ++c) {
+    const long o = c * N + idx;
+    E0[o] = accumulate ? E0[o] + E[c] : E[c];
+  }
+}
+
+int launch_background(int nx, int ny, int nz, double h, const double origin[3], const Medium& m,
+                      const ie_source* src, int nsrc, c128* E0, hipStream_t s) {
+  const long N = long(nx) * ny * nz;
+  for (int s0 = 0; s0 < nsrc; s0 += kSrcPerLaunch) {
+    SrcPack sp{};
+    sp.n = nsrc - s0 < kSrcPerLaunch ? nsrc - s0 : kSrcPerLaunch;
+    for (int q = 0; q < sp.n; ++q) {
+      for (int c = 0; c < 3; ++c) {
+        sp.pos[q][c] = src[s0 + q].pos[c];
+        sp.mom[q][c] = src[s0 + q].moment[c];
+      }
+      sp.kind[q] = src[s0 + q].kind;
+    }
+    hipLaunchKernelGGL(k_background, dim3(ceil_div(N, 256)), dim3(256), 0, s, E0, nx, ny, nz, h,
+                       origin[0], origin[1], origin[2], m.omega * m.mu0, m.k0re, m.k0im, m.sigma0,
+                       sp, s0 > 0 ? 1 : 0);
+    IE_LAUNCH_CHECK();
+  }
+  return IE_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// contrast preparation
+// ---------------------------------------------------------------------------------------
+__global__ void k_prep(const double* __restrict__ s6, long N, double sigma0, int form,
+                       double* __restrict__ M, float* __restrict__ Mf, double* __restrict__ A,
+                       double* __restrict__ Ai, int* __restrict__ bad) {
+  const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double s[6];
+  for (int c = 0; c < 6; ++c) s[c] = s6[c * N + i];
+  bool ok = true;
+  for (int c = 0; c < 6; ++c) ok = ok && isfinite(s[c]);
+  // Sylvester's criterion on sigma (xx, yy, zz, xy, xz, yz)
+  const double m2 = s[0] * s[1] - s[3] * s[3];
+  const double det = s[0] * (s[1] * s[2] - s[5] * s[5]) - s[3] * (s[3] * s[2] - s[5] * s[4]) +
+                     s[4] * (s[3] * s[5] - s[1] * s[4]);
+  ok = ok && s[0] > 0.0 && m2 > 0.0 && det > 0.0;
+  if (!ok) atomicOr(bad, 1);
+  double out[6];
+  if (form == IE_CIE) {
+    // P = sigma + sigma0 I = 2 sigma0 I + dsigma;  b = I - 2 sigma0 P^-1;  a = P / (2 sqrt sigma0)
+    const double a = s[0] + sigma0, b = s[1] + sigma0, c = s[2] + sigma0;
+    const double d = s[3], e = s[4], f = s[5];
+    const double cxx = b * c - f * f, cyy = a * c - e * e, czz = a * b - d * d;
+    const double cxy = e * f - d * c, cxz = d * f - b * e, cyz = d * e - a * f;
+    const double dt = a * cxx + d * cxy + e * cxz;
+    const double inv[6] = {cxx / dt, cyy / dt, czz / dt, cxy / dt, cxz / dt, cyz / dt};
+    const double ts = 2.0 * sqrt(sigma0);
+    for (int q = 0; q < 6; ++q) out[q] = (q < 3 ? 1.0 : 0.0) - 2.0 * sigma0 * inv[q];
+    const double P[6] = {a, b, c, d, e, f};
+    if (A)
+      for (int q = 0; q < 6; ++q) A[q * N + i] = P[q] / ts;
+    if (Ai)
+      for (int q = 0; q < 6; ++q) Ai[q * N + i] = ts * inv[q];
+  } else {
+    for (int q = 0; q < 6; ++q) out[q] = s[q] - (q < 3 ? sigma0 : 0.0);
+  }
+  for (int q = 0; q < 6; ++q) {
+    if (M) M[q * N + i] = out[q];
+    if (Mf) Mf[q * N + i] = float(out[q]);
+  }
+}
+
+int launch_prep(const double* sigma6, long ncell, double sigma0, int form, double* M, float* Mf,
+                double* A, double* Ainv, int* bad, hipStream_t s) {
+  hipLaunchKernelGGL(k_prep, dim3(ceil_div(ncell, 256)), dim3(256), 0, s, sigma6, ncell, sigma0,
+                     form, M, Mf, A, Ainv, bad);
+  IE_LAUNCH_CHECK();
+  return IE_OK;
+}
+
+__global__ void k_tensor_apply(const double* __restrict__ T6, long t_cs, const c128* __restrict__ x,
+                               long x_cs, c128* __restrict__ y, long y_cs, long N) {
+  const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double m[6];
+  for (int c = 0; c < 6; ++c) m[c] = T6[c * t_cs + i];
+  c128 v[3], o[3];
+  for (int c = 0; c < 3; ++c) v[c] = x[c * x_cs + i];
+  tensor_apply(m, v, o);
+  for (int c = 0; c < 3; ++c) y[c * y_cs + i] = o[c];
+}
+
+int launch_tensor_apply(const double* T6, long t_cs, const c128* x, long x_cs, c128* y, long y_cs,
+                        long ncell, hipStream_t s) {
+  hipLaunchKernelGGL(k_tensor_apply, dim3(ceil_div(ncell, 256)), dim3(256), 0, s, T6, t_cs, x,
+                     x_cs, y, y_cs, ncell);
+  IE_LAUNCH_CHECK();
+  return IE_OK;
+}
+
+}  // namespace ie

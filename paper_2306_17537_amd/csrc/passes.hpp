@@ -1,0 +1,333 @@
+// Kernels of the FFT-accelerated operator (eq. 10 with 2x zero padding), five passes:
+//
+//   xfwd : per-cell 3x3 contrast J = M x (eq. 3 integrand), zero-pad to LX, FFT along x
+//          -> T1[3][nz][ny][LX]
+//   yfwd : FFT along y of the ny non-zero rows, padded to LY          -> T2[3][nz][LY][LX]
+//   zconv: per (kx, ky) column, FFT along z of the nz non-zero planes, S^_p = sum_q G^_pq J^_q
+//          with the six stored octant components of G^ (G_pq = G_qp, each even or odd per axis),
+//          inverse FFT along z, keep the output planes                  -> T2 (in place)
+//   yinv : inverse FFT along y, keep ny rows                             -> T1
+//   xinv : inverse FFT along x, keep nx cells, combine
+//          y = a_e e + a_x x - a_m (M x) + a_s S                          -> y
+//
+// 1 / (LX LY LZ) is folded into the stored G^.  Every kernel returns at once when the
+// problem's `active` flag is 0 (used to retire converged Krylov iterations without a host
+// round trip).  blockIdx.z indexes a batch of problems of the same shape; per-problem arrays
+// advance by their batch stride.
+#pragma once
+
+#include "common.hpp"
+#include "fft.hpp"
+
+namespace ie {
+
+template <typename T>
+struct MvArgs {
+  int nx, ny, nz;
+  int LX, LY, LZ;
+  // source: x view and contrast tensor M (6 comps xx,yy,zz,xy,xz,yz; nullptr = identity)
+  const cx<T>* x;
+  long x_cs, x_bs;
+  int x_zoff;
+  const T* M;
+  long M_cs, M_bs;
+  int M_zoff;
+  int src_z0, src_z1;    // source planes outside [src_z0, src_z1) are zero
+  int hole_z0, hole_z1;  // and so are planes inside [hole_z0, hole_z1)
+  // work
+  cx<T>* T1;
+  cx<T>* T2;
+  long T1_bs, T2_bs;
+  const cx<T>* ghat;  // octant [6][LZ/2+1][LY/2+1][LX/2+1], scaled by 1/(LX LY LZ)
+  long ghat_bs;
+  // output planes and combination
+  int out_z0, out_z1;
+  cx<T>* y;
+  long y_cs, y_bs;
+  int y_zoff;
+  const cx<T>* e;
+  long e_cs, e_bs;
+  int e_zoff;
+  T a_e, a_x, a_m, a_s;
+  const int* active;
+  int active_bs;
+  const cx<T>* tw;
+};
+
+template <typename T>
+__device__ __forceinline__ bool retired(const MvArgs<T>& a, int b) {
+  return a.active != nullptr && a.active[b * a.active_bs] == 0;
+}
+
+// ---------------------------------------------------------------------------------------
+// launch geometry per (precision, length)
+// ---------------------------------------------------------------------------------------
+template <typename T, int L>
+struct Geo {
+  static constexpr int Edef = sizeof(T) == 8 ? 8 : 16;
+  static constexpr int E = L < Edef ? L : Edef;  // values per thread per line
+  static constexpr int TL = L / E;               // threads per line
+  // column passes: W adjacent columns per block, LDS budget 64 KB for one component
+  static constexpr int Wt = (256 / TL) < 1 ? 1 : (256 / TL);
+  static constexpr int Wl = (65536 / int(L * sizeof(cx<T>))) < 1 ? 1 : (65536 / int(L * sizeof(cx<T>)));
+  static constexpr int W0 = Wt < Wl ? Wt : Wl;
+  static constexpr int W = W0 > 64 ? 64 : W0;
+  // row passes: NL rows per block
+  static constexpr int NL0 = 256 / TL;
+  static constexpr int NL = NL0 < 1 ? 1 : NL0;
+  static constexpr int LP = LdsPadded::padded_len(L);
+};
+
+// 3x3 symmetric tensor (6 comps) times a complex 3-vector
+template <typename T>
+__device__ __forceinline__ void tensor_apply(const T m[6], const cx<T> v[3], cx<T> out[3]) {
+  out[0] = cx<T>{m[0] * v[0].re + m[3] * v[1].re + m[4] * v[2].re,
+                 m[0] * v[0].im + m[3] * v[1].im + m[4] * v[2].im};
+  out[1] = cx<T>{m[3] * v[0].re + m[1] * v[1].re + m[5] * v[2].re,
+                 m[3] * v[0].im + m[1] * v[1].im + m[5] * v[2].im};
+  out[2] = cx<T>{m[4] * v[0].re + m[5] * v[1].re + m[2] * v[2].re,
+                 m[4] * v[0].im + m[5] * v[1].im + m[2] * v[2].im};
+}
+
+// ---------------------------------------------------------------------------------------
+// xfwd: contrast, pad, FFT along x.  Block: NL rows x TL threads; thread (row, t).
+// ---------------------------------------------------------------------------------------
+template <typename T, int LX>
+__global__ void __launch_bounds__((Geo<T, LX>::NL * Geo<T, LX>::TL))
+    k_xfwd(const MvArgs<T> a) {
+  using G = Geo<T, LX>;
+  constexpr int E = G::E, TL = G::TL, NL = G::NL;
+  __shared__ cx<T> lds[NL * G::LP];
+  const int b = blockIdx.z;
+  if (retired(a, b)) return;
+  const int t = threadIdx.x % TL;
+  const int line = threadIdx.x / TL;
+  const long row = long(blockIdx.x) * NL + line;  // (z, y) row
+  const long nrows = long(a.nz) * a.ny;
+  const bool live = row < nrows;
+  const int z = live ? int(row / a.ny) : 0;
+  const int yy = live ? int(row % a.ny) : 0;
+  const bool zero = !live || z < a.src_z0 || z >= a.src_z1 || (z >= a.hole_z0 && z < a.hole_z1);
+  const cx<T>* x = a.x + b * a.x_bs + (long(z - a.x_zoff) * a.ny + yy) * a.nx;
+  const T* M = a.M ? a.M + b * a.M_bs + (long(z - a.M_zoff) * a.ny + yy) * a.nx : nullptr;
+  cx<T> v[3][E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int i = t + m * TL;
+    cx<T> xv[3] = {{0, 0}, {0, 0}, {0, 0}};
+    if (!zero && i < a.nx) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) xv[c] = x[c * a.x_cs + i];
+    }
+    if (M != nullptr && !zero && i < a.nx) {
+      T mm[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) mm[c] = M[c * a.M_cs + i];
+      cx<T> j3[3];
+      tensor_apply(mm, xv, j3);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) v[c][m] = j3[c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) v[c][m] = xv[c];
+    }
+  }
+  const LdsPadded addr{line * G::LP};
+  cx<T>* out = a.T1 + b * a.T1_bs + (long(z) * a.ny + yy) * LX;
+  const long cs = long(a.nz) * a.ny * LX;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    fft_line<T, LX, E, false>(v[c], lds, addr, t, a.tw);
+    if (live) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) out[c * cs + t + m * TL] = v[c][m];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Column FFT along a strided axis.  Plane q of nplanes: comp c = q / nzp, index zq = z0 + q % nzp;
+// in element (row r, col x) of plane q at in[c*in_cs + zq*in_zs + r*in_ls + x]; rows >= rows_in
+// are zero on input; rows < rows_out are written.  Block: W columns x TL threads.
+// ---------------------------------------------------------------------------------------
+struct ColArgs {
+  int ncols, nzp, z0;
+  long in_cs, in_zs, in_ls, out_cs, out_zs, out_ls;
+  int rows_in, rows_out;
+  long in_bs, out_bs;
+  const int* active;
+  int active_bs;
+};
+
+template <typename T, int L, bool INV>
+__global__ void __launch_bounds__((Geo<T, L>::W * Geo<T, L>::TL))
+    k_colfft(const cx<T>* in, cx<T>* out, const ColArgs a,
+             const cx<T>* __restrict__ tw) {
+  using G = Geo<T, L>;
+  constexpr int E = G::E, TL = G::TL, W = G::W;
+  __shared__ cx<T> lds[W * L];
+  const int b = blockIdx.z;
+  if (a.active != nullptr && a.active[b * a.active_bs] == 0) return;
+  const int w = threadIdx.x % W;
+  const int t = threadIdx.x / W;
+  const int col = blockIdx.x * W + w;
+  const bool live = col < a.ncols;
+  const int q = blockIdx.y;
+  const int c = q / a.nzp;
+  const long zq = a.z0 + q % a.nzp;
+  const cx<T>* src = in + b * a.in_bs + c * a.in_cs + zq * a.in_zs + col;
+  cx<T>* dst = out + b * a.out_bs + c * a.out_cs + zq * a.out_zs + col;
+  cx<T> v[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int r = t + m * TL;
+    v[m] = (live && r < a.rows_in) ? src[r * a.in_ls] : cx<T>{0, 0};
+  }
+  fft_line<T, L, E, INV>(v, lds, LdsInterleaved{W, w}, t, tw);
+  if (live) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int r = t + m * TL;
+      if (r < a.rows_out) dst[r * a.out_ls] = v[m];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// zconv: FFT along z, tensor multiply with the octant G^, inverse FFT along z (in place in T2).
+// Block: W kx-columns x TL threads at one ky (blockIdx.y).
+// ---------------------------------------------------------------------------------------
+template <typename T, int LZ>
+__global__ void __launch_bounds__((Geo<T, LZ>::W * Geo<T, LZ>::TL))
+    k_zconv(const MvArgs<T> a) {
+  using G = Geo<T, LZ>;
+  constexpr int E = G::E, TL = G::TL, W = G::W;
+  __shared__ cx<T> lds[W * LZ];
+  const int b = blockIdx.z;
+  if (retired(a, b)) return;
+  const int w = threadIdx.x % W;
+  const int t = threadIdx.x / W;
+  const int kx = blockIdx.x * W + w;
+  const int ky = blockIdx.y;
+  const bool live = kx < a.LX;
+  const long ls = long(a.LY) * a.LX;  // z stride
+  const long cs = long(a.nz) * ls;
+  cx<T>* buf = a.T2 + b * a.T2_bs + long(ky) * a.LX + kx;
+  cx<T> v[3][E];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int z = t + m * TL;
+      v[c][m] = (live && z < a.nz) ? buf[c * cs + z * ls] : cx<T>{0, 0};
+    }
+  }
+  const LdsInterleaved addr{W, w};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) fft_line<T, LZ, E, false>(v[c], lds, addr, t, a.tw);
+  // octant coordinates and parity signs
+  const int hx = a.LX / 2, hy = a.LY / 2, hz = LZ / 2;
+  const int ox = (live && kx > hx) ? a.LX - kx : (live ? kx : 0);
+  const int oy = ky > hy ? a.LY - ky : ky;
+  const T sx = (live && kx > hx) ? T(-1) : T(1);
+  const T sy = ky > hy ? T(-1) : T(1);
+  const long gps = long(hy + 1) * (hx + 1);
+  const long gcs = long(hz + 1) * gps;
+  const cx<T>* gh = a.ghat + b * a.ghat_bs + long(oy) * (hx + 1) + ox;
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int kz = t + m * TL;
+    const int oz = kz > hz ? LZ - kz : kz;
+    const T sz = kz > hz ? T(-1) : T(1);
+    const cx<T>* g = gh + oz * gps;
+    cx<T> gxx = g[0], gyy = g[gcs], gzz = g[2 * gcs];
+    cx<T> gxy = (sx * sy) * g[3 * gcs];
+    cx<T> gxz = (sx * sz) * g[4 * gcs];
+    cx<T> gyz = (sy * sz) * g[5 * gcs];
+    const cx<T> j0 = v[0][m], j1 = v[1][m], j2 = v[2][m];
+    v[0][m] = gxx * j0 + gxy * j1 + gxz * j2;
+    v[1][m] = gxy * j0 + gyy * j1 + gyz * j2;
+    v[2][m] = gxz * j0 + gyz * j1 + gzz * j2;
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) fft_line<T, LZ, E, true>(v[c], lds, addr, t, a.tw);
+  if (live) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int z = t + m * TL;
+        if (z >= a.out_z0 && z < a.out_z1) buf[c * cs + z * ls] = v[c][m];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// xinv: inverse FFT along x, crop, combine.  Rows (z, y) for z in [out_z0, out_z1).
+// ---------------------------------------------------------------------------------------
+template <typename T, int LX>
+__global__ void __launch_bounds__((Geo<T, LX>::NL * Geo<T, LX>::TL))
+    k_xinv(const MvArgs<T> a) {
+  using G = Geo<T, LX>;
+  constexpr int E = G::E, TL = G::TL, NL = G::NL;
+  __shared__ cx<T> lds[NL * G::LP];
+  const int b = blockIdx.z;
+  if (retired(a, b)) return;
+  const int t = threadIdx.x % TL;
+  const int line = threadIdx.x / TL;
+  const long row = long(blockIdx.x) * NL + line;
+  const long nrows = long(a.out_z1 - a.out_z0) * a.ny;
+  const bool live = row < nrows;
+  const int z = live ? a.out_z0 + int(row / a.ny) : a.out_z0;
+  const int yy = live ? int(row % a.ny) : 0;
+  const cx<T>* in = a.T1 + b * a.T1_bs + (long(z) * a.ny + yy) * LX;
+  const long cs = long(a.nz) * a.ny * LX;
+  cx<T> v[3][E];
+  const LdsPadded addr{line * G::LP};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[c][m] = live ? in[c * cs + t + m * TL] : cx<T>{0, 0};
+    fft_line<T, LX, E, true>(v[c], lds, addr, t, a.tw);
+  }
+  if (!live) return;
+  const long cell = long(yy) * a.nx;
+  cx<T>* y = a.y + b * a.y_bs + long(z - a.y_zoff) * a.ny * a.nx + cell;
+  const cx<T>* x = a.x ? a.x + b * a.x_bs + long(z - a.x_zoff) * a.ny * a.nx + cell : nullptr;
+  const cx<T>* e = a.e ? a.e + b * a.e_bs + long(z - a.e_zoff) * a.ny * a.nx + cell : nullptr;
+  const T* M = (a.M && a.a_m != T(0)) ? a.M + b * a.M_bs + long(z - a.M_zoff) * a.ny * a.nx + cell
+                                       : nullptr;
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int i = t + m * TL;
+    if (i >= a.nx) continue;
+    cx<T> r[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) r[c] = a.a_s * v[c][m];
+    if (x != nullptr && (a.a_x != T(0) || M != nullptr)) {
+      cx<T> xv[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) xv[c] = x[c * a.x_cs + i];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) r[c] = r[c] + a.a_x * xv[c];
+      if (M != nullptr) {
+        T mm[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) mm[c] = M[c * a.M_cs + i];
+        cx<T> mx[3];
+        tensor_apply(mm, xv, mx);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) r[c] = r[c] - a.a_m * mx[c];
+      }
+    }
+    if (e != nullptr) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) r[c] = r[c] + a.a_e * e[c * a.e_cs + i];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) y[c * a.y_cs + i] = r[c];
+  }
+}
+
+}  // namespace ie

@@ -1,0 +1,213 @@
+"""Thin ctypes binding of the gfx950 library ``libie_gfx950.so`` (C ABI in ``include/ie.h``).
+
+Functions carry the C names and only marshal arguments: device arrays are passed as raw
+pointers (``tensor.data_ptr()``), the stream as ``torch.cuda.current_stream().cuda_stream``.
+Every step of the computation runs in the HIP library; there is no host fallback.  A missing
+or unloadable library raises ``ImportError`` on first use.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libie_gfx950.so")
+
+IE_OK, IE_ENOCONV, IE_EINVAL, IE_ENOMEM, IE_EDEVICE, IE_ESTATE = 0, 1, -1, -2, -3, -4
+IE_FP64, IE_MIXED = 1, 2
+IE_CONVENTIONAL, IE_CIE, IE_GREEN_ONLY, IE_SCATTER = 0, 1, 2, 3
+IE_GS, IE_JACOBI = 0, 1
+IE_INIT_BACKGROUND, IE_INIT_USER, IE_INIT_LEARNED = 0, 1, 2
+IE_MAG_DIPOLE, IE_ELEC_DIPOLE = 0, 1
+IE_MAX_SWEEPS, IE_MAX_BLOCKS = 128, 16
+
+
+class ie_grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("h", C.c_double), ("origin", C.c_double * 3)]
+
+
+class ie_medium(C.Structure):
+    _fields_ = [("sigma0", C.c_double), ("freq_hz", C.c_double), ("mu0", C.c_double)]
+
+
+class ie_source(C.Structure):
+    _fields_ = [("pos", C.c_double * 3), ("moment", C.c_double * 3), ("kind", C.c_int32)]
+
+
+class ie_partition(C.Structure):
+    _fields_ = [("nblocks", C.c_int32), ("z_bounds", C.POINTER(C.c_int32))]
+
+
+class ie_gmres_opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("restart", C.c_int32), ("max_its", C.c_int32),
+                ("precision", C.c_int32), ("form", C.c_int32)]
+
+
+class ie_gmres_stats(C.Structure):
+    _fields_ = [("its", C.c_int32), ("restarts", C.c_int32), ("refinements", C.c_int32),
+                ("matvecs64", C.c_int32), ("matvecs32", C.c_int32),
+                ("relres", C.c_double), ("seconds", C.c_double)]
+
+
+class ie_dd_opts(C.Structure):
+    _fields_ = [("scheme", C.c_int32), ("adaptive", C.c_int32), ("max_sweeps", C.c_int32),
+                ("init", C.c_int32), ("tol", C.c_double), ("inner_tol_fixed", C.c_double),
+                ("inner", ie_gmres_opts), ("nn", C.c_void_p)]
+
+
+class ie_dd_stats(C.Structure):
+    _fields_ = [("sweeps", C.c_int32), ("total_its", C.c_int32), ("nblocks", C.c_int32),
+                ("block_its", (C.c_int32 * IE_MAX_BLOCKS) * IE_MAX_SWEEPS),
+                ("relres", C.c_double * (IE_MAX_SWEEPS + 1)),
+                ("matvecs64", C.c_int32), ("matvecs32", C.c_int32),
+                ("full_matvecs", C.c_int32), ("learned_used", C.c_int32),
+                ("seconds", C.c_double)]
+
+
+class ie_problem(C.Structure):
+    _fields_ = [("grid", C.POINTER(ie_grid)), ("sigma6", C.c_void_p),
+                ("sources", C.POINTER(ie_source)), ("nsources", C.c_int32),
+                ("E_total", C.c_void_p), ("E_anom", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the library once; raise ImportError if it is missing (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2306_17537_amd.build_lib")
+        L = C.CDLL(LIB_PATH)
+        vp, i32 = C.c_void_p, C.c_int32
+        L.ie_green_setup.argtypes = [C.POINTER(ie_grid), C.POINTER(ie_medium),
+                                     C.POINTER(ie_partition), i32, vp, C.POINTER(vp)]
+        L.ie_ctx_destroy.argtypes = [vp]
+        L.ie_background_field.argtypes = [vp, C.POINTER(ie_source), i32, vp, vp]
+        L.ie_matvec.argtypes = [vp, vp, vp, vp, i32, i32, vp]
+        L.ie_gmres.argtypes = [vp, vp, vp, vp, C.POINTER(ie_gmres_opts),
+                               C.POINTER(ie_gmres_stats), vp]
+        L.ie_dd_solve.argtypes = [C.POINTER(vp), i32, C.POINTER(ie_problem),
+                                  C.POINTER(ie_dd_opts), C.POINTER(ie_dd_stats), vp]
+        for f in ("ie_green_setup", "ie_ctx_destroy", "ie_background_field", "ie_matvec",
+                  "ie_gmres", "ie_dd_solve"):
+            getattr(L, f).restype = C.c_int
+        L.ie_last_error.restype = C.c_char_p
+        L.ie_version.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+class IEError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where} returned {code}: {ie_last_error()}")
+
+
+def _check(code, where, allow_noconv=False):
+    if code < 0 or (code == IE_ENOCONV and not allow_noconv):
+        raise IEError(code, where)
+    return code
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(stream)
+
+
+def ie_last_error() -> str:
+    return lib().ie_last_error().decode()
+
+
+def ie_version() -> str:
+    return lib().ie_version().decode()
+
+
+def make_grid(n, h, origin) -> ie_grid:
+    return ie_grid(int(n[0]), int(n[1]), int(n[2]), float(h), (C.c_double * 3)(*origin))
+
+
+def make_sources(sources):
+    """[(pos, moment, kind)] with kind 'magnetic' / 'electric' (or the IE_ constant)."""
+    arr = (ie_source * len(sources))()
+    for i, (pos, mom, kind) in enumerate(sources):
+        k = kind if isinstance(kind, int) else (IE_MAG_DIPOLE if kind == "magnetic" else IE_ELEC_DIPOLE)
+        arr[i] = ie_source((C.c_double * 3)(*pos), (C.c_double * 3)(*mom), k)
+    return arr
+
+
+def ie_green_setup(grid: ie_grid, medium: ie_medium, z_bounds=None, precision_mask=IE_FP64 | IE_MIXED,
+                   stream=None):
+    """Returns an opaque context handle (int)."""
+    part = None
+    keep = None
+    if z_bounds is not None:
+        keep = (C.c_int32 * len(z_bounds))(*z_bounds)
+        part = ie_partition(len(z_bounds) - 1, keep)
+    out = C.c_void_p()
+    rc = lib().ie_green_setup(C.byref(grid), C.byref(medium),
+                              C.byref(part) if part is not None else None,
+                              precision_mask, _stream(stream), C.byref(out))
+    _check(rc, "ie_green_setup")
+    return out.value
+
+
+def ie_ctx_destroy(ctx):
+    return _check(lib().ie_ctx_destroy(C.c_void_p(ctx)), "ie_ctx_destroy")
+
+
+def ie_background_field(ctx, sources, E0, stream=None):
+    src = make_sources(sources) if not isinstance(sources, C.Array) else sources
+    return _check(lib().ie_background_field(C.c_void_p(ctx), src, len(src), _ptr(E0),
+                                            _stream(stream)), "ie_background_field")
+
+
+def ie_matvec(ctx, sigma6, x, y, form=IE_CONVENTIONAL, precision=IE_FP64, stream=None):
+    return _check(lib().ie_matvec(C.c_void_p(ctx), _ptr(sigma6), _ptr(x), _ptr(y), form,
+                                  precision, _stream(stream)), "ie_matvec")
+
+
+def ie_gmres(ctx, sigma6, b, x, tol=1e-6, restart=10, max_its=2000, precision=IE_FP64,
+             form=IE_CIE, stream=None, allow_noconv=False):
+    """Solve in place (x holds the initial guess).  Returns (status, ie_gmres_stats)."""
+    opts = ie_gmres_opts(tol, restart, max_its, precision, form)
+    st = ie_gmres_stats()
+    rc = lib().ie_gmres(C.c_void_p(ctx), _ptr(sigma6), _ptr(b), _ptr(x), C.byref(opts),
+                        C.byref(st), _stream(stream))
+    _check(rc, "ie_gmres", allow_noconv)
+    return rc, st
+
+
+def dd_opts(scheme=IE_GS, adaptive=True, tol=1e-6, inner_tol_fixed=1e-6, max_sweeps=50,
+            init=IE_INIT_BACKGROUND, restart=10, max_its=5000, precision=IE_FP64, form=IE_CIE,
+            nn=None) -> ie_dd_opts:
+    return ie_dd_opts(scheme, 1 if adaptive else 0, max_sweeps, init, tol, inner_tol_fixed,
+                      ie_gmres_opts(0.0, restart, max_its, precision, form),
+                      C.c_void_p(nn) if nn else None)
+
+
+def ie_dd_solve(ctxs, problems, opts: ie_dd_opts, stream=None, allow_noconv=False):
+    """problems: list of dicts with keys grid (ie_grid), sigma6, sources, E_total, E_anom.
+    Returns (status, [ie_dd_stats])."""
+    n = len(problems)
+    carr = (C.c_void_p * n)(*ctxs)
+    parr = (ie_problem * n)()
+    keep = []
+    for i, p in enumerate(problems):
+        src = make_sources(p["sources"])
+        g = p["grid"]
+        keep += [src, g]
+        parr[i] = ie_problem(C.pointer(g), _ptr(p["sigma6"]), src, len(src),
+                             _ptr(p["E_total"]), _ptr(p.get("E_anom")))
+    stats = (ie_dd_stats * n)()
+    rc = lib().ie_dd_solve(carr, n, parr, C.byref(opts), stats, _stream(stream))
+    _check(rc, "ie_dd_solve", allow_noconv)
+    return rc, list(stats)

@@ -1,0 +1,168 @@
+"""GPU parity of the solvers through the C ABI: restarted GMRES on the full domain (section 2.2)
+and Alg. 1 (block Gauss-Seidel / Jacobi, section 2.3), in float64 and mixed precision, against
+the CPU oracle (dense LU on small grids, the oracle's own converged solve otherwise).
+Gate (the benchmark spec): relative L2 error of the anomalous field <= 1e-4 at relative residual 1e-6."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dense, operator, solve
+from tests.gpu_common import banner, context, dev, field_shape, host, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _gpu_e0(ctx, p, torch):
+    from paper_2306_17537_amd import ie
+    E0 = torch.zeros(field_shape(p), dtype=torch.complex128, device="cuda:0")
+    ie.ie_background_field(ctx, p.sources, E0)
+    return E0
+
+
+@pytest.mark.parametrize("form", ["cie", "conventional"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_gmres_small_matches_dense_lu(torch, form, prec):
+    from paper_2306_17537_amd import ie
+    banner(f"gmres 8^3 {form} {prec}")
+    p = synth.random_problem((8, 8, 8), seed=31, contrast=4.0, freq=4e5)
+    st = solve.setup(p)
+    Ed = dense.dense_solve(p.n, p.h, p.origin, st.k0, p.sigma0, st.dsig, st.E0)
+    ctx, _ = context(p)
+    try:
+        E0 = _gpu_e0(ctx, p, torch)
+        x = E0.clone()
+        tol = 1e-10 if prec == "fp64" else 1e-6
+        rc, stats = ie.ie_gmres(ctx, dev(p.sigma6), E0, x, tol=tol,
+                                precision=ie.IE_FP64 if prec == "fp64" else ie.IE_MIXED,
+                                form=ie.IE_CIE if form == "cie" else ie.IE_CONVENTIONAL)
+        E = host(x)
+        assert stats.relres <= tol
+        err = rel(E - st.E0, Ed - st.E0)
+        assert err < (1e-7 if prec == "fp64" else 1e-4), err
+        assert operator.relres(st.Ghat, st.dsig, E, st.E0, p.n) <= 1.01 * tol
+        if prec == "mixed":
+            assert stats.matvecs32 > 0 and stats.refinements >= 1
+    finally:
+        ie.ie_ctx_destroy(ctx)
+
+
+@pytest.fixture(scope="module")
+def config0_ref():
+    p = synth.config0()
+    st = solve.setup(p)
+    E, info = solve.solve_full(st, form="cie", tol=1e-11)
+    assert info["converged"]
+    return p, st, E
+
+
+@pytest.mark.parametrize("form", ["cie", "conventional"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_gmres_config0_matches_oracle(torch, config0_ref, form, prec):
+    """16^3 two-layer VTI, 100 kHz, complex128 full-domain GMRES(10) (and the mixed form)."""
+    from paper_2306_17537_amd import ie
+    banner(f"gmres config0 {form} {prec}")
+    p, st, Eref = config0_ref
+    ctx, _ = context(p)
+    try:
+        E0 = _gpu_e0(ctx, p, torch)
+        assert rel(host(E0), st.E0) < 1e-13
+        x = E0.clone()
+        rc, stats = ie.ie_gmres(ctx, dev(p.sigma6), E0, x, tol=1e-6, restart=10,
+                                precision=ie.IE_FP64 if prec == "fp64" else ie.IE_MIXED,
+                                form=ie.IE_CIE if form == "cie" else ie.IE_CONVENTIONAL)
+        E = host(x)
+        err = rel(E - st.E0, Eref - st.E0)
+        e_or = operator.relres(st.Ghat, st.dsig, E, st.E0, p.n)
+        banner(f"  its={stats.its} relres={stats.relres:.3e} oracle relres={e_or:.3e} err={err:.2e}")
+        assert stats.relres <= 1e-6 and e_or <= 1.01e-6
+        assert err <= 1e-4
+    finally:
+        ie.ie_ctx_destroy(ctx)
+
+
+def test_gmres_reports_nonconvergence_with_best_iterate(torch):
+    from paper_2306_17537_amd import ie
+    p = synth.config0()
+    ctx, _ = context(p)
+    try:
+        E0 = _gpu_e0(ctx, p, torch)
+        x = E0.clone()
+        rc, stats = ie.ie_gmres(ctx, dev(p.sigma6), E0, x, tol=1e-12, max_its=3,
+                                allow_noconv=True)
+        assert rc == ie.IE_ENOCONV
+        assert stats.its == 3
+        assert 0 < stats.relres < 1.0
+        assert "GMRES stopped" in ie.ie_last_error()
+    finally:
+        ie.ie_ctx_destroy(ctx)
+
+
+def test_zero_contrast_returns_background(torch):
+    from paper_2306_17537_amd import ie
+    p = synth.random_problem((8, 6, 5), seed=2)
+    p.sigma6[:] = 0.0
+    p.sigma6[:3] = p.sigma0
+    ctx, _ = context(p)
+    try:
+        E0 = _gpu_e0(ctx, p, torch)
+        x = E0.clone()
+        rc, stats = ie.ie_gmres(ctx, dev(p.sigma6), E0, x, tol=1e-10, form=ie.IE_CONVENTIONAL)
+        assert stats.its == 0
+        assert torch.equal(x, E0)
+    finally:
+        ie.ie_ctx_destroy(ctx)
+
+
+@pytest.mark.parametrize("scheme", ["gs", "jacobi"])
+@pytest.mark.parametrize("adaptive", [True, False])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_dd_small_matches_dense_lu(torch, scheme, adaptive, prec):
+    from paper_2306_17537_amd import ie
+    banner(f"dd 8^3 {scheme} adaptive={adaptive} {prec}")
+    p = synth.random_problem((8, 8, 8), seed=24, contrast=1.0, freq=1e5)
+    st = solve.setup(p)
+    Ed = dense.dense_solve(p.n, p.h, p.origin, st.k0, p.sigma0, st.dsig, st.E0)
+    zb = (0, 4, 8)
+    ctx, g = context(p, z_bounds=zb)
+    try:
+        E = torch.zeros(field_shape(p), dtype=torch.complex128, device="cuda:0")
+        Ea = torch.zeros_like(E)
+        opts = ie.dd_opts(scheme=ie.IE_GS if scheme == "gs" else ie.IE_JACOBI, adaptive=adaptive,
+                          tol=1e-6, inner_tol_fixed=1e-7,
+                          precision=ie.IE_FP64 if prec == "fp64" else ie.IE_MIXED)
+        rc, stats = ie.ie_dd_solve([ctx], [dict(grid=g, sigma6=dev(p.sigma6), sources=p.sources,
+                                                E_total=E, E_anom=Ea)], opts)
+        s = stats[0]
+        assert s.sweeps >= 1 and s.relres[s.sweeps] <= 1e-6
+        Eh = host(E)
+        assert rel(host(Ea), Ed - st.E0) <= 1e-4
+        assert np.allclose(host(Ea), Eh - st.E0, atol=1e-12 * np.abs(Eh).max())
+        assert operator.relres(st.Ghat, st.dsig, Eh, st.E0, p.n) <= 1.01e-6
+    finally:
+        ie.ie_ctx_destroy(ctx)
+
+
+def test_dd_single_block_equals_full_gmres(torch):
+    from paper_2306_17537_amd import ie
+    p = synth.random_problem((8, 8, 6), seed=8, contrast=2.0, freq=4e5)
+    ctx, g = context(p, z_bounds=(0, 6))
+    try:
+        E0 = _gpu_e0(ctx, p, torch)
+        x = E0.clone()
+        _, gst = ie.ie_gmres(ctx, dev(p.sigma6), E0, x, tol=1e-9, form=ie.IE_CIE)
+        E = torch.zeros_like(E0)
+        opts = ie.dd_opts(scheme=ie.IE_GS, adaptive=False, tol=1e-9, inner_tol_fixed=1e-9)
+        _, stats = ie.ie_dd_solve([ctx], [dict(grid=g, sigma6=dev(p.sigma6), sources=p.sources,
+                                               E_total=E)], opts)
+        assert stats[0].sweeps == 1
+        assert stats[0].total_its == gst.its
+        assert rel(host(E), host(x)) < 1e-12
+    finally:
+        ie.ie_ctx_destroy(ctx)
