@@ -1,0 +1,287 @@
+#!/usr/bin/env python3
+"""Benchmark of the integral-equation solver on one MI355X.
+
+Workload (one "step"): one complete solve of the 64^3 three-layer dipping TI model (cell
+0.25 m, 2 MHz, z dipole at the centre) to full-domain relative residual 1e-6 (eq. 9) by the
+chosen form: background field, contrast preparation and restarted GMRES(10) on the contraction
+form in mixed precision (complex64 Krylov vectors and convolutions; float64 residual at every
+restart, Arnoldi scalars, Givens rotations and solution accumulation).  The Green's spectrum is
+built once before the timed region (it depends on grid and medium only) and timed separately.
+The same solve by Alg. 1 (block Gauss-Seidel and Jacobi over two z slabs, float64 and mixed)
+and by plain float64 GMRES is timed in the same run and reported beside it.
+
+Printed: one JSON line with the contract fields plus
+  roofline     - dominant kernel of the timed region: algorithmic bytes / duration, HIP events
+                 on the launch stream (library launch profiler), against 8 TB/s;
+  cpu_baseline - the CPU oracle on this host, sampled and scaled to one solve;
+  plain_fp64   - the same solve in plain float64 (better of full-domain GMRES and DD-GS-A);
+  accuracy     - relative L2 error of the anomalous field against the stored oracle reference.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-to-solve @ rel.resid 1e-6 + matvec HBM GB/s; plain FP64 vs mixed+NN"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--profile-json", default=None, help="write the kernel profile here")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the solver has no "
+                                   "multi-GPU path (see DESIGN.md: how the path would shard)",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    import synth
+    from paper_2306_17537_amd import ie
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    ie.lib()
+    p = synth.config1()
+    nx, ny, nz = p.n
+    zb = (0, nz // 2, nz)
+    g = ie.make_grid(p.n, p.h, p.origin)
+    med = ie.ie_medium(p.sigma0, p.freq, 0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx = ie.ie_green_setup(g, med, zb, ie.IE_FP64 | ie.IE_MIXED)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    log(f"green setup {setup_s * 1e3:.1f} ms")
+    s6 = torch.from_numpy(p.sigma6).cuda()
+    shape = (3, nz, ny, nx)
+    E = torch.zeros(shape, dtype=torch.complex128, device="cuda:0")
+    Ea = torch.zeros_like(E)
+    prob = dict(grid=g, sigma6=s6, sources=p.sources, E_total=E, E_anom=Ea)
+
+    chosen = ie.dd_opts(scheme=ie.IE_GS, adaptive=True, tol=1e-6, precision=ie.IE_MIXED,
+                        form=ie.IE_CIE, restart=10)
+
+    def solve_dd(opts):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, st = ie.ie_dd_solve([ctx], [prob], opts)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, st[0]
+
+    E0 = torch.zeros_like(E)
+    ie.ie_background_field(ctx, p.sources, E0)
+
+    def solve_full(precision):
+        x = E0.clone()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, gst = ie.ie_gmres(ctx, s6, E0, x, tol=1e-6, precision=precision, form=ie.IE_CIE)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, gst, (x - E0).cpu().numpy()
+
+    def solve_chosen():
+        # background field + contrast + mixed-precision GMRES, all inside the timed step
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ie.ie_background_field(ctx, p.sources, E0)
+        x = E0.clone()
+        _, gst = ie.ie_gmres(ctx, s6, E0, x, tol=1e-6, precision=ie.IE_MIXED, form=ie.IE_CIE)
+        torch.sub(x, E0, out=Ea)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, gst
+
+    for _ in range(args.warmup):
+        solve_chosen()
+    log("timed region")
+    times = []
+    for _ in range(args.steps):
+        dt, st = solve_chosen()
+        times.append(dt)
+    total = sum(times)
+    ms_per_step = 1e3 * total / args.steps
+    chosen_stats = st
+    Ea_chosen = Ea.cpu().numpy()
+    log(f"chosen form: {ms_per_step:.2f} ms/solve, its={st.its} refinements={st.refinements} "
+        f"mv32={st.matvecs32} mv64={st.matvecs64} graph_cycles={st.graph_cycles}")
+
+    # the same steps with direct kernel launches (no graph replay), then profiled
+    ie.ie_set_option(ie.IE_OPT_GRAPHS, 0)
+    t_eager = [solve_chosen()[0] for _ in range(args.steps)]
+    ie.ie_set_option(ie.IE_OPT_GRAPHS, 1)
+    ie.ie_profile_begin()
+    t_prof = [solve_chosen()[0] for _ in range(args.steps)]
+    prof = ie.ie_profile_end()
+    log(f"direct launches: {1e3 * sum(t_eager) / args.steps:.2f} ms/solve; profiled "
+        f"{1e3 * sum(t_prof) / args.steps:.2f} ms/solve")
+
+    # dominant kernel (largest share of the profiled replay of the timed steps)
+    kern = [k for k in prof if not k["name"].startswith("finalise")]
+    dom = kern[0]
+    avg_ms = dom["total_ms"] / dom["launches"]
+    achieved = dom["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
+    prof_total = sum(k["total_ms"] for k in prof)
+    if args.profile_json:
+        with open(args.profile_json, "w") as f:
+            json.dump(dict(kernels=prof, steps=args.steps), f, indent=1)
+
+    # matvec throughput on the full grid (standalone, float64 and complex64)
+    mv = {}
+    for prec, dt_, nm in ((ie.IE_FP64, torch.complex128, "fp64"), (ie.IE_MIXED, torch.complex64, "c64")):
+        x = torch.randn(shape, dtype=dt_, device="cuda:0")
+        y = torch.empty_like(x)
+        ie.ie_matvec(ctx, s6, x, y, ie.IE_CIE, prec)
+        torch.cuda.synchronize()
+        ie.ie_profile_begin()
+        reps = 20
+        for _ in range(reps):
+            ie.ie_matvec(ctx, s6, x, y, ie.IE_CIE, prec)
+        pr = ie.ie_profile_end()
+        passes = [k for k in pr if k["name"].split()[0] in ("xfwd", "yfwd", "zconv", "yinv", "xinv")]
+        t_ms = sum(k["total_ms"] for k in passes) / reps
+        byts = sum(k["bytes_per_launch"] * k["launches"] for k in passes) / reps
+        mv[nm] = dict(ms=round(t_ms, 4), algorithmic_bytes=int(byts),
+                      gbs=round(byts / (t_ms * 1e-3) / 1e9, 1),
+                      matvecs_per_s=round(1e3 / t_ms, 1))
+    log(f"matvec: {mv}")
+
+    # other forms on the same GPU: plain float64 (the better of full-domain GMRES and DD-GS-A),
+    # full-domain mixed GMRES and mixed DD-Jacobi
+    plain = None
+    variants = {}
+    acc = {}
+    ref = None
+    refp = os.path.join(ROOT, "tests", "golden", "config1_Ea.npz")
+    if os.path.exists(refp):
+        ref = np.load(refp)["Ea"].astype(np.complex128)
+        rn = np.linalg.norm(ref)
+        acc["chosen_Ea_rel_err"] = float(np.linalg.norm(Ea_chosen - ref) / rn)
+    st_dd = None
+    if not args.no_plain:
+        fp64_dd = ie.dd_opts(scheme=ie.IE_GS, adaptive=True, tol=1e-6, precision=ie.IE_FP64,
+                             form=ie.IE_CIE, restart=10)
+        solve_dd(fp64_dd)
+        t_dd, st_dd = solve_dd(fp64_dd)
+        Ea_dd = Ea.cpu().numpy()
+        solve_full(ie.IE_FP64)
+        t_full, gst, Ea_full = solve_full(ie.IE_FP64)
+        solve_dd(chosen)
+        t_gm, st_gm = solve_dd(chosen)
+        Ea_gm = Ea.cpu().numpy()
+        jac = ie.dd_opts(scheme=ie.IE_JACOBI, adaptive=True, tol=1e-6, precision=ie.IE_MIXED,
+                         form=ie.IE_CIE, restart=10)
+        solve_dd(jac)
+        t_j, st_j = solve_dd(jac)
+        Ea_j = Ea.cpu().numpy()
+        plain = dict(dd_gs_a_fp64_s=round(t_dd, 5), dd_sweeps=st_dd.sweeps, dd_its=st_dd.total_its,
+                     full_gmres_fp64_s=round(t_full, 5), full_its=gst.its,
+                     best_s=round(min(t_dd, t_full), 5),
+                     speedup_chosen_vs_plain=round(min(t_dd, t_full) / (total / args.steps), 3))
+        variants = dict(dd_gs_a_mixed_s=round(t_gm, 5), gs_mixed_sweeps=st_gm.sweeps,
+                        gs_mixed_its=st_gm.total_its,
+                        dd_jacobi_a_mixed_s=round(t_j, 5), jacobi_sweeps=st_j.sweeps,
+                        jacobi_its=st_j.total_its, jacobi_blocks_batched=2,
+                        chosen_direct_launch_s=round(sum(t_eager) / args.steps, 5))
+        if ref is not None:
+            acc["plain_dd_Ea_rel_err"] = float(np.linalg.norm(Ea_dd - ref) / rn)
+            acc["plain_full_Ea_rel_err"] = float(np.linalg.norm(Ea_full - ref) / rn)
+            acc["dd_gs_mixed_Ea_rel_err"] = float(np.linalg.norm(Ea_gm - ref) / rn)
+            acc["jacobi_mixed_Ea_rel_err"] = float(np.linalg.norm(Ea_j - ref) / rn)
+        log(f"plain fp64: {plain}")
+        log(f"variants: {variants}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(p, chosen_stats)
+        log(f"cpu baseline: {cpu}")
+
+    out = {
+        "metric": METRIC,
+        "value": round(total / args.steps, 6),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64+f64",
+        "data": "synthetic",
+        "config": {"workload": "config1: 64^3 cells of 0.25 m, 3-layer TI dipping 30 deg "
+                               "(seed 101), 2 MHz, z dipole; full-domain contraction-form "
+                               "GMRES(10), complex64 Krylov/convolutions + float64 restarts, "
+                               "tol 1e-6",
+                   "grid": list(p.n), "its": chosen_stats.its,
+                   "refinements": chosen_stats.refinements, "matvecs32": chosen_stats.matvecs32,
+                   "matvecs64": chosen_stats.matvecs64, "graph_cycles": chosen_stats.graph_cycles,
+                   "green_setup_s": round(setup_s, 5), "solves_per_s": round(args.steps / total, 3)},
+        "roofline": {"bound": "hbm", "kernel": dom["name"], "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "avg_launch_ms": round(avg_ms, 5),
+                     "launches": dom["launches"], "bytes_per_launch": int(dom["bytes_per_launch"]),
+                     "share_of_profiled_time": round(dom["total_ms"] / prof_total, 3),
+                     "measured": "HIP events on the launch stream around every launch, in a "
+                                 "profiled replay of the timed steps (direct launches)"},
+        "cpu_baseline": cpu,
+        "plain_fp64": plain,
+        "variants": variants,
+        "matvec": mv,
+        "accuracy": acc,
+    }
+    print(json.dumps(out))
+    ie.ie_ctx_destroy(ctx)
+
+
+def cpu_baseline(p, gst):
+    """The oracle on this host: time restarted GMRES(10) iterations of its full-domain
+    contraction-form solve on a bounded sample, then scale to one solve with the iteration and
+    restart counts of the GPU run."""
+    import scipy.fft
+    from oracle import operator, solve as osolve
+    from oracle.gmres import gmres
+    cores = os.cpu_count() or 1
+    with scipy.fft.set_workers(cores):
+        t0 = time.perf_counter()
+        st = osolve.setup(p)
+        t_setup = time.perf_counter() - t0
+        b, a, _ = operator.cie_tensors(st.dsig, p.sigma0)
+        rhs = np.sqrt(p.sigma0) * st.E0
+        x0 = operator.tensor_apply(a, st.E0)
+        its = 40
+        t0 = time.perf_counter()
+        _, info = gmres(lambda v: operator.apply_C(st.Ghat, b, v, p.sigma0, st.n), rhs, x0, 1e-14,
+                        10, its)
+        t_sample = time.perf_counter() - t0
+        # one iteration = one operator application; each restart adds one more (true residual)
+        napp = info["its"] + info["restarts"] + 2
+        t_app = t_sample / napp
+    est = (gst.its + gst.restarts + 2) * t_app
+    return {"value": round(est, 3), "unit": "s", "cores": cores, "kind": "oracle",
+            "sample": f"oracle FP64 full-domain contraction-form GMRES(10) on this host: "
+                      f"{info['its']} iterations ({napp} operator applications, "
+                      f"{t_sample:.2f} s, {t_app:.3f} s each), scaled to the GPU solve's "
+                      f"{gst.its} iterations and {gst.restarts + 1} restarts; oracle setup "
+                      f"{t_setup:.2f} s excluded like the GPU setup"}
+
+
+if __name__ == "__main__":
+    main()

@@ -100,6 +100,7 @@ typedef struct {
     int32_t max_its;     /* limit on Arnoldi steps (operator applications); > 0 */
     int32_t precision;   /* IE_FP64 or IE_MIXED */
     int32_t form;        /* IE_CONVENTIONAL or IE_CIE */
+    int32_t reorth;      /* Gram-Schmidt passes: 1 (classical), 2 (repeated once), 0 = default (1) */
 } ie_gmres_opts;
 
 typedef struct {
@@ -108,6 +109,7 @@ typedef struct {
     int32_t refinements;  /* IE_MIXED: float64 residual corrections */
     int32_t matvecs64;    /* float64 operator applications */
     int32_t matvecs32;    /* complex64 operator applications */
+    int32_t graph_cycles; /* restart cycles replayed from a captured hipGraph */
     double  relres;       /* final relative residual, recomputed in float64 */
     double  seconds;      /* wall time measured on the host around the call */
 } ie_gmres_stats;
@@ -135,6 +137,7 @@ typedef struct {
     int32_t matvecs64, matvecs32;                    /* operator applications, all grids */
     int32_t full_matvecs;                            /* full-domain convolutions (coupling + residual) */
     int32_t learned_used;                            /* blocks whose learned guess was accepted */
+    int32_t graph_cycles;                            /* inner restart cycles replayed from graphs */
     double  seconds;
 } ie_dd_stats;
 
@@ -216,6 +219,33 @@ int ie_gmres(ie_ctx* ctx, const double* sigma6, const void* b, void* x,
  */
 int ie_dd_solve(ie_ctx* const* ctxs, int32_t nproblems, const ie_problem* problems,
                 const ie_dd_opts* opts, ie_dd_stats* stats, void* stream);
+
+/*
+ * Launch profiler for measurement harnesses.  Between ie_profile_begin() and ie_profile_end()
+ * every kernel launch of the operator and Krylov passes is bracketed by HIP events recorded on
+ * the launch stream.  ie_profile_end() synchronises the device and returns one record per
+ * (kernel, shape, precision), sorted by total time, with the algorithmic bytes each launch must
+ * move (compulsory reads and writes, each counted once).  `out` is a HOST array of `cap`
+ * records; `count` receives the number of distinct records (may exceed cap).
+ */
+typedef struct {
+    char    name[96];
+    int32_t launches;
+    double  total_ms, min_ms, max_ms;
+    double  bytes_per_launch;
+} ie_kernel_stat;
+
+int ie_profile_begin(void);
+int ie_profile_end(ie_kernel_stat* out, int32_t cap, int32_t* count);
+
+/*
+ * Library options (process-wide).
+ *   IE_OPT_GRAPHS: 1 (default) replays each Krylov restart cycle as a captured hipGraph; 0 issues
+ *                  every kernel launch directly (the launch profiler always uses direct launches).
+ * Returns IE_EINVAL for an unknown option or value.
+ */
+#define IE_OPT_GRAPHS 1
+int ie_set_option(int32_t option, int32_t value);
 
 /* Description of the last error on this thread (never NULL). */
 const char* ie_last_error(void);

@@ -131,6 +131,15 @@ const char* ie_last_error(void) { return g_err.c_str(); }
 
 const char* ie_version(void) { return "ie-gfx950 0.1"; }
 
+int ie_set_option(int32_t option, int32_t value) {
+  if (option == IE_OPT_GRAPHS) {
+    if (value != 0 && value != 1) return fail(IE_EINVAL, "IE_OPT_GRAPHS takes 0 or 1");
+    g_use_graphs = value != 0;
+    return IE_OK;
+  }
+  return fail(IE_EINVAL, "unknown option %d", option);
+}
+
 int ie_green_setup(const ie_grid* grid, const ie_medium* medium, const ie_partition* partition,
                    int32_t precision_mask, void* stream, ie_ctx** out) {
   if (out == nullptr) return fail(IE_EINVAL, "out is NULL");
@@ -302,6 +311,8 @@ int ie_gmres(ie_ctx* ctx, const double* sigma6, const void* b, void* x, const ie
   o.restart = opts->restart;
   o.max_its = opts->max_its;
   o.precision = opts->precision;
+  if (opts->reorth < 0 || opts->reorth > 2) return fail(IE_EINVAL, "reorth must be 0, 1 or 2");
+  o.reorth = opts->reorth == 2 ? 1 : 0;
   GmResult r;
   c128* xs = (c128*)x;
   const c128* rhs = (const c128*)b;
@@ -324,6 +335,7 @@ int ie_gmres(ie_ctx* ctx, const double* sigma6, const void* b, void* x, const ie
     stats->refinements = opts->precision == IE_MIXED ? r.cycles : 0;
     stats->matvecs64 = r.mv64;
     stats->matvecs32 = r.mv32;
+    stats->graph_cycles = r.graph_cycles;
     stats->relres = r.relres;
     stats->seconds =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

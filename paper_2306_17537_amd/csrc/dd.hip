@@ -111,6 +111,7 @@ int block_solve(DdRun& r, Plan& B, int z0, int batch, c128* rhs, c128* x, double
   o.restart = inner.restart;
   o.max_its = inner.max_its;
   o.precision = inner.precision;
+  o.reorth = inner.reorth == 2 ? 1 : 0;
   if (r.form == IE_CIE) {
     // C e = sqrt(sigma0) b_i, e = a x;  x = a^-1 e, per block
     IE_TRY(r.c->blk_rhs2.ensure(sizeof(c128) * 3 * nb * batch));
@@ -255,6 +256,7 @@ int dd_one(ie_ctx* c, const ie_problem& pr, const ie_dd_opts& o, ie_dd_stats& st
           st.block_its[k][i] = gr.its;
           st.matvecs64 += gr.mv64;
           st.matvecs32 += gr.mv32;
+          st.graph_cycles += gr.graph_cycles;
         }
       }
       if (equal) {
@@ -275,6 +277,7 @@ int dd_one(ie_ctx* c, const ie_problem& pr, const ie_dd_opts& o, ie_dd_stats& st
           st.block_its[k][i] = has[i] ? gr[i].its : 0;
           st.matvecs64 += gr[i].mv64;
           st.matvecs32 += gr[i].mv32;
+          if (i == 0) st.graph_cycles += gr[i].graph_cycles;
         }
       }
     } else {
@@ -298,6 +301,7 @@ int dd_one(ie_ctx* c, const ie_problem& pr, const ie_dd_opts& o, ie_dd_stats& st
         st.block_its[k][i] = gr.its;
         st.matvecs64 += gr.mv64;
         st.matvecs32 += gr.mv32;
+        st.graph_cycles += gr.graph_cycles;
       }
     }
     for (int i = 0; i < M; ++i) st.total_its += st.block_its[k][i];

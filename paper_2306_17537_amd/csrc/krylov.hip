@@ -1,17 +1,23 @@
 // Device-side restarted GMRES: fused Gram-Schmidt passes, float64 reductions, Givens
 // rotations and back substitution in single-block kernels (see krylov.hpp).
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "krylov.hpp"
+#include "prof.hpp"
 
 namespace ie {
 
+bool g_use_graphs = true;
+
 namespace {
 
-constexpr int RB = 256;                 // threads per reduction block
-constexpr int PW = MAXM + 2;            // partial slots per block: dots [0, MAXM], norm at MAXM+1
-constexpr int NORM = MAXM + 1;
+constexpr int RB = 256;             // threads per reduction block
+constexpr int NWV = RB / 64;        // wavefronts per block
+constexpr int PWD = 2 * MAXM + 1;  // doubles per block partial (at most 2 MAXM dots + norm)
+
+enum Fin { FIN_NONE = 0, FIN_H = 1, FIN_GIVENS = 2, FIN_CYCLE = 3, FIN_BNORM = 4 };
 
 int red_grid(long n) {
   long g = (n + RB * 8 - 1) / (RB * 8);
@@ -26,115 +32,58 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Deterministic block-wide sum of one double (all threads receive the result).
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  v = wave_sum(v);
-  __syncthreads();
-  if (lane == 0) sh[wv] = v;
-  __syncthreads();
-  double r = 0;
-#pragma unroll
-  for (int q = 0; q < RB / 64; ++q) r += sh[q];
-  return r;
-}
-
 template <typename T>
 __device__ __forceinline__ c128 up(cx<T> v) { return c128{double(v.re), double(v.im)}; }
 
-// Fused Gram-Schmidt pass on w (stride wbs per problem):
-//   UPD : w <- w - sum_{i<count} hc[i] V_i   (hc from the problem state)
-//   DOTS: partial <V_i, w> for i < count;    NRM: partial ||w||^2
-template <typename TA, bool UPD, bool DOTS, bool NRM>
-__global__ void __launch_bounds__(RB)
-    k_orth(const cx<TA>* __restrict__ V, long vstride, long vbs, cx<TA>* w, long wbs, long n,
-           int count, const GmState* __restrict__ st, c128* __restrict__ part) {
-  const int b = blockIdx.z;
-  if (st != nullptr && st[b].active == 0) return;
-  __shared__ double sh[RB / 64];
-  const cx<TA>* Vb = V + b * vbs;
-  cx<TA>* wb = w + b * wbs;
-  c128 h[MAXM + 1];
-  c128 acc[MAXM + 1];
+// Slots of a partial: dots (re, im) in [0, 2 CM), the squared norm in slot NS = 2 CM.
+template <int CM>
+struct Slots {
+  static constexpr int NV = 2 * CM + 1;
+  static constexpr int NS = 2 * CM;
+};
+
+// Block-wide sums of the needed slots (k < nd, and NS if nrm); thread k writes out[k].
+template <int NV>
+__device__ __forceinline__ void block_sums(double (&v)[NV], int nd, bool nrm, double* sh,
+                                           double* out) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int i = 0; i <= MAXM; ++i) {
-    h[i] = (UPD && i < count) ? st[b].hc[i] : c128{0, 0};
-    acc[i] = c128{0, 0};
-  }
-  double nrm = 0;
-  const long stride = long(gridDim.x) * RB;
-  for (long e = long(blockIdx.x) * RB + threadIdx.x; e < n; e += stride) {
-    cx<TA> vv[MAXM + 1];
-#pragma unroll
-    for (int i = 0; i <= MAXM; ++i)
-      if ((UPD || DOTS) && i < count) vv[i] = Vb[i * vstride + e];
-    cx<TA> wv = wb[e];
-    if (UPD) {
-      c128 wd = up(wv);
-#pragma unroll
-      for (int i = 0; i <= MAXM; ++i)
-        if (i < count) wd = wd - h[i] * up(vv[i]);
-      wv = cx<TA>{TA(wd.re), TA(wd.im)};
-      wb[e] = wv;
+  for (int k = 0; k < NV; ++k)
+    if (k < nd || (nrm && k == NV - 1)) {
+      const double r = wave_sum(v[k]);
+      if (lane == 0) sh[wv * NV + k] = r;
     }
-    const c128 wd = up(wv);
-    if (DOTS) {
+  __syncthreads();
+  for (int k = threadIdx.x; k < NV; k += RB) {
+    if (k < nd || (nrm && k == NV - 1)) {
+      double r = 0;
 #pragma unroll
-      for (int i = 0; i <= MAXM; ++i)
-        if (i < count) acc[i] = acc[i] + cjmul(up(vv[i]), wd);
+      for (int q = 0; q < NWV; ++q) r += sh[q * NV + k];
+      out[k] = r;
     }
-    if (NRM) nrm += wd.re * wd.re + wd.im * wd.im;
-  }
-  c128* pb = part + (long(b) * gridDim.x + blockIdx.x) * PW;
-  if (DOTS) {
-    for (int i = 0; i < count; ++i) {
-      const double re = block_sum(acc[i].re, sh);
-      const double im = block_sum(acc[i].im, sh);
-      if (threadIdx.x == 0) pb[i] = c128{re, im};
-    }
-  }
-  if (NRM) {
-    const double r = block_sum(nrm, sh);
-    if (threadIdx.x == 0) pb[NORM] = c128{r, 0};
   }
 }
 
-// Sum slot `slot` of the G block partials of problem b (deterministic order).
-__device__ c128 reduce_slot(const c128* part, int b, int G, int slot, double* sh) {
-  double re = 0, im = 0;
+// Sum the G block partials of problem b (every thread a fixed subset of rows, then one block
+// reduction; deterministic) into fin[].  Called by a one-block kernel.
+template <int NV>
+__device__ void reduce_partials(const double* part, int b, int G, int nd, bool nrm, double* sh,
+                                double* fin) {
+  double a[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) a[k] = 0;
   for (int q = threadIdx.x; q < G; q += RB) {
-    const c128 v = part[(long(b) * G + q) * PW + slot];
-    re += v.re;
-    im += v.im;
+    const double* row = part + (long(b) * G + q) * PWD;
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+      if (k < nd || (nrm && k == NV - 1)) a[k] += row[k];
   }
-  re = block_sum(re, sh);
-  im = block_sum(im, sh);
-  return c128{re, im};
+  block_sums<NV>(a, nd, nrm, sh, fin);
+  __syncthreads();
 }
 
-// Coefficients of a Gram-Schmidt pass: hc[i] = <V_i, w>, accumulated into column j of H.
-__global__ void __launch_bounds__(RB)
-    k_hsum(GmState* st, const c128* part, int G, int j, int count, int first) {
-  const int b = blockIdx.x;
-  if (st[b].active == 0) return;
-  __shared__ double sh[RB / 64];
-  for (int i = 0; i < count; ++i) {
-    const c128 h = reduce_slot(part, b, G, i, sh);
-    if (threadIdx.x == 0) {
-      st[b].hc[i] = h;
-      st[b].H[j][i] = first ? h : st[b].H[j][i] + h;
-    }
-  }
-}
-
-// h_{j+1,j} = ||w||, previous rotations applied to column j, new rotation, residual estimate.
-__global__ void __launch_bounds__(RB) k_givens(GmState* st, const c128* part, int G, int j) {
-  const int b = blockIdx.x;
-  if (st[b].active == 0) return;
-  __shared__ double sh[RB / 64];
-  const double hn2 = reduce_slot(part, b, G, NORM, sh).re;
-  if (threadIdx.x != 0) return;
-  GmState& s = st[b];
+// Givens step for Hessenberg column j once h_{j+1,j}^2 = hn2 is known (thread 0).
+__device__ void givens_update(GmState& s, int j, double hn2, int* flags, int batch, int b) {
   const double hn = sqrt(hn2);
   c128* H = s.H[j];
   for (int i = 0; i < j; ++i) {
@@ -162,58 +111,167 @@ __global__ void __launch_bounds__(RB) k_givens(GmState* st, const c128* part, in
   s.est = sqrt(s.g[j + 1].re * s.g[j + 1].re + s.g[j + 1].im * s.g[j + 1].im);
   s.k = j + 1;
   s.its += 1;
-  s.hn2 = hn2;
   const bool brk = (hn == 0.0) || (den == 0.0);
   s.breakdown = brk ? 1 : 0;
-  s.inv_h = brk ? 0.0 : 1.0 / hn;
+  s.nv[j + 1] = brk ? 0.0 : 1.0 / hn;
   if (s.est <= s.target || s.its >= s.max_its || brk) s.active = 0;
+  flags[j * batch + b] = s.active;
 }
 
-template <typename TA>
-__global__ void __launch_bounds__(RB) k_scale(cx<TA>* w, long wbs, long n, const GmState* st) {
+// Fused Gram-Schmidt pass over w (per problem b = blockIdx.z), with v_i = nv[i] V_i:
+//   UPD : w <- w - sum_{i<count} hc[i] v_i
+//   DOTS: <v_i, w> for i < count;  NRM: ||w||^2
+// and a last-block finalisation FIN:
+//   FIN_H      : hc[i] = <v_i, w>, H[j][i] = (first ? 0 : H[j][i]) + hc[i]
+//   FIN_GIVENS : h_{j+1,j} = ||w||, rotations, residual estimate, active flag, nv[j+1]
+//   FIN_CYCLE  : beta = ||w||, g = beta e1, active unless converged (start of a restart cycle)
+//   FIN_BNORM  : ||b||, target = tol ||b||, counters reset (start of a solve)
+template <typename TA, typename TW, bool UPD, bool DOTS, bool NRM, int FIN, int CM>
+__global__ void __launch_bounds__(RB)
+    k_orth(const cx<TA>* __restrict__ V, long vstride, long vbs, cx<TW>* w, long wbs, long n,
+           int count, int j, int first, GmState* __restrict__ st, double* __restrict__ part,
+           int* __restrict__ flags, int batch, double tol, int max_its) {
   const int b = blockIdx.z;
-  if (st[b].active == 0) return;
-  const double s = st[b].inv_h;
-  cx<TA>* wb = w + b * wbs;
+  GmState& S = st[b];
+  if (FIN != FIN_CYCLE && FIN != FIN_BNORM && S.active == 0) {
+    if (FIN == FIN_GIVENS && blockIdx.x == 0 && threadIdx.x == 0) flags[j * batch + b] = 0;
+    return;
+  }
+  using SL = Slots<CM>;
+  constexpr int NV = SL::NV;
+  __shared__ double sh[NWV * NV];
+  __shared__ double fin[NV];
+  const cx<TA>* Vb = V + b * vbs;
+  cx<TW>* wb = w + b * wbs;
+  c128 h[CM];
+  double nvi[CM];
+#pragma unroll
+  for (int i = 0; i < CM; ++i) {
+    nvi[i] = ((UPD || DOTS) && i < count) ? S.nv[i] : 0.0;
+    h[i] = (UPD && i < count) ? nvi[i] * S.hc[i] : c128{0, 0};
+  }
+  double acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0;
   const long stride = long(gridDim.x) * RB;
   for (long e = long(blockIdx.x) * RB + threadIdx.x; e < n; e += stride) {
-    const cx<TA> v = wb[e];
-    wb[e] = cx<TA>{TA(double(v.re) * s), TA(double(v.im) * s)};
+    cx<TA> vv[CM];
+#pragma unroll
+    for (int i = 0; i < CM; ++i)
+      if ((UPD || DOTS) && i < count) vv[i] = Vb[i * vstride + e];
+    cx<TW> wv = wb[e];
+    if (UPD) {
+      c128 wd = up(wv);
+#pragma unroll
+      for (int i = 0; i < CM; ++i)
+        if (i < count) wd = wd - h[i] * up(vv[i]);
+      wv = cx<TW>{TW(wd.re), TW(wd.im)};
+      wb[e] = wv;
+    }
+    const c128 wd = up(wv);
+    if (DOTS) {
+#pragma unroll
+      for (int i = 0; i < CM; ++i)
+        if (i < count) {
+          const c128 d = cjmul(up(vv[i]), wd);
+          acc[2 * i] += d.re;
+          acc[2 * i + 1] += d.im;
+        }
+    }
+    if (NRM) acc[SL::NS] += wd.re * wd.re + wd.im * wd.im;
   }
+  const int nd = DOTS ? 2 * count : 0;
+  double* pb = part + (long(b) * gridDim.x + blockIdx.x) * PWD;
+  block_sums<NV>(acc, nd, NRM, sh, pb);
 }
 
-// Start-of-solve: ||b||, target, counters.
+// Finalisation of a reduction (one block per problem):
+//   FIN_H      : hc[i] = <v_i, w>, H[j][i] = (first ? 0 : H[j][i]) + hc[i]
+//   FIN_GIVENS : h_{j+1,j} = ||w||, rotations, residual estimate, active flag, nv[j+1]
+//   FIN_CYCLE  : beta = ||r||, g = beta e1, active unless converged (start of a restart cycle)
+//   FIN_BNORM  : ||b||, target = tol ||b||, counters reset (start of a solve)
+template <int FIN, int CM>
 __global__ void __launch_bounds__(RB)
-    k_set_bnorm(GmState* st, const c128* part, int G, double tol, int max_its) {
+    k_fin(GmState* __restrict__ st, const double* __restrict__ part, int G, int count, int j,
+          int first, int* __restrict__ flags, int batch, double tol, int max_its) {
   const int b = blockIdx.x;
-  __shared__ double sh[RB / 64];
-  const double n2 = reduce_slot(part, b, G, NORM, sh).re;
-  if (threadIdx.x == 0) {
-    st[b].bnorm = sqrt(n2);
-    st[b].target = tol * sqrt(n2);
-    st[b].its = 0;
-    st[b].max_its = max_its;
-    st[b].active = 0;
-    st[b].k = 0;
+  GmState& S = st[b];
+  if (FIN == FIN_H || FIN == FIN_GIVENS) {
+    if (S.active == 0) {
+      if (FIN == FIN_GIVENS && threadIdx.x == 0) flags[j * batch + b] = 0;
+      return;
+    }
+  }
+  using SL = Slots<CM>;
+  constexpr int NV = SL::NV;
+  __shared__ double sh[NWV * NV];
+  __shared__ double fin[NV];
+  const int nd = FIN == FIN_H ? 2 * count : 0;
+  reduce_partials<NV>(part, b, G, nd, FIN != FIN_H, sh, fin);
+  if (threadIdx.x != 0) return;
+  if (FIN == FIN_H) {
+    for (int i = 0; i < count; ++i) {
+      const double nvi = S.nv[i];
+      const c128 hv = c128{nvi * fin[2 * i], nvi * fin[2 * i + 1]};
+      S.hc[i] = hv;
+      S.H[j][i] = first ? hv : S.H[j][i] + hv;
+    }
+  } else if (FIN == FIN_GIVENS) {
+    givens_update(S, j, fin[SL::NS], flags, batch, b);
+  } else if (FIN == FIN_CYCLE) {
+    const double beta = sqrt(fin[SL::NS]);
+    S.beta = beta;
+    S.est = beta;
+    S.k = 0;
+    for (int i = 0; i <= MAXM; ++i) S.g[i] = c128{0, 0};
+    S.g[0] = c128{beta, 0};
+    S.nv[0] = 1.0;
+    S.inv_h = beta > 0 ? 1.0 / beta : 0.0;
+    S.active = (beta > S.target && S.its < S.max_its) ? 1 : 0;
+  } else if (FIN == FIN_BNORM) {
+    S.bnorm = sqrt(fin[SL::NS]);
+    S.target = tol * S.bnorm;
+    S.its = 0;
+    S.max_its = max_its;
+    S.active = 0;
+    S.k = 0;
   }
 }
 
-// Start-of-cycle: beta = ||r||, g = beta e1, active unless converged or out of iterations.
-__global__ void __launch_bounds__(RB) k_cycle_begin(GmState* st, const c128* part, int G) {
-  const int b = blockIdx.x;
-  __shared__ double sh[RB / 64];
-  const double n2 = reduce_slot(part, b, G, NORM, sh).re;
-  if (threadIdx.x == 0) {
-    GmState& s = st[b];
-    const double beta = sqrt(n2);
-    s.beta = beta;
-    s.est = beta;
-    s.k = 0;
-    for (int i = 0; i <= MAXM; ++i) s.g[i] = c128{0, 0};
-    s.g[0] = c128{beta, 0};
-    s.inv_h = beta > 0 ? 1.0 / beta : 0.0;
-    s.active = (beta > s.target && s.its < s.max_its) ? 1 : 0;
-  }
+// Launch a Gram-Schmidt pass with the smallest register bucket that holds `count` vectors.
+template <typename TA, typename TW, bool UPD, bool DOTS, bool NRM, int FIN>
+int launch_orth(const char* pname, const char* ptag, double pbytes, dim3 grid, hipStream_t s,
+                const cx<TA>* V, long vstride, long vbs, cx<TW>* w, long wbs, long n, int count,
+                int j, int first, GmState* st, double* part, int* flags, int batch, double tol,
+                int max_its) {
+#define IE_ORTH(CMV)                                                                             \
+  do {                                                                                           \
+    {                                                                                            \
+      ProfScope ps(s, pname, ptag, pbytes);                                                      \
+      hipLaunchKernelGGL((k_orth<TA, TW, UPD, DOTS, NRM, FIN, CMV>), grid, dim3(RB), 0, s, V,     \
+                         vstride, vbs, w, wbs, n, count, j, first, st, part, flags, batch, tol,  \
+                         max_its);                                                               \
+    }                                                                                            \
+    IE_LAUNCH_CHECK();                                                                           \
+    if (FIN != FIN_NONE) {                                                                       \
+      ProfScope ps(s, "finalise", ptag, 0);                                                      \
+      hipLaunchKernelGGL((k_fin<FIN, CMV>), dim3(grid.z), dim3(RB), 0, s, st, part, int(grid.x),   \
+                         count, j, first, flags, batch, tol, max_its);                           \
+    }                                                                                            \
+  } while (0)
+  if (count <= 1)
+    IE_ORTH(1);
+  else if (count <= 4)
+    IE_ORTH(4);
+  else if (count <= 8)
+    IE_ORTH(8);
+  else if (count <= 12)
+    IE_ORTH(12);
+  else
+    IE_ORTH(MAXM);
+#undef IE_ORTH
+  IE_LAUNCH_CHECK();
+  return IE_OK;
 }
 
 __global__ void k_summary(const GmState* st, GmSummary* out, int batch) {
@@ -225,6 +283,7 @@ __global__ void k_summary(const GmState* st, GmSummary* out, int batch) {
   out[b].its = st[b].its;
 }
 
+// V0 = r / beta (cast to the Krylov precision)
 template <typename TA>
 __global__ void __launch_bounds__(RB)
     k_scale_cast(const c128* __restrict__ r, long rbs, cx<TA>* __restrict__ v, long vbs, long n,
@@ -241,33 +300,32 @@ __global__ void __launch_bounds__(RB)
   }
 }
 
-// y = R^-1 g on the k x k rotated Hessenberg (upper triangular).
-__global__ void k_backsolve(GmState* st, int batch) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= batch) return;
-  GmState& s = st[b];
-  const int k = s.k;
-  for (int i = k - 1; i >= 0; --i) {
-    c128 acc = s.g[i];
-    for (int l = i + 1; l < k; ++l) acc = acc - s.H[l][i] * s.y[l];
-    const c128 d = s.H[i][i];
-    const double dd = d.re * d.re + d.im * d.im;
-    s.y[i] = dd > 0 ? c128{(acc.re * d.re + acc.im * d.im) / dd, (acc.im * d.re - acc.re * d.im) / dd}
-                    : c128{0, 0};
-  }
-}
-
-// x += sum_{i<k} y_i V_i (float64 accumulation).
+// x += sum_{i<k} y_i v_i with y = R^-1 g from the rotated Hessenberg (float64); every block
+// solves the k x k triangular system itself (k <= 16), so no separate launch is needed.
 template <typename TA>
 __global__ void __launch_bounds__(RB)
     k_xupdate(c128* x, long xbs, const cx<TA>* __restrict__ V, long vstride, long vbs, long n,
               const GmState* st) {
   const int b = blockIdx.z;
-  const int k = st[b].k;
+  const GmState& S = st[b];
+  const int k = S.k;
   if (k == 0) return;
+  __shared__ c128 ys[MAXM];
+  if (threadIdx.x == 0) {
+    for (int i = k - 1; i >= 0; --i) {
+      c128 acc = S.g[i];
+      for (int l = i + 1; l < k; ++l) acc = acc - S.H[l][i] * ys[l];
+      const c128 d = S.H[i][i];
+      const double dd = d.re * d.re + d.im * d.im;
+      ys[i] = dd > 0 ? c128{(acc.re * d.re + acc.im * d.im) / dd, (acc.im * d.re - acc.re * d.im) / dd}
+                     : c128{0, 0};
+    }
+    for (int i = 0; i < k; ++i) ys[i] = S.nv[i] * ys[i];
+  }
+  __syncthreads();
   c128 y[MAXM];
 #pragma unroll
-  for (int i = 0; i < MAXM; ++i) y[i] = i < k ? st[b].y[i] : c128{0, 0};
+  for (int i = 0; i < MAXM; ++i) y[i] = i < k ? ys[i] : c128{0, 0};
   c128* xb = x + b * xbs;
   const cx<TA>* Vb = V + b * vbs;
   const long stride = long(gridDim.x) * RB;
@@ -355,17 +413,23 @@ static int fetch_summary(KrylovWork& w, const GmState* st, int batch, hipStream_
   return IE_OK;
 }
 
+static int ensure_state(KrylovWork& w, int batch, int G, hipStream_t s) {
+  IE_TRY(w.part.ensure(sizeof(double) * PWD * G * batch));
+  const bool grow = w.st.bytes < sizeof(GmState) * batch;
+  IE_TRY(w.st.ensure(sizeof(GmState) * batch));
+  if (grow) IE_HIP(hipMemsetAsync(w.st.p, 0, sizeof(GmState) * batch, s));  // reduction counters
+  IE_TRY(ensure_host(w, batch));
+  IE_TRY(w.flags.ensure(sizeof(int) * MAXM * batch));
+  return IE_OK;
+}
+
 int norms_host(const c128* v, long n, int batch, double* out, KrylovWork& w, hipStream_t s) {
   const int G = red_grid(n);
-  IE_TRY(w.part.ensure(sizeof(c128) * PW * G * batch));
-  IE_TRY(w.st.ensure(sizeof(GmState) * batch));
-  IE_TRY(ensure_host(w, batch));
+  IE_TRY(ensure_state(w, batch, G, s));
   GmState* st = w.st.as<GmState>();
-  hipLaunchKernelGGL((k_orth<double, false, false, true>), dim3(G, 1, batch), dim3(RB), 0, s, v, 0L,
-                     0L, const_cast<c128*>(v), n, n, 0, nullptr, w.part.as<c128>());
-  IE_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_set_bnorm, dim3(batch), dim3(RB), 0, s, st, w.part.as<c128>(), G, 0.0, 0);
-  IE_LAUNCH_CHECK();
+  IE_TRY((launch_orth<double, double, false, false, true, FIN_BNORM>("norm", "", 16.0 * n * batch,
+                                                                     dim3(G, 1, batch), s, nullptr, 0L, 0L, const_cast<c128*>(v), n, n,
+                     0, 0, 0, st, w.part.as<double>(), w.flags.as<int>(), batch, 0.0, 0)));
   IE_TRY(fetch_summary(w, st, batch, s));
   for (int b = 0; b < batch; ++b) out[b] = w.host[b].bnorm;
   return IE_OK;
@@ -374,7 +438,7 @@ int norms_host(const c128* v, long n, int batch, double* out, KrylovWork& w, hip
 template <typename TA>
 static int gmres_impl(Plan& p, const OpDesc& op, const c128* rhs, c128* x, int batch,
                       const GmOpts& o, GmResult* res, KrylovWork& w, const c128* tw64,
-                      const cx<TA>* twa, hipStream_t s) {
+                      const cx<TA>* twa, hipStream_t us) {
   const long N = p.ncell();
   const long n = 3 * N;
   const int m = o.restart;
@@ -382,38 +446,187 @@ static int gmres_impl(Plan& p, const OpDesc& op, const c128* rhs, c128* x, int b
   const bool reorth = o.reorth < 0 ? (sizeof(TA) == 4) : (o.reorth != 0);
   const int G = red_grid(n);
   const long vbs = long(m + 1) * n;
+  // all work runs on the private stream, ordered after and before the caller's stream
+  if (!w.ps) IE_HIP(hipStreamCreateWithFlags(&w.ps, hipStreamNonBlocking));
+  for (auto& e : w.join)
+    if (!e) IE_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  for (auto& e : w.ev)
+    if (!e) IE_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  const hipStream_t s = w.ps;
+  IE_HIP(hipEventRecord(w.join[0], us));
+  IE_HIP(hipStreamWaitEvent(s, w.join[0], 0));
   IE_TRY(w.V.ensure(sizeof(cx<TA>) * vbs * batch));
   IE_TRY(w.r.ensure(sizeof(c128) * n * batch));
-  IE_TRY(w.part.ensure(sizeof(c128) * PW * G * batch));
-  IE_TRY(w.st.ensure(sizeof(GmState) * batch));
-  IE_TRY(ensure_host(w, batch));
+  IE_TRY(ensure_state(w, batch, G, s));
+  IE_TRY(p.work(IE_FP64, batch));
+  IE_TRY(p.work(sizeof(TA) == 8 ? IE_FP64 : IE_MIXED, batch));
+  if (w.hflags_cap < batch) {
+    if (w.hflags) (void)hipHostFree(w.hflags);
+    w.hflags = nullptr;
+    IE_HIP(hipHostMalloc((void**)&w.hflags, sizeof(int) * MAXM * batch, hipHostMallocDefault));
+    w.hflags_cap = batch;
+  }
   GmState* st = w.st.as<GmState>();
   cx<TA>* V = w.V.as<cx<TA>>();
   c128* r = w.r.as<c128>();
-  c128* part = w.part.as<c128>();
+  double* part = w.part.as<double>();
+  int* flags = w.flags.as<int>();
   const int* act = &st[0].active;
   const int act_bs = int(sizeof(GmState) / sizeof(int));
+  const long nv_bs = long(sizeof(GmState) / sizeof(double));
   const dim3 vgrid(G, 1, batch);
   for (int b = 0; b < batch; ++b) res[b] = GmResult{};
+  char tgb[96];
+  snprintf(tgb, sizeof(tgb), "%s n%ld b%d", sizeof(TA) == 4 ? "c64" : "c128", n, batch);
+  const char* tg = tgb;
+  const double sa = sizeof(cx<TA>), nb = double(n) * batch;
+  std::vector<std::pair<int, long>> pending;  // (step, profiler group) awaiting byte scaling
+  int prev_start_active = 0;
 
-  // ||b||
-  hipLaunchKernelGGL((k_orth<double, false, false, true>), vgrid, dim3(RB), 0, s, rhs, 0L, 0L,
-                     const_cast<c128*>(rhs), n, n, 0, nullptr, part);
-  IE_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_set_bnorm, dim3(batch), dim3(RB), 0, s, st, part, G, o.tol, o.max_its);
-  IE_LAUNCH_CHECK();
-
-  for (int cycle = 0;; ++cycle) {
-    // r = b - A x in float64, beta = ||r||
+  // r = b - A x (float64), beta = ||r||, per-problem summary copied to the host
+  auto enqueue_residual = [&]() -> int {
     IE_TRY(apply_op<double>(p, op, x, r, rhs, true, batch, nullptr, 0, s, tw64));
+    IE_TRY((launch_orth<TA, double, false, false, true, FIN_CYCLE>("norm", tg, nb * 16, vgrid, s,
+                                                                   nullptr, 0L, 0L, r, n, n, 0, 0,
+                                                                   0, st, part, flags, batch, 0.0, 0)));
+    hipLaunchKernelGGL(k_summary, dim3(ceil_div(batch, 64)), dim3(64), 0, s, st,
+                       w.sum.as<GmSummary>(), batch);
+    IE_LAUNCH_CHECK();
+    IE_HIP(hipMemcpyAsync(w.host, w.sum.p, sizeof(GmSummary) * batch, hipMemcpyDeviceToHost, s));
+    return IE_OK;
+  };
+  // one restart cycle of Arnoldi steps and the solution update; `lagged` enqueues step j only if
+  // some problem was active after step j-2 (host reads the flags with one step of look-ahead)
+  auto enqueue_steps = [&](bool lagged) -> int {
+    {
+      ProfScope ps(s, "scale_cast", tg, nb * (16 + sa));
+      hipLaunchKernelGGL((k_scale_cast<TA>), vgrid, dim3(RB), 0, s, r, n, V, vbs, n, st);
+      IE_LAUNCH_CHECK();
+    }
+    for (int j = 0; j < m; ++j) {
+      if (lagged && j >= 2) {
+        IE_HIP(hipEventSynchronize(w.ev[j - 2]));
+        int cnt = 0;
+        for (int b = 0; b < batch; ++b) cnt += w.hflags[(j - 2) * batch + b];
+        if (cnt == 0) break;
+      }
+      if (lagged) {
+        const long grp = prof_new_group();
+        pending.emplace_back(j, grp);
+        prof_set_group(grp);
+      }
+      cx<TA>* vj = V + j * n;
+      cx<TA>* w1 = V + (j + 1) * n;
+      // w = A v_j  (v_j = nv[j] V_j, the factor applied on load)
+      MvArgs<TA> a{};
+      a.x = vj;
+      a.x_cs = N;
+      a.x_bs = vbs;
+      a.xscale = &st[0].nv[j];
+      a.xscale_bs = nv_bs;
+      a.M = sizeof(TA) == 8 ? (const TA*)op.M64 : (const TA*)op.M32;
+      a.M_cs = op.M_cs;
+      a.M_bs = op.M_bs;
+      a.src_z0 = 0;
+      a.src_z1 = p.nz;
+      a.hole_z0 = a.hole_z1 = -1;
+      a.out_z0 = 0;
+      a.out_z1 = p.nz;
+      a.y = w1;
+      a.y_cs = N;
+      a.y_bs = vbs;
+      a.a_e = 0;
+      a.a_x = 1;
+      a.a_m = (op.form == IE_CIE) ? TA(1) : TA(0);
+      a.a_s = (op.form == IE_CIE) ? TA(-2.0 * op.sigma0) : TA(-1);
+      a.active = act;
+      a.active_bs = act_bs;
+      IE_TRY(launch_matvec<TA>(p, a, batch, s, twa));
+      // Gram-Schmidt: h = V^H w (+ H column), w -= V h with ||w|| and the Givens update
+      IE_TRY((launch_orth<TA, TA, false, true, false, FIN_H>("orth_dots", tg, nb * sa * (j + 2),
+                                                             vgrid, s, V, n, vbs, w1, vbs, n, j + 1,
+                                                             j, 1, st, part, flags, batch, 0.0, 0)));
+      if (reorth)
+        IE_TRY((launch_orth<TA, TA, true, true, false, FIN_H>(
+            "orth_upd_dots", tg, nb * sa * (j + 3), vgrid, s, V, n, vbs, w1, vbs, n, j + 1, j, 0, st,
+            part, flags, batch, 0.0, 0)));
+      IE_TRY((launch_orth<TA, TA, true, false, true, FIN_GIVENS>(
+          "orth_upd_norm", tg, nb * sa * (j + 3), vgrid, s, V, n, vbs, w1, vbs, n, j + 1, j, 0, st,
+          part, flags, batch, 0.0, 0)));
+      if (lagged) {
+        prof_set_group(-1);
+        IE_HIP(hipMemcpyAsync(w.hflags + j * batch, flags + j * batch, sizeof(int) * batch,
+                              hipMemcpyDeviceToHost, s));
+        IE_HIP(hipEventRecord(w.ev[j], s));
+      }
+    }
+    ProfScope ps(s, "xupdate", tg, nb * (32 + sa * m));
+    hipLaunchKernelGGL((k_xupdate<TA>), vgrid, dim3(RB), 0, s, x, n, V, n, vbs, n, st);
+    IE_LAUNCH_CHECK();
+    return IE_OK;
+  };
+  // captured cycle for exactly these buffers / operator (replayed with one launch per cycle)
+  auto cycle_graph = [&]() -> hipGraphExec_t {
+    std::vector<const void*> key = {
+        (const void*)&p, p.t1_64.p, p.t2_64.p, p.t1_32.p, p.t2_32.p, p.ghat64.p, p.ghat32.p,
+        op.M64, op.M32, (const void*)op.M_cs, (const void*)op.M_bs, (const void*)long(op.form),
+        rhs, x, (const void*)long(batch), (const void*)long(m), (const void*)long(reorth),
+        (const void*)sizeof(TA), w.V.p, w.r.p, w.part.p, w.st.p, w.sum.p, w.host, w.flags.p,
+        tw64, twa};
+    double sg = op.sigma0;
+    const void* sgp;
+    std::memcpy(&sgp, &sg, sizeof(sgp));
+    key.push_back(sgp);
+    for (auto& g : w.graphs)
+      if (g.key == key) return g.exec;
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
+    int rc = enqueue_steps(false);
+    if (rc >= 0) rc = enqueue_residual();
+    const hipError_t ec = hipStreamEndCapture(s, &graph);
+    if (rc < 0 || ec != hipSuccess || graph == nullptr) {
+      if (graph) (void)hipGraphDestroy(graph);
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    if (w.graphs.size() >= 8) {
+      (void)hipGraphExecDestroy(w.graphs.front().exec);
+      w.graphs.erase(w.graphs.begin());
+    }
+    w.graphs.push_back(CycleGraph{key, exec});
+    return exec;
+  };
+
+  // ||b||, target, counters; first residual
+  IE_TRY((launch_orth<TA, double, false, false, true, FIN_BNORM>("norm", tg, nb * 16, vgrid, s,
+                                                                 nullptr, 0L, 0L,
+                                                                 const_cast<c128*>(rhs), n, n, 0, 0,
+                                                                 0, st, part, flags, batch, o.tol,
+                                                                 o.max_its)));
+  IE_TRY(enqueue_residual());
+  const bool graphs = g_use_graphs && w.use_graphs && !prof_enabled();
+  for (int cycle = 0;; ++cycle) {
+    IE_HIP(hipStreamSynchronize(s));
     for (int b = 0; b < batch; ++b) res[b].mv64 += 1;
-    hipLaunchKernelGGL((k_orth<double, false, false, true>), vgrid, dim3(RB), 0, s, r, 0L, 0L, r, n,
-                       n, 0, nullptr, part);
-    IE_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_cycle_begin, dim3(batch), dim3(RB), 0, s, st, part, G);
-    IE_LAUNCH_CHECK();
-    IE_TRY(fetch_summary(w, st, batch, s));
-    int any = 0;
+    // byte scaling of the previous cycle's launch groups (all its flags have arrived now)
+    for (auto& pg : pending) {
+      const int j = pg.first;
+      int cnt = 0;
+      if (j == 0)
+        cnt = prev_start_active;
+      else
+        for (int b = 0; b < batch; ++b) cnt += w.hflags[(j - 1) * batch + b];
+      prof_scale_group(pg.second, double(cnt) / batch);
+    }
+    pending.clear();
+    int any = 0, start_active = 0;
     for (int b = 0; b < batch; ++b) {
       const GmSummary& h = w.host[b];
       res[b].its = h.its;
@@ -421,67 +634,20 @@ static int gmres_impl(Plan& p, const OpDesc& op, const c128* rhs, c128* x, int b
       res[b].converged = h.beta <= o.tol * h.bnorm;
       if (h.active) {
         any = 1;
+        start_active += 1;
         res[b].cycles += 1;
       }
     }
     if (!any) break;
-    // V0 = r / beta
-    hipLaunchKernelGGL((k_scale_cast<TA>), vgrid, dim3(RB), 0, s, r, n, V, vbs, n, st);
-    IE_LAUNCH_CHECK();
-    for (int j = 0; j < m; ++j) {
-      cx<TA>* vj = V + j * n;
-      cx<TA>* w1 = V + (j + 1) * n;
-      // w = A v_j
-      {
-        MvArgs<TA> a{};
-        a.x = vj;
-        a.x_cs = N;
-        a.x_bs = vbs;
-        a.M = sizeof(TA) == 8 ? (const TA*)op.M64 : (const TA*)op.M32;
-        a.M_cs = op.M_cs;
-        a.M_bs = op.M_bs;
-        a.src_z0 = 0;
-        a.src_z1 = p.nz;
-        a.hole_z0 = a.hole_z1 = -1;
-        a.out_z0 = 0;
-        a.out_z1 = p.nz;
-        a.y = w1;
-        a.y_cs = N;
-        a.y_bs = vbs;
-        const TA sg = (op.form == IE_CIE) ? TA(-2.0 * op.sigma0) : TA(-1);
-        a.a_e = 0;
-        a.a_x = 1;
-        a.a_m = (op.form == IE_CIE) ? TA(1) : TA(0);
-        a.a_s = sg;
-        a.active = act;
-        a.active_bs = act_bs;
-        IE_TRY(launch_matvec<TA>(p, a, batch, s, twa));
-      }
-      // Gram-Schmidt: h = V^H w, w -= V h (twice with re-orthogonalisation), ||w||
-      hipLaunchKernelGGL((k_orth<TA, false, true, false>), vgrid, dim3(RB), 0, s, V, n, vbs, w1,
-                         vbs, n, j + 1, st, part);
-      IE_LAUNCH_CHECK();
-      hipLaunchKernelGGL(k_hsum, dim3(batch), dim3(RB), 0, s, st, part, G, j, j + 1, 1);
-      IE_LAUNCH_CHECK();
-      if (reorth) {
-        hipLaunchKernelGGL((k_orth<TA, true, true, false>), vgrid, dim3(RB), 0, s, V, n, vbs, w1,
-                           vbs, n, j + 1, st, part);
-        IE_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_hsum, dim3(batch), dim3(RB), 0, s, st, part, G, j, j + 1, 0);
-        IE_LAUNCH_CHECK();
-      }
-      hipLaunchKernelGGL((k_orth<TA, true, false, true>), vgrid, dim3(RB), 0, s, V, n, vbs, w1, vbs,
-                         n, j + 1, st, part);
-      IE_LAUNCH_CHECK();
-      hipLaunchKernelGGL(k_givens, dim3(batch), dim3(RB), 0, s, st, part, G, j);
-      IE_LAUNCH_CHECK();
-      hipLaunchKernelGGL((k_scale<TA>), vgrid, dim3(RB), 0, s, w1, vbs, n, st);
-      IE_LAUNCH_CHECK();
+    prev_start_active = start_active;
+    hipGraphExec_t ex = graphs ? cycle_graph() : nullptr;
+    if (ex != nullptr) {
+      IE_HIP(hipGraphLaunch(ex, s));
+      for (int b = 0; b < batch; ++b) res[b].graph_cycles += 1;
+    } else {
+      IE_TRY(enqueue_steps(true));
+      IE_TRY(enqueue_residual());
     }
-    hipLaunchKernelGGL(k_backsolve, dim3(ceil_div(batch, 64)), dim3(64), 0, s, st, batch);
-    IE_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_xupdate<TA>), vgrid, dim3(RB), 0, s, x, n, V, n, vbs, n, st);
-    IE_LAUNCH_CHECK();
   }
   for (int b = 0; b < batch; ++b) {
     const int arn = res[b].its;
@@ -490,6 +656,8 @@ static int gmres_impl(Plan& p, const OpDesc& op, const c128* rhs, c128* x, int b
     else
       res[b].mv32 += arn;
   }
+  IE_HIP(hipEventRecord(w.join[1], s));
+  IE_HIP(hipStreamWaitEvent(us, w.join[1], 0));
   return IE_OK;
 }
 

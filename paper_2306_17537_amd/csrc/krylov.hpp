@@ -10,6 +10,8 @@
 // once per restart cycle.
 #pragma once
 
+#include <vector>
+
 #include "ctx.hpp"
 
 namespace ie {
@@ -20,11 +22,11 @@ struct alignas(16) GmState {
   c128 H[MAXM][MAXM + 1];  // H[j][i]: Hessenberg column j, row i (rotated in place)
   c128 cs[MAXM], sn[MAXM];
   c128 g[MAXM + 1];
-  c128 y[MAXM];
-  c128 hc[MAXM + 1];  // coefficients of the current Gram-Schmidt pass
-  double beta, bnorm, target, est, hn2, inv_h;
+  c128 hc[MAXM + 1];   // coefficients of the current Gram-Schmidt pass
+  double nv[MAXM + 1]; // Krylov vector i is stored unnormalised: v_i = nv[i] V_i
+  double beta, bnorm, target, est, inv_h;
   int k, active, its, max_its;
-  int breakdown, pad_;
+  int breakdown, counter;  // counter: blocks done in the current reduction (last block finalises)
 };
 
 struct GmSummary {  // per problem, copied to the host once per cycle
@@ -49,17 +51,38 @@ struct GmOpts {
 };
 
 struct GmResult {
-  int its = 0, cycles = 0, converged = 0;
+  int its = 0, cycles = 0, converged = 0, graph_cycles = 0;
   double relres = 0;
   int mv64 = 0, mv32 = 0;
 };
 
+// A captured restart cycle, valid for the exact buffers and operator it was recorded with.
+struct CycleGraph {
+  std::vector<const void*> key;
+  hipGraphExec_t exec = nullptr;
+};
+
 struct KrylovWork {
-  DevBuf V, r, part, st, sum;
+  DevBuf V, r, part, st, sum, flags;
   GmSummary* host = nullptr;  // pinned
   int host_cap = 0;
+  int* hflags = nullptr;      // pinned [MAXM][batch] active flags after each Arnoldi step
+  int hflags_cap = 0;
+  hipEvent_t ev[MAXM] = {};
+  hipEvent_t join[2] = {};
+  hipStream_t ps = nullptr;   // private stream (capturable; default priority)
+  std::vector<CycleGraph> graphs;
+  bool use_graphs = true;
   ~KrylovWork() {
+    for (auto& g : graphs)
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (host) (void)hipHostFree(host);
+    if (hflags) (void)hipHostFree(hflags);
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    for (auto& e : join)
+      if (e) (void)hipEventDestroy(e);
+    if (ps) (void)hipStreamDestroy(ps);
   }
 };
 
@@ -73,6 +96,9 @@ int gmres_solve(Plan& p, const OpDesc& op, const c128* rhs, c128* x, int batch,
 template <typename T>
 int apply_op(Plan& p, const OpDesc& op, const cx<T>* x, cx<T>* y, const cx<T>* e, bool residual,
              int batch, const int* active, int active_bs, hipStream_t s, const cx<T>* tw);
+
+// process-wide switch for captured restart cycles (ie_set_option)
+extern bool g_use_graphs;
 
 // Deterministic float64 2-norms of `batch` complex128 vectors (stride n) -> host array.
 int norms_host(const c128* v, long n, int batch, double* out, KrylovWork& w, hipStream_t s);

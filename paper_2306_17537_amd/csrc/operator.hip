@@ -2,11 +2,20 @@
 // the discretised Green's tensor (eqs. 5-7, section 2.2), the background field of point dipoles
 // and the per-cell contrast tensors (eq. 3 and the contraction form).
 #include <cmath>
+#include <algorithm>
 #include <complex>
+#include <string>
 
 #include "ctx.hpp"
+#include "prof.hpp"
 
 namespace ie {
+
+static std::string shape_tag(int esz, int LX, int LY, int LZ, int nz, int batch) {
+  char b[96];
+  snprintf(b, sizeof(b), "%s L%dx%dx%d nz%d b%d", esz == 8 ? "c64" : "c128", LX, LY, LZ, nz, batch);
+  return b;
+}
 
 int fft_len(int n) {
   int L = 2;
@@ -36,7 +45,15 @@ struct XfwdL {
     using G = Geo<T, L>;
     const long rows = long(a.nz) * a.ny;
     dim3 grid(ceil_div(rows, G::NL), 1, batch);
-    hipLaunchKernelGGL((k_xfwd<T, L>), grid, dim3(G::NL * G::TL), 0, s, a);
+    const int z0 = std::max(a.src_z0, 0), z1 = std::min(a.src_z1, a.nz);
+    constexpr int threads = G::NL * G::TLR;
+    int zs = std::max(0, z1 - z0);
+    zs -= std::max(0, std::min(a.hole_z1, z1) - std::max(a.hole_z0, z0));
+    const double cs = sizeof(cx<T>), rs = sizeof(T);
+    const double by = double(batch) * (double(zs) * a.ny * a.nx * (3 * cs + (a.M ? 6 * rs : 0)) +
+                                       double(rows) * L * 3 * cs);
+    ProfScope ps(s, "xfwd", shape_tag(int(cs), a.LX, a.LY, a.LZ, a.nz, batch).c_str(), by);
+    hipLaunchKernelGGL((k_xfwd<T, L>), grid, dim3(threads), 0, s, a);
     IE_LAUNCH_CHECK();
     return IE_OK;
   }
@@ -47,7 +64,13 @@ struct XinvL {
     using G = Geo<T, L>;
     const long rows = long(a.out_z1 - a.out_z0) * a.ny;
     dim3 grid(ceil_div(rows, G::NL), 1, batch);
-    hipLaunchKernelGGL((k_xinv<T, L>), grid, dim3(G::NL * G::TL), 0, s, a);
+    const double cs = sizeof(cx<T>), rs = sizeof(T);
+    const bool ux = a.x && (a.a_x != T(0) || (a.M && a.a_m != T(0)));
+    const bool um = a.M && a.a_m != T(0);
+    const double per = 3 * cs + (ux ? 3 * cs : 0) + (um ? 6 * rs : 0) + (a.e ? 3 * cs : 0);
+    const double by = double(batch) * (double(rows) * L * 3 * cs + double(rows) * a.nx * per);
+    ProfScope ps(s, "xinv", shape_tag(int(cs), a.LX, a.LY, a.LZ, a.nz, batch).c_str(), by);
+    hipLaunchKernelGGL((k_xinv<T, L>), grid, dim3(G::NL * G::TLR), 0, s, a);
     IE_LAUNCH_CHECK();
     return IE_OK;
   }
@@ -57,6 +80,10 @@ struct ZconvL {
   static int run(const MvArgs<T>& a, int batch, hipStream_t s) {
     using G = Geo<T, L>;
     dim3 grid(ceil_div(a.LX, G::W), a.LY, batch);
+    const double cs = sizeof(cx<T>);
+    const double oct = 6.0 * (a.LX / 2 + 1) * (a.LY / 2 + 1) * (L / 2 + 1);
+    const double by = double(batch) * 3.0 * a.LY * a.LX * cs * (a.nz + (a.out_z1 - a.out_z0)) + oct * cs;
+    ProfScope ps(s, "zconv", shape_tag(int(cs), a.LX, a.LY, a.LZ, a.nz, batch).c_str(), by);
     hipLaunchKernelGGL((k_zconv<T, L>), grid, dim3(G::W * G::TL), 0, s, a);
     IE_LAUNCH_CHECK();
     return IE_OK;
@@ -68,6 +95,12 @@ struct ColL {
                  hipStream_t s, const cx<T>* tw) {
     using G = Geo<T, L>;
     dim3 grid(ceil_div(c.ncols, G::W), nplanes, batch);
+    const double cs = sizeof(cx<T>);
+    const double by = double(batch) * nplanes * double(c.ncols) * (c.rows_in + c.rows_out) * cs;
+    char tg[96];
+    snprintf(tg, sizeof(tg), "%s L%d planes%d cols%d b%d", cs == 8 ? "c64" : "c128", L, nplanes,
+             c.ncols, batch);
+    ProfScope ps(s, inv ? "yinv" : "yfwd", tg, by);
     if (inv)
       hipLaunchKernelGGL((k_colfft<T, L, true>), grid, dim3(G::W * G::TL), 0, s, in, out, c, tw);
     else
@@ -224,10 +257,10 @@ __global__ void k_green_eval(c128* __restrict__ out, int nx, int ny, int nz, int
 
 // Row FFT (contiguous lines of length L), in place, full length.
 template <typename T, int L, bool INV>
-__global__ void __launch_bounds__((Geo<T, L>::NL * Geo<T, L>::TL))
+__global__ void __launch_bounds__((Geo<T, L>::NL * Geo<T, L>::TLR))
     k_rowfft(cx<T>* buf, long nrows, const cx<T>* __restrict__ tw) {
   using G = Geo<T, L>;
-  constexpr int E = G::E, TL = G::TL, NL = G::NL;
+  constexpr int E = G::ER, TL = G::TLR, NL = G::NL;
   __shared__ cx<T> lds[NL * G::LP];
   const int t = threadIdx.x % TL;
   const int line = threadIdx.x / TL;
@@ -248,7 +281,7 @@ template <typename T, int L>
 struct RowL {
   static int run(cx<T>* buf, long nrows, hipStream_t s, const cx<T>* tw) {
     using G = Geo<T, L>;
-    hipLaunchKernelGGL((k_rowfft<T, L, false>), dim3(ceil_div(nrows, G::NL)), dim3(G::NL * G::TL),
+    hipLaunchKernelGGL((k_rowfft<T, L, false>), dim3(ceil_div(nrows, G::NL)), dim3(G::NL * G::TLR),
                        0, s, buf, nrows, tw);
     IE_LAUNCH_CHECK();
     return IE_OK;

@@ -29,6 +29,8 @@ struct MvArgs {
   const cx<T>* x;
   long x_cs, x_bs;
   int x_zoff;
+  const double* xscale;  // optional per-problem factor applied to x on load (batch stride xscale_bs)
+  long xscale_bs;
   const T* M;
   long M_cs, M_bs;
   int M_zoff;
@@ -64,16 +66,19 @@ __device__ __forceinline__ bool retired(const MvArgs<T>& a, int b) {
 // ---------------------------------------------------------------------------------------
 template <typename T, int L>
 struct Geo {
+  // column passes (y, z): E values per thread per line, W adjacent columns per block so that a
+  // row segment is one 128-byte line; at least 64 threads per block; LDS budget 64 KB
   static constexpr int Edef = sizeof(T) == 8 ? 8 : 16;
-  static constexpr int E = L < Edef ? L : Edef;  // values per thread per line
-  static constexpr int TL = L / E;               // threads per line
-  // column passes: W adjacent columns per block, LDS budget 64 KB for one component
-  static constexpr int Wt = (256 / TL) < 1 ? 1 : (256 / TL);
+  static constexpr int E = L < Edef ? L : Edef;
+  static constexpr int TL = L / E;
+  static constexpr int Wc = 128 / int(sizeof(cx<T>));
+  static constexpr int Wm = (64 / TL) > Wc ? (64 / TL) : Wc;
   static constexpr int Wl = (65536 / int(L * sizeof(cx<T>))) < 1 ? 1 : (65536 / int(L * sizeof(cx<T>)));
-  static constexpr int W0 = Wt < Wl ? Wt : Wl;
-  static constexpr int W = W0 > 64 ? 64 : W0;
-  // row passes: NL rows per block
-  static constexpr int NL0 = 256 / TL;
+  static constexpr int W = Wm < Wl ? Wm : Wl;
+  // row passes (x): ER values per thread, TLR threads per line, NL rows per block (~128 threads)
+  static constexpr int ER = L < 4 ? L : 4;
+  static constexpr int TLR = L / ER;
+  static constexpr int NL0 = 128 / TLR;
   static constexpr int NL = NL0 < 1 ? 1 : NL0;
   static constexpr int LP = LdsPadded::padded_len(L);
 };
@@ -93,10 +98,10 @@ __device__ __forceinline__ void tensor_apply(const T m[6], const cx<T> v[3], cx<
 // xfwd: contrast, pad, FFT along x.  Block: NL rows x TL threads; thread (row, t).
 // ---------------------------------------------------------------------------------------
 template <typename T, int LX>
-__global__ void __launch_bounds__((Geo<T, LX>::NL * Geo<T, LX>::TL))
+__global__ void __launch_bounds__((Geo<T, LX>::NL * Geo<T, LX>::TLR))
     k_xfwd(const MvArgs<T> a) {
   using G = Geo<T, LX>;
-  constexpr int E = G::E, TL = G::TL, NL = G::NL;
+  constexpr int E = G::ER, TL = G::TLR, NL = G::NL;
   __shared__ cx<T> lds[NL * G::LP];
   const int b = blockIdx.z;
   if (retired(a, b)) return;
@@ -110,6 +115,7 @@ __global__ void __launch_bounds__((Geo<T, LX>::NL * Geo<T, LX>::TL))
   const bool zero = !live || z < a.src_z0 || z >= a.src_z1 || (z >= a.hole_z0 && z < a.hole_z1);
   const cx<T>* x = a.x + b * a.x_bs + (long(z - a.x_zoff) * a.ny + yy) * a.nx;
   const T* M = a.M ? a.M + b * a.M_bs + (long(z - a.M_zoff) * a.ny + yy) * a.nx : nullptr;
+  const T xs = a.xscale ? T(a.xscale[b * a.xscale_bs]) : T(1);
   cx<T> v[3][E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
@@ -117,7 +123,7 @@ __global__ void __launch_bounds__((Geo<T, LX>::NL * Geo<T, LX>::TL))
     cx<T> xv[3] = {{0, 0}, {0, 0}, {0, 0}};
     if (!zero && i < a.nx) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) xv[c] = x[c * a.x_cs + i];
+      for (int c = 0; c < 3; ++c) xv[c] = xs * x[c * a.x_cs + i];
     }
     if (M != nullptr && !zero && i < a.nx) {
       T mm[6];
@@ -267,10 +273,10 @@ __global__ void __launch_bounds__((Geo<T, LZ>::W * Geo<T, LZ>::TL))
 // xinv: inverse FFT along x, crop, combine.  Rows (z, y) for z in [out_z0, out_z1).
 // ---------------------------------------------------------------------------------------
 template <typename T, int LX>
-__global__ void __launch_bounds__((Geo<T, LX>::NL * Geo<T, LX>::TL))
+__global__ void __launch_bounds__((Geo<T, LX>::NL * Geo<T, LX>::TLR))
     k_xinv(const MvArgs<T> a) {
   using G = Geo<T, LX>;
-  constexpr int E = G::E, TL = G::TL, NL = G::NL;
+  constexpr int E = G::ER, TL = G::TLR, NL = G::NL;
   __shared__ cx<T> lds[NL * G::LP];
   const int b = blockIdx.z;
   if (retired(a, b)) return;
@@ -298,6 +304,7 @@ __global__ void __launch_bounds__((Geo<T, LX>::NL * Geo<T, LX>::TL))
   const cx<T>* e = a.e ? a.e + b * a.e_bs + long(z - a.e_zoff) * a.ny * a.nx + cell : nullptr;
   const T* M = (a.M && a.a_m != T(0)) ? a.M + b * a.M_bs + long(z - a.M_zoff) * a.ny * a.nx + cell
                                        : nullptr;
+  const T xs = a.xscale ? T(a.xscale[b * a.xscale_bs]) : T(1);
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int i = t + m * TL;
@@ -308,7 +315,7 @@ __global__ void __launch_bounds__((Geo<T, LX>::NL * Geo<T, LX>::TL))
     if (x != nullptr && (a.a_x != T(0) || M != nullptr)) {
       cx<T> xv[3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) xv[c] = x[c * a.x_cs + i];
+      for (int c = 0; c < 3; ++c) xv[c] = xs * x[c * a.x_cs + i];
 #pragma unroll
       for (int c = 0; c < 3; ++c) r[c] = r[c] + a.a_x * xv[c];
       if (M != nullptr) {

@@ -20,6 +20,7 @@ IE_GS, IE_JACOBI = 0, 1
 IE_INIT_BACKGROUND, IE_INIT_USER, IE_INIT_LEARNED = 0, 1, 2
 IE_MAG_DIPOLE, IE_ELEC_DIPOLE = 0, 1
 IE_MAX_SWEEPS, IE_MAX_BLOCKS = 128, 16
+IE_OPT_GRAPHS = 1
 
 
 class ie_grid(C.Structure):
@@ -41,12 +42,12 @@ class ie_partition(C.Structure):
 
 class ie_gmres_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("restart", C.c_int32), ("max_its", C.c_int32),
-                ("precision", C.c_int32), ("form", C.c_int32)]
+                ("precision", C.c_int32), ("form", C.c_int32), ("reorth", C.c_int32)]
 
 
 class ie_gmres_stats(C.Structure):
     _fields_ = [("its", C.c_int32), ("restarts", C.c_int32), ("refinements", C.c_int32),
-                ("matvecs64", C.c_int32), ("matvecs32", C.c_int32),
+                ("matvecs64", C.c_int32), ("matvecs32", C.c_int32), ("graph_cycles", C.c_int32),
                 ("relres", C.c_double), ("seconds", C.c_double)]
 
 
@@ -62,13 +63,18 @@ class ie_dd_stats(C.Structure):
                 ("relres", C.c_double * (IE_MAX_SWEEPS + 1)),
                 ("matvecs64", C.c_int32), ("matvecs32", C.c_int32),
                 ("full_matvecs", C.c_int32), ("learned_used", C.c_int32),
-                ("seconds", C.c_double)]
+                ("graph_cycles", C.c_int32), ("seconds", C.c_double)]
 
 
 class ie_problem(C.Structure):
     _fields_ = [("grid", C.POINTER(ie_grid)), ("sigma6", C.c_void_p),
                 ("sources", C.POINTER(ie_source)), ("nsources", C.c_int32),
                 ("E_total", C.c_void_p), ("E_anom", C.c_void_p)]
+
+
+class ie_kernel_stat(C.Structure):
+    _fields_ = [("name", C.c_char * 96), ("launches", C.c_int32), ("total_ms", C.c_double),
+                ("min_ms", C.c_double), ("max_ms", C.c_double), ("bytes_per_launch", C.c_double)]
 
 
 _lib = None
@@ -91,8 +97,12 @@ def lib():
                                C.POINTER(ie_gmres_stats), vp]
         L.ie_dd_solve.argtypes = [C.POINTER(vp), i32, C.POINTER(ie_problem),
                                   C.POINTER(ie_dd_opts), C.POINTER(ie_dd_stats), vp]
+        L.ie_set_option.argtypes = [i32, i32]
+        L.ie_set_option.restype = C.c_int
+        L.ie_profile_begin.argtypes = []
+        L.ie_profile_end.argtypes = [C.POINTER(ie_kernel_stat), i32, C.POINTER(i32)]
         for f in ("ie_green_setup", "ie_ctx_destroy", "ie_background_field", "ie_matvec",
-                  "ie_gmres", "ie_dd_solve"):
+                  "ie_gmres", "ie_dd_solve", "ie_profile_begin", "ie_profile_end"):
             getattr(L, f).restype = C.c_int
         L.ie_last_error.restype = C.c_char_p
         L.ie_version.restype = C.c_char_p
@@ -176,9 +186,9 @@ def ie_matvec(ctx, sigma6, x, y, form=IE_CONVENTIONAL, precision=IE_FP64, stream
 
 
 def ie_gmres(ctx, sigma6, b, x, tol=1e-6, restart=10, max_its=2000, precision=IE_FP64,
-             form=IE_CIE, stream=None, allow_noconv=False):
+             form=IE_CIE, stream=None, allow_noconv=False, reorth=0):
     """Solve in place (x holds the initial guess).  Returns (status, ie_gmres_stats)."""
-    opts = ie_gmres_opts(tol, restart, max_its, precision, form)
+    opts = ie_gmres_opts(tol, restart, max_its, precision, form, reorth)
     st = ie_gmres_stats()
     rc = lib().ie_gmres(C.c_void_p(ctx), _ptr(sigma6), _ptr(b), _ptr(x), C.byref(opts),
                         C.byref(st), _stream(stream))
@@ -188,9 +198,9 @@ def ie_gmres(ctx, sigma6, b, x, tol=1e-6, restart=10, max_its=2000, precision=IE
 
 def dd_opts(scheme=IE_GS, adaptive=True, tol=1e-6, inner_tol_fixed=1e-6, max_sweeps=50,
             init=IE_INIT_BACKGROUND, restart=10, max_its=5000, precision=IE_FP64, form=IE_CIE,
-            nn=None) -> ie_dd_opts:
+            nn=None, reorth=0) -> ie_dd_opts:
     return ie_dd_opts(scheme, 1 if adaptive else 0, max_sweeps, init, tol, inner_tol_fixed,
-                      ie_gmres_opts(0.0, restart, max_its, precision, form),
+                      ie_gmres_opts(0.0, restart, max_its, precision, form, reorth),
                       C.c_void_p(nn) if nn else None)
 
 
@@ -211,3 +221,23 @@ def ie_dd_solve(ctxs, problems, opts: ie_dd_opts, stream=None, allow_noconv=Fals
     rc = lib().ie_dd_solve(carr, n, parr, C.byref(opts), stats, _stream(stream))
     _check(rc, "ie_dd_solve", allow_noconv)
     return rc, list(stats)
+
+
+def ie_profile_begin():
+    return _check(lib().ie_profile_begin(), "ie_profile_begin")
+
+
+def ie_profile_end(cap=256):
+    """Returns a list of dicts (name, launches, total_ms, min_ms, max_ms, bytes_per_launch)."""
+    arr = (ie_kernel_stat * cap)()
+    n = C.c_int32(0)
+    _check(lib().ie_profile_end(arr, cap, C.byref(n)), "ie_profile_end")
+    out = []
+    for k in arr[:min(cap, n.value)]:
+        out.append(dict(name=k.name.decode(), launches=k.launches, total_ms=k.total_ms,
+                        min_ms=k.min_ms, max_ms=k.max_ms, bytes_per_launch=k.bytes_per_launch))
+    return out
+
+
+def ie_set_option(option, value):
+    return _check(lib().ie_set_option(option, value), "ie_set_option")
