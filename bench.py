@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-seq", type=int, default=16,
+                    help="problems of the logging run also solved one call each (speed-up)")
     ap.add_argument("--profile-json", default=None, help="write the kernel profile here")
     return ap.parse_args()
 
@@ -208,6 +211,8 @@ def main():
         log(f"plain fp64: {plain}")
         log(f"variants: {variants}")
 
+    batch = None if args.no_batch else batch_bench(ie, torch)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(p, chosen_stats)
@@ -244,11 +249,70 @@ def main():
         "cpu_baseline": cpu,
         "plain_fp64": plain,
         "variants": variants,
+        "batch": batch,
         "matvec": mv,
         "accuracy": acc,
     }
     print(json.dumps(out))
     ie.ie_ctx_destroy(ctx)
+
+
+def batch_bench(ie, torch):
+    """Logging run: 64 tool positions x 2 frequencies = 128 solves on tool-centred grids of
+    three shapes, one block each (full-domain mixed GMRES), all in ONE ie_dd_solve call;
+    problems sharing (shape, frequency) are advanced as one batch (blockIdx.z)."""
+    import dataclasses
+    import synth
+    args = parse()
+    probs = [dataclasses.replace(p, z_bounds=(0, p.n[2])) for p in synth.config2()]
+    ctxs, grids = {}, {}
+    t0 = time.perf_counter()
+    for p in probs:
+        key = (p.n, p.freq)
+        if key not in ctxs:
+            g = ie.make_grid(p.n, p.h, p.origin)
+            ctxs[key] = ie.ie_green_setup(g, ie.ie_medium(p.sigma0, p.freq, 0.0), p.z_bounds)
+            grids[key] = g
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    opts = ie.dd_opts(tol=1e-6, adaptive=False, inner_tol_fixed=5e-7, precision=ie.IE_MIXED,
+                      max_its=5000)
+    data = []
+    for p in probs:
+        key = (p.n, p.freq)
+        E = torch.zeros((3, p.n[2], p.n[1], p.n[0]), dtype=torch.complex128, device="cuda:0")
+        data.append((ctxs[key], dict(grid=grids[key], sigma6=torch.from_numpy(p.sigma6).cuda(),
+                                     sources=p.sources, E_total=E)))
+
+    def run(sel):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, st = ie.ie_dd_solve([data[i][0] for i in sel], [data[i][1] for i in sel], opts)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, st
+
+    allsel = list(range(len(probs)))
+    run(allsel[:12])  # warm-up of every kernel shape
+    log("logging run: 128 solves in one call")
+    t_all, st = run(allsel)
+    mv = sum(s.matvecs32 + s.matvecs64 for s in st)
+    worst = max(s.relres[s.sweeps] for s in st)
+    nseq = min(args.batch_seq, len(probs))
+    t_seq = sum(run([i])[0] for i in range(nseq))
+    t_bat, _ = run(list(range(nseq)))
+    for c in ctxs.values():
+        ie.ie_ctx_destroy(c)
+    out = dict(workload="config2: 64 positions x {400 kHz, 2 MHz} = 128 solves, grids "
+                        "32^3 / 48x48x64 / 64x64x96 (seed 202), full-domain mixed GMRES(10), "
+                        "tol 1e-6, one ie_dd_solve call",
+               solves=len(probs), groups=len(ctxs), wall_s=round(t_all, 4),
+               solves_per_s=round(len(probs) / t_all, 2), matvecs=mv,
+               matvecs_per_s=round(mv / t_all, 1), worst_relres=worst,
+               green_setup_s=round(t_setup, 3),
+               subset=dict(problems=nseq, one_call_each_s=round(t_seq, 4),
+                           batched_s=round(t_bat, 4), speedup=round(t_seq / t_bat, 3)))
+    log(f"batch: {out}")
+    return out
 
 
 def cpu_baseline(p, gst):

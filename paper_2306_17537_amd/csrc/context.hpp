@@ -7,6 +7,13 @@
 
 #include "krylov.hpp"
 
+namespace ie {
+// Scratch of the domain-decomposition driver, sized for the largest problem group seen.
+struct DdBufs {
+  DevBuf D64, M64, M32, A64, Ai64, E0, E, Eold, rhs, x, active, flags, bad;
+};
+}  // namespace ie
+
 struct ie_ctx {
   ie_grid grid{};
   ie::Medium med{};
@@ -21,7 +28,8 @@ struct ie_ctx {
   ie::DevBuf xt, bt, E0, tmp;
   ie::KrylovWork kw;
   // domain decomposition scratch
-  ie::DevBuf blk_rhs, blk_rhs2, blk_x, blk_save;
+  ie::DevBuf blk_rhs2, blk_save;
+  ie::DdBufs dd;
   ie::KrylovWork kw_blk;
   ie::Plan* block_plan(int nzb) {
     auto it = blocks.find(nzb);

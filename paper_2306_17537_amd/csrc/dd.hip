@@ -1,4 +1,5 @@
-// Alg. 1: block Gauss-Seidel / Jacobi over z-slab sub-domains (section 2.3, eqs. 19-24).
+// Alg. 1: block Gauss-Seidel / Jacobi over z-slab sub-domains (section 2.3, eqs. 19-24), for a
+// batch of problems.
 //
 // Per sweep and block i: the right-hand side b_i = E(i,0) + sum_{j != i} G(ij) dsigma(j) E(j)
 // is one full-grid convolution whose source skips block i's planes and whose output keeps only
@@ -6,10 +7,19 @@
 // block system (I - G(ii) dsigma(i)) E(i) = b_i is then solved by restarted GMRES on the
 // block's own padded FFT grid, warm-started from the previous sweep, to the adaptive (e / 10)
 // or fixed inner tolerance.  After each sweep the full-domain relative residual e of eq. (9)
-// is recomputed in float64.  Block Jacobi solves all equal-sized blocks as one batch.
+// is recomputed in float64.
+//
+// Problems that share a context (same grid, partition and medium, hence the same spectra) are
+// advanced together: every convolution and every block solve runs once per group with the
+// problem as the batch index; each problem keeps its own e, inner tolerance and stopping, and a
+// converged problem drops out (its inner tolerance becomes infinite and its coupling / residual
+// convolutions are retired by its active flag).
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <limits>
+#include <map>
 #include <vector>
 
 #include "context.hpp"
@@ -18,7 +28,7 @@ namespace ie {
 
 namespace {
 
-__global__ void k_plane_nonzero(const double* __restrict__ D, long N, long plane, int nz,
+__global__ void k_plane_nonzero(const double* __restrict__ D, long N, long plane,
                                 int* __restrict__ flag) {
   const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= N) return;
@@ -27,38 +37,67 @@ __global__ void k_plane_nonzero(const double* __restrict__ D, long N, long plane
   if (nz_) flag[i / plane] = 1;
 }
 
-// copy planes [z0, z0 + nzb) of a [3][nz][ny][nx] field (component stride N) to or from a
-// contiguous [3][nzb][ny][nx] block
-int copy_block(const c128* src, long src_cs, c128* dst, long dst_cs, long plane_elems, int nzb,
-               hipStream_t s) {
-  for (int c = 0; c < 3; ++c)
-    IE_HIP(hipMemcpyAsync(dst + c * dst_cs, src + c * src_cs, sizeof(c128) * plane_elems * nzb,
-                          hipMemcpyDeviceToDevice, s));
+// Copy planes [z0, z0 + nzb) of `batch` fields [3][nz][ny][nx] (field stride fs, component
+// stride cs) to / from contiguous blocks [3][nzb][ny][nx] (block stride 3 nb); problems whose
+// mask entry is 0 are skipped.
+__global__ void k_copy_blocks(const c128* __restrict__ src, c128* __restrict__ dst, long fs,
+                              long cs, long plane, int z0, int nzb, int to_block,
+                              const int* __restrict__ mask) {
+  const long nb = long(nzb) * plane;
+  const long total = 3 * nb;
+  const int b = blockIdx.y;
+  if (mask != nullptr && mask[b] == 0) return;
+  for (long e = long(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += long(gridDim.x) * blockDim.x) {
+    const int c = int(e / nb);
+    const long r = e % nb;
+    const long fi = b * fs + c * cs + z0 * plane + r;
+    const long bi = b * total + e;
+    if (to_block)
+      dst[bi] = src[fi];
+    else
+      dst[fi] = src[bi];
+  }
+}
+
+int copy_blocks(const c128* src, c128* dst, long fs, long cs, long plane, int z0, int nzb,
+                bool to_block, int batch, const int* mask, hipStream_t s) {
+  const long total = 3L * nzb * plane;
+  dim3 grid(std::min(4096, ceil_div(total, 256)), batch);
+  hipLaunchKernelGGL(k_copy_blocks, grid, dim3(256), 0, s, src, dst, fs, cs, plane, z0, nzb,
+                     to_block ? 1 : 0, mask);
+  IE_LAUNCH_CHECK();
   return IE_OK;
 }
 
-struct DdRun {
+struct Group {
   ie_ctx* c;
   hipStream_t s;
+  int B;  // problems in the group
   long N, plane;
   int form;
-  const double* D64;  // dsigma (coupling and residual)
-  // inner-form contrast (dsigma or b) and CIE transforms, full-grid arrays
-  const double* M64;
-  const float* M32;
-  const double* A64;
-  const double* Ai64;
+  // device arrays; problem stride in brackets
+  double* D64;   // dsigma           [6N]
+  double* M64;   // inner contrast   [6N]
+  float* M32;    //                  [6N]
+  double* A64;   // CIE a            [6N]
+  double* Ai64;  // CIE a^-1         [6N]
+  c128* E0;      //                  [3N]
+  c128* E;       //                  [3N]
+  c128* Eold;    //                  [3N]
+  int* active;   // per problem: still sweeping
 };
 
-// rhs = E0 on block [z0, z1) + G (dsigma src) with block planes removed from the source
-int coupling_rhs(DdRun& r, const c128* src, const c128* E0, int z0, int z1, c128* rhs) {
-  Plan& F = *r.c->full;
+// rhs_p = E0_p on block [z0, z1) + G (dsigma_p src_p) with block planes removed from the source
+int coupling_rhs(Group& g, const c128* src, int z0, int z1, c128* rhs) {
+  Plan& F = *g.c->full;
   MvArgs<double> a{};
   a.x = src;
-  a.x_cs = r.N;
-  a.x_bs = 0;
-  a.M = r.D64;
-  a.M_cs = r.N;
+  a.x_cs = g.N;
+  a.x_bs = 3 * g.N;
+  a.M = g.D64;
+  a.M_cs = g.N;
+  a.M_bs = 6 * g.N;
   a.src_z0 = 0;
   a.src_z1 = F.nz;
   a.hole_z0 = z0;
@@ -66,256 +105,267 @@ int coupling_rhs(DdRun& r, const c128* src, const c128* E0, int z0, int z1, c128
   a.out_z0 = z0;
   a.out_z1 = z1;
   a.y = rhs;
-  a.y_cs = long(z1 - z0) * r.plane;
+  a.y_cs = long(z1 - z0) * g.plane;
+  a.y_bs = 3 * a.y_cs;
   a.y_zoff = z0;
-  a.e = E0;
-  a.e_cs = r.N;
+  a.e = g.E0;
+  a.e_cs = g.N;
+  a.e_bs = 3 * g.N;
   a.e_zoff = 0;
   a.a_e = 1;
   a.a_x = 0;
   a.a_m = 0;
   a.a_s = 1;
-  return launch_matvec<double>(F, a, 1, r.s, tw64(r.c));
+  a.active = g.active;
+  a.active_bs = 1;
+  return launch_matvec<double>(F, a, g.B, g.s, tw64(g.c));
 }
 
-// e = ||E0 - (I - G dsigma) E|| / ||E0|| on the full grid
-int full_relres(DdRun& r, const c128* E, const c128* E0, double e0norm, double* e) {
-  Plan& F = *r.c->full;
-  IE_TRY(r.c->tmp.ensure(sizeof(c128) * 3 * r.N));
+// e_p = ||E0_p - (I - G dsigma_p) E_p|| / ||E0_p|| on the full grid, all problems
+int full_relres(Group& g, const double* e0norm, double* e) {
+  Plan& F = *g.c->full;
+  IE_TRY(g.c->tmp.ensure(sizeof(c128) * 3 * g.N * g.B));
   OpDesc op;
   op.form = IE_CONVENTIONAL;
-  op.M64 = r.D64;
-  op.M_cs = r.N;
-  op.M_bs = 0;
-  IE_TRY(apply_op<double>(F, op, E, r.c->tmp.as<c128>(), E0, true, 1, nullptr, 0, r.s, tw64(r.c)));
-  double nr = 0;
-  IE_TRY(norms_host(r.c->tmp.as<c128>(), 3 * r.N, 1, &nr, r.c->kw, r.s));
-  *e = e0norm > 0 ? nr / e0norm : 0.0;
+  op.M64 = g.D64;
+  op.M_cs = g.N;
+  op.M_bs = 6 * g.N;
+  IE_TRY(apply_op<double>(F, op, g.E, g.c->tmp.as<c128>(), g.E0, true, g.B, nullptr, 0, g.s,
+                          tw64(g.c)));
+  std::vector<double> nr(g.B);
+  IE_TRY(norms_host(g.c->tmp.as<c128>(), 3 * g.N, g.B, nr.data(), g.c->kw, g.s));
+  for (int b = 0; b < g.B; ++b) e[b] = e0norm[b] > 0 ? nr[b] / e0norm[b] : 0.0;
   return IE_OK;
 }
 
-// Solve `batch` consecutive equal blocks starting at plane z0 (rhs, x contiguous per block).
-int block_solve(DdRun& r, Plan& B, int z0, int batch, c128* rhs, c128* x, double tol,
+// Solve block [z0, z0 + nzb) of every problem (rhs, x contiguous, block stride 3 nb).
+int block_solve(Group& g, Plan& B, int z0, c128* rhs, c128* x, const double* tols,
                 const ie_gmres_opts& inner, GmResult* res) {
   const long nb = B.ncell();
-  const long off = long(z0) * r.plane;
+  const long off = long(z0) * g.plane;
   OpDesc op;
-  op.form = r.form;
-  op.sigma0 = r.c->med.sigma0;
-  op.M64 = r.M64 + off;
-  op.M32 = r.M32 + off;
-  op.M_cs = r.N;
-  op.M_bs = nb;  // consecutive equal slabs
+  op.form = g.form;
+  op.sigma0 = g.c->med.sigma0;
+  op.M64 = g.M64 + off;
+  op.M32 = g.M32 + off;
+  op.M_cs = g.N;
+  op.M_bs = 6 * g.N;
   GmOpts o;
-  o.tol = tol;
+  o.tols = tols;
   o.restart = inner.restart;
   o.max_its = inner.max_its;
   o.precision = inner.precision;
   o.reorth = inner.reorth == 2 ? 1 : 0;
-  if (r.form == IE_CIE) {
+  if (g.form == IE_CIE) {
     // C e = sqrt(sigma0) b_i, e = a x;  x = a^-1 e, per block
-    IE_TRY(r.c->blk_rhs2.ensure(sizeof(c128) * 3 * nb * batch));
-    IE_TRY(r.c->blk_save.ensure(sizeof(c128) * 3 * nb * batch));
-    c128* rs = r.c->blk_rhs2.as<c128>();
-    IE_TRY(launch_scale(rhs, rs, std::sqrt(r.c->med.sigma0), 3 * nb * batch, r.s));
-    c128* xt = r.c->blk_save.as<c128>();
-    for (int b = 0; b < batch; ++b)
-      IE_TRY(launch_tensor_apply(r.A64 + off + b * nb, r.N, x + b * 3 * nb, nb, xt + b * 3 * nb, nb,
-                                 nb, r.s));
-    IE_TRY(gmres_solve(B, op, rs, xt, batch, o, res, r.c->kw_blk, tw64(r.c), tw32(r.c), r.s));
-    for (int b = 0; b < batch; ++b)
-      IE_TRY(launch_tensor_apply(r.Ai64 + off + b * nb, r.N, xt + b * 3 * nb, nb, x + b * 3 * nb, nb,
-                                 nb, r.s));
+    IE_TRY(g.c->blk_rhs2.ensure(sizeof(c128) * 3 * nb * g.B));
+    IE_TRY(g.c->blk_save.ensure(sizeof(c128) * 3 * nb * g.B));
+    c128* rs = g.c->blk_rhs2.as<c128>();
+    c128* xt = g.c->blk_save.as<c128>();
+    IE_TRY(launch_scale(rhs, rs, std::sqrt(g.c->med.sigma0), 3 * nb * g.B, g.s));
+    for (int b = 0; b < g.B; ++b)
+      IE_TRY(launch_tensor_apply(g.A64 + b * 6 * g.N + off, g.N, x + b * 3 * nb, nb,
+                                 xt + b * 3 * nb, nb, nb, g.s));
+    IE_TRY(gmres_solve(B, op, rs, xt, g.B, o, res, g.c->kw_blk, tw64(g.c), tw32(g.c), g.s));
+    for (int b = 0; b < g.B; ++b)
+      IE_TRY(launch_tensor_apply(g.Ai64 + b * 6 * g.N + off, g.N, xt + b * 3 * nb, nb,
+                                 x + b * 3 * nb, nb, nb, g.s));
     return IE_OK;
   }
-  return gmres_solve(B, op, rhs, x, batch, o, res, r.c->kw_blk, tw64(r.c), tw32(r.c), r.s);
+  return gmres_solve(B, op, rhs, x, g.B, o, res, g.c->kw_blk, tw64(g.c), tw32(g.c), g.s);
 }
 
-int dd_one(ie_ctx* c, const ie_problem& pr, const ie_dd_opts& o, ie_dd_stats& st, hipStream_t s) {
-  const auto t0 = std::chrono::steady_clock::now();
-  std::memset(&st, 0, sizeof(st));
-  if (c->zb.empty()) return fail(IE_ESTATE, "context was set up without a partition");
+int check_problem(ie_ctx* c, const ie_problem& pr) {
   const ie_grid& g = c->grid;
   if (pr.grid) {
     const ie_grid& q = *pr.grid;
     if (q.nx != g.nx || q.ny != g.ny || q.nz != g.nz || q.h != g.h || q.origin[0] != g.origin[0] ||
         q.origin[1] != g.origin[1] || q.origin[2] != g.origin[2])
-      return fail(IE_EINVAL, "problem grid differs from the context grid");
+      return fail(IE_EINVAL, "problem grid differs from its context grid");
   }
-  if (pr.E_total == nullptr) return fail(IE_EINVAL, "E_total is NULL");
-  IE_TRY(check_sources(c, pr.sources, pr.nsources));
+  if (pr.E_total == nullptr || pr.sigma6 == nullptr)
+    return fail(IE_EINVAL, "E_total or sigma6 is NULL");
+  return check_sources(c, pr.sources, pr.nsources);
+}
+
+int dd_group(ie_ctx* c, const std::vector<int>& idx, const ie_problem* problems,
+             const ie_dd_opts& o, ie_dd_stats* stats, hipStream_t s, int* worst) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (c->zb.empty()) return fail(IE_ESTATE, "context was set up without a partition");
+  const int B = int(idx.size());
+  for (int b = 0; b < B; ++b) {
+    IE_TRY(check_problem(c, problems[idx[b]]));
+    std::memset(&stats[idx[b]], 0, sizeof(ie_dd_stats));
+  }
   const int form = o.inner.form;
-  if (form != IE_CONVENTIONAL && form != IE_CIE) return fail(IE_EINVAL, "bad inner form");
-  if (o.inner.precision != IE_FP64 && o.inner.precision != IE_MIXED)
-    return fail(IE_EINVAL, "bad inner precision");
-  if (!(c->prec_mask & o.inner.precision) || !(c->prec_mask & IE_FP64))
-    return fail(IE_EINVAL, "context lacks the spectra this precision needs");
-  if (o.max_sweeps < 1 || o.max_sweeps > IE_MAX_SWEEPS)
-    return fail(IE_EINVAL, "max_sweeps must be in [1, %d]", IE_MAX_SWEEPS);
-  if (o.init == IE_INIT_LEARNED) return fail(IE_EINVAL, "learned initial guess needs an ie_nn handle");
+  const ie_grid& gr = c->grid;
   Plan& F = *c->full;
-  DdRun r;
-  r.c = c;
-  r.s = s;
-  r.N = F.ncell();
-  r.plane = long(g.nx) * g.ny;
-  r.form = form;
+  const long N = F.ncell();
+  const long plane = long(gr.nx) * gr.ny;
   const int M = int(c->zb.size()) - 1;
-  st.nblocks = M;
-
-  // contrast tensors: dsigma for coupling / residual, inner form for the block operators
-  IE_TRY(prepare_contrast(c, pr.sigma6, form, s));
-  DevBuf dsig;
+  DdBufs& gb = c->dd;
+  IE_TRY(gb.D64.ensure(sizeof(double) * 6 * N * B));
+  IE_TRY(gb.M64.ensure(sizeof(double) * 6 * N * B));
+  IE_TRY(gb.M32.ensure(sizeof(float) * 6 * N * B));
   if (form == IE_CIE) {
-    IE_TRY(dsig.ensure(sizeof(double) * 6 * r.N));
-    IE_TRY(launch_prep(pr.sigma6, r.N, c->med.sigma0, IE_CONVENTIONAL, dsig.as<double>(), nullptr,
-                       nullptr, nullptr, c->bad.as<int>(), s));
-    r.D64 = dsig.as<double>();
-  } else {
-    r.D64 = c->M64.as<double>();
+    IE_TRY(gb.A64.ensure(sizeof(double) * 6 * N * B));
+    IE_TRY(gb.Ai64.ensure(sizeof(double) * 6 * N * B));
   }
-  r.M64 = c->M64.as<double>();
-  r.M32 = c->M32.as<float>();
-  r.A64 = form == IE_CIE ? c->A64.as<double>() : nullptr;
-  r.Ai64 = form == IE_CIE ? c->Ai64.as<double>() : nullptr;
+  IE_TRY(gb.E0.ensure(sizeof(c128) * 3 * N * B));
+  IE_TRY(gb.E.ensure(sizeof(c128) * 3 * N * B));
+  if (o.scheme == IE_JACOBI) IE_TRY(gb.Eold.ensure(sizeof(c128) * 3 * N * B));
+  IE_TRY(gb.active.ensure(sizeof(int) * B));
+  IE_TRY(gb.flags.ensure(sizeof(int) * gr.nz * B));
+  IE_TRY(gb.bad.ensure(sizeof(int)));
+  Group g;
+  g.c = c;
+  g.s = s;
+  g.B = B;
+  g.N = N;
+  g.plane = plane;
+  g.form = form;
+  g.D64 = gb.D64.as<double>();
+  g.M64 = gb.M64.as<double>();
+  g.M32 = gb.M32.as<float>();
+  g.A64 = gb.A64.as<double>();
+  g.Ai64 = gb.Ai64.as<double>();
+  g.E0 = gb.E0.as<c128>();
+  g.E = gb.E.as<c128>();
+  g.Eold = gb.Eold.as<c128>();
+  g.active = gb.active.as<int>();
 
-  // which blocks carry contrast
-  std::vector<int> plane_flag(g.nz, 0);
-  {
-    DevBuf f;
-    IE_TRY(f.ensure(sizeof(int) * g.nz));
-    IE_HIP(hipMemsetAsync(f.p, 0, sizeof(int) * g.nz, s));
-    hipLaunchKernelGGL(k_plane_nonzero, dim3(ceil_div(r.N, 256)), dim3(256), 0, s, r.D64, r.N,
-                       r.plane, g.nz, f.as<int>());
+  // contrast tensors (dsigma for coupling / residual; the inner form for block operators),
+  // background fields, initial guesses, and which blocks carry contrast
+  IE_HIP(hipMemsetAsync(gb.bad.p, 0, sizeof(int), s));
+  IE_HIP(hipMemsetAsync(gb.flags.p, 0, sizeof(int) * gr.nz * B, s));
+  for (int b = 0; b < B; ++b) {
+    const ie_problem& pr = problems[idx[b]];
+    IE_TRY(launch_prep(pr.sigma6, N, c->med.sigma0, IE_CONVENTIONAL, g.D64 + b * 6 * N,
+                       form == IE_CIE ? nullptr : g.M32 + b * 6 * N, nullptr, nullptr,
+                       gb.bad.as<int>(), s));
+    if (form == IE_CIE)
+      IE_TRY(launch_prep(pr.sigma6, N, c->med.sigma0, IE_CIE, g.M64 + b * 6 * N,
+                         g.M32 + b * 6 * N, g.A64 + b * 6 * N, g.Ai64 + b * 6 * N,
+                         gb.bad.as<int>(), s));
+    else
+      IE_HIP(hipMemcpyAsync(g.M64 + b * 6 * N, g.D64 + b * 6 * N, sizeof(double) * 6 * N,
+                            hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_plane_nonzero, dim3(ceil_div(N, 256)), dim3(256), 0, s,
+                       g.D64 + b * 6 * N, N, plane, gb.flags.as<int>() + b * gr.nz);
     IE_LAUNCH_CHECK();
-    IE_HIP(hipMemcpyAsync(plane_flag.data(), f.p, sizeof(int) * g.nz, hipMemcpyDeviceToHost, s));
-    IE_HIP(hipStreamSynchronize(s));
+    IE_TRY(launch_background(gr.nx, gr.ny, gr.nz, gr.h, gr.origin, c->med, pr.sources,
+                             pr.nsources, g.E0 + b * 3 * N, s));
+    const c128* init = o.init == IE_INIT_USER ? (const c128*)pr.E_total : g.E0 + b * 3 * N;
+    IE_HIP(hipMemcpyAsync(g.E + b * 3 * N, init, sizeof(c128) * 3 * N, hipMemcpyDeviceToDevice,
+                          s));
   }
-  std::vector<int> has(M, 0);
-  for (int i = 0; i < M; ++i)
-    for (int z = c->zb[i]; z < c->zb[i + 1]; ++z) has[i] |= plane_flag[z];
+  int bad = 0;
+  std::vector<int> pflag(size_t(gr.nz) * B);
+  IE_HIP(hipMemcpyAsync(&bad, gb.bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  IE_HIP(hipMemcpyAsync(pflag.data(), gb.flags.p, sizeof(int) * gr.nz * B,
+                        hipMemcpyDeviceToHost, s));
+  IE_HIP(hipStreamSynchronize(s));
+  if (bad) return fail(IE_EINVAL, "sigma6 holds a non-finite or non-positive-definite tensor");
+  std::vector<std::vector<int>> has(B, std::vector<int>(M, 0));
+  for (int b = 0; b < B; ++b)
+    for (int i = 0; i < M; ++i)
+      for (int z = c->zb[i]; z < c->zb[i + 1]; ++z) has[b][i] |= pflag[size_t(b) * gr.nz + z];
 
-  // background field and initial guess
-  IE_TRY(c->E0.ensure(sizeof(c128) * 3 * r.N));
-  c128* E0 = c->E0.as<c128>();
-  c128* E = (c128*)pr.E_total;
-  IE_TRY(launch_background(g.nx, g.ny, g.nz, g.h, g.origin, c->med, pr.sources, pr.nsources, E0, s));
-  if (o.init != IE_INIT_USER)
-    IE_HIP(hipMemcpyAsync(E, E0, sizeof(c128) * 3 * r.N, hipMemcpyDeviceToDevice, s));
-  double e0norm = 0;
-  IE_TRY(norms_host(E0, 3 * r.N, 1, &e0norm, c->kw, s));
-  double e = 0;
-  IE_TRY(full_relres(r, E, E0, e0norm, &e));
-  st.full_matvecs += 1;
-  st.matvecs64 += 1;
-  st.relres[0] = e;
-
-  // equal blocks -> batched Jacobi
-  bool equal = true;
-  for (int i = 0; i < M; ++i) equal = equal && (c->zb[i + 1] - c->zb[i] == c->zb[1] - c->zb[0]);
-  const long maxb = [&] {
-    long m = 0;
-    for (int i = 0; i < M; ++i) m = std::max(m, long(c->zb[i + 1] - c->zb[i]) * r.plane);
-    return m;
-  }();
-  IE_TRY(c->blk_rhs.ensure(sizeof(c128) * 3 * maxb * M));
-  IE_TRY(c->blk_x.ensure(sizeof(c128) * 3 * maxb * M));
-  DevBuf Eold;
-  if (o.scheme == IE_JACOBI) IE_TRY(Eold.ensure(sizeof(c128) * 3 * r.N));
-
-  int status = IE_OK;
-  while (e > o.tol) {
-    if (st.sweeps >= o.max_sweeps) {
-      status = IE_ENOCONV;
-      break;
-    }
-    const double itol = o.adaptive ? e / 10.0 : o.inner_tol_fixed;
-    const int k = st.sweeps;
-    if (o.scheme == IE_JACOBI) {
-      IE_HIP(hipMemcpyAsync(Eold.p, E, sizeof(c128) * 3 * r.N, hipMemcpyDeviceToDevice, s));
-      // all right-hand sides from the previous sweep
-      for (int i = 0; i < M; ++i) {
-        const int z0 = c->zb[i], z1 = c->zb[i + 1];
-        const long nb = long(z1 - z0) * r.plane;
-        c128* rhs = c->blk_rhs.as<c128>() + (equal ? i * 3 * nb : 0);
-        IE_TRY(coupling_rhs(r, Eold.as<c128>(), E0, z0, z1, rhs));
-        st.full_matvecs += 1;
-        st.matvecs64 += 1;
-        if (!equal) {
-          // unequal blocks: solve one at a time
-          c128* x = c->blk_x.as<c128>();
-          if (!has[i]) {
-            IE_TRY(copy_block(rhs, nb, E + z0 * r.plane, r.N, r.plane, z1 - z0, s));
-            st.block_its[k][i] = 0;
-            continue;
-          }
-          IE_TRY(copy_block(Eold.as<c128>() + z0 * r.plane, r.N, x, nb, r.plane, z1 - z0, s));
-          GmResult gr;
-          IE_TRY(block_solve(r, *c->block_plan(z1 - z0), z0, 1, rhs, x, itol, o.inner, &gr));
-          IE_TRY(copy_block(x, nb, E + z0 * r.plane, r.N, r.plane, z1 - z0, s));
-          st.block_its[k][i] = gr.its;
-          st.matvecs64 += gr.mv64;
-          st.matvecs32 += gr.mv32;
-          st.graph_cycles += gr.graph_cycles;
-        }
-      }
-      if (equal) {
-        const int nzb = c->zb[1] - c->zb[0];
-        const long nb = long(nzb) * r.plane;
-        c128* x = c->blk_x.as<c128>();
-        // x <- previous iterate of every block ([3][nz] slabs are consecutive per component)
-        for (int i = 0; i < M; ++i)
-          IE_TRY(copy_block(Eold.as<c128>() + c->zb[i] * r.plane, r.N, x + i * 3 * nb, nb, r.plane,
-                            nzb, s));
-        std::vector<GmResult> gr(M);
-        IE_TRY(block_solve(r, *c->block_plan(nzb), 0, M, c->blk_rhs.as<c128>(), x, itol, o.inner,
-                           gr.data()));
-        for (int i = 0; i < M; ++i) {
-          // blocks without contrast have A_ii = I: E(i) = b_i (their GMRES converges at once)
-          const c128* srcb = has[i] ? x + i * 3 * nb : c->blk_rhs.as<c128>() + i * 3 * nb;
-          IE_TRY(copy_block(srcb, nb, E + c->zb[i] * r.plane, r.N, r.plane, nzb, s));
-          st.block_its[k][i] = has[i] ? gr[i].its : 0;
-          st.matvecs64 += gr[i].mv64;
-          st.matvecs32 += gr[i].mv32;
-          if (i == 0) st.graph_cycles += gr[i].graph_cycles;
-        }
-      }
-    } else {
-      for (int i = 0; i < M; ++i) {
-        const int z0 = c->zb[i], z1 = c->zb[i + 1];
-        const long nb = long(z1 - z0) * r.plane;
-        c128* rhs = c->blk_rhs.as<c128>();
-        c128* x = c->blk_x.as<c128>();
-        IE_TRY(coupling_rhs(r, E, E0, z0, z1, rhs));
-        st.full_matvecs += 1;
-        st.matvecs64 += 1;
-        if (!has[i]) {
-          IE_TRY(copy_block(rhs, nb, E + z0 * r.plane, r.N, r.plane, z1 - z0, s));
-          st.block_its[k][i] = 0;
-          continue;
-        }
-        IE_TRY(copy_block(E + z0 * r.plane, r.N, x, nb, r.plane, z1 - z0, s));
-        GmResult gr;
-        IE_TRY(block_solve(r, *c->block_plan(z1 - z0), z0, 1, rhs, x, itol, o.inner, &gr));
-        IE_TRY(copy_block(x, nb, E + z0 * r.plane, r.N, r.plane, z1 - z0, s));
-        st.block_its[k][i] = gr.its;
-        st.matvecs64 += gr.mv64;
-        st.matvecs32 += gr.mv32;
-        st.graph_cycles += gr.graph_cycles;
-      }
-    }
-    for (int i = 0; i < M; ++i) st.total_its += st.block_its[k][i];
-    st.sweeps += 1;
-    IE_TRY(full_relres(r, E, E0, e0norm, &e));
+  std::vector<double> e0norm(B), e(B);
+  IE_TRY(norms_host(g.E0, 3 * N, B, e0norm.data(), c->kw, s));
+  IE_TRY(full_relres(g, e0norm.data(), e.data()));
+  std::vector<int> act(B), sweeps(B, 0);
+  for (int b = 0; b < B; ++b) {
+    ie_dd_stats& st = stats[idx[b]];
+    st.nblocks = M;
     st.full_matvecs += 1;
     st.matvecs64 += 1;
-    st.relres[st.sweeps] = e;
+    st.relres[0] = e[b];
+    act[b] = e[b] > o.tol;
   }
-  if (pr.E_anom) IE_TRY(launch_sub(E, E0, (c128*)pr.E_anom, 3 * r.N, s));
+  long maxb = 0;
+  for (int i = 0; i < M; ++i) maxb = std::max(maxb, long(c->zb[i + 1] - c->zb[i]) * plane);
+  IE_TRY(gb.rhs.ensure(sizeof(c128) * 3 * maxb * B));
+  IE_TRY(gb.x.ensure(sizeof(c128) * 3 * maxb * B));
+  c128* rhs = gb.rhs.as<c128>();
+  c128* x = gb.x.as<c128>();
+  std::vector<double> tols(B);
+  std::vector<GmResult> res(B);
+  const double inf = std::numeric_limits<double>::infinity();
+
+  while (true) {
+    bool any = false;
+    for (int b = 0; b < B; ++b) {
+      if (act[b] && sweeps[b] >= o.max_sweeps) act[b] = 0;  // out of sweeps: reported below
+      any = any || act[b];
+    }
+    if (!any) break;
+    IE_HIP(hipMemcpyAsync(g.active, act.data(), sizeof(int) * B, hipMemcpyHostToDevice, s));
+    const c128* src = g.E;
+    if (o.scheme == IE_JACOBI) {
+      IE_HIP(hipMemcpyAsync(g.Eold, g.E, sizeof(c128) * 3 * N * B, hipMemcpyDeviceToDevice, s));
+      src = g.Eold;
+    }
+    for (int i = 0; i < M; ++i) {
+      const int z0 = c->zb[i], z1 = c->zb[i + 1], nzb = z1 - z0;
+      const long nb = long(nzb) * plane;
+      IE_TRY(coupling_rhs(g, src, z0, z1, rhs));
+      // warm start from the previous sweep (for Jacobi src = E at sweep k; for GS block i of E
+      // has not been updated yet in this sweep either)
+      IE_TRY(copy_blocks(src, x, 3 * N, N, plane, z0, nzb, true, B, g.active, s));
+      bool solve = false;
+      for (int b = 0; b < B; ++b) {
+        const bool live = act[b] && has[b][i];
+        tols[b] = live ? (o.adaptive ? e[b] / 10.0 : o.inner_tol_fixed) : inf;
+        solve = solve || live;
+      }
+      if (solve)
+        IE_TRY(block_solve(g, *c->block_plan(nzb), z0, rhs, x, tols.data(), o.inner, res.data()));
+      for (int b = 0; b < B; ++b) {
+        if (!act[b]) continue;
+        // blocks without contrast have A_ii = I: E(i) = b_i
+        const c128* from = has[b][i] ? x + b * 3 * nb : rhs + b * 3 * nb;
+        for (int cc = 0; cc < 3; ++cc)
+          IE_HIP(hipMemcpyAsync(g.E + b * 3 * N + cc * N + z0 * plane, from + cc * nb,
+                                sizeof(c128) * nb, hipMemcpyDeviceToDevice, s));
+        ie_dd_stats& st = stats[idx[b]];
+        st.full_matvecs += 1;
+        st.matvecs64 += 1;
+        if (has[b][i]) {
+          st.block_its[sweeps[b]][i] = res[b].its;
+          st.matvecs64 += res[b].mv64;
+          st.matvecs32 += res[b].mv32;
+          st.graph_cycles += res[b].graph_cycles;
+        }
+      }
+    }
+    IE_TRY(full_relres(g, e0norm.data(), e.data()));
+    for (int b = 0; b < B; ++b) {
+      if (!act[b]) continue;
+      ie_dd_stats& st = stats[idx[b]];
+      for (int i = 0; i < M; ++i) st.total_its += st.block_its[sweeps[b]][i];
+      sweeps[b] += 1;
+      st.sweeps = sweeps[b];
+      st.relres[sweeps[b]] = e[b];
+      st.full_matvecs += 1;
+      st.matvecs64 += 1;
+      if (e[b] <= o.tol) act[b] = 0;
+    }
+  }
+  // outputs
+  for (int b = 0; b < B; ++b) {
+    const ie_problem& pr = problems[idx[b]];
+    IE_HIP(hipMemcpyAsync(pr.E_total, g.E + b * 3 * N, sizeof(c128) * 3 * N,
+                          hipMemcpyDeviceToDevice, s));
+    if (pr.E_anom)
+      IE_TRY(launch_sub(g.E + b * 3 * N, g.E0 + b * 3 * N, (c128*)pr.E_anom, 3 * N, s));
+  }
   IE_HIP(hipStreamSynchronize(s));
-  st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  if (status == IE_ENOCONV)
-    return fail(IE_ENOCONV, "DD stopped after %d sweeps at relative residual %.3e", st.sweeps, e);
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  for (int b = 0; b < B; ++b) {
+    stats[idx[b]].seconds = secs;
+    if (e[b] > o.tol) *worst = IE_ENOCONV;
+  }
   return IE_OK;
 }
 
@@ -328,18 +378,43 @@ extern "C" int ie_dd_solve(ie_ctx* const* ctxs, int32_t nproblems, const ie_prob
                            const ie_dd_opts* opts, ie_dd_stats* stats, void* stream) {
   if (ctxs == nullptr || problems == nullptr || opts == nullptr || nproblems < 1)
     return fail(IE_EINVAL, "NULL argument or no problems");
-  if (!(opts->tol >= 0)) return fail(IE_EINVAL, "bad tol");
-  if (opts->scheme != IE_GS && opts->scheme != IE_JACOBI) return fail(IE_EINVAL, "bad scheme");
-  hipStream_t s = (hipStream_t)stream;
-  int worst = IE_OK;
+  const ie_dd_opts& o = *opts;
+  if (!(o.tol >= 0)) return fail(IE_EINVAL, "bad tol");
+  if (o.scheme != IE_GS && o.scheme != IE_JACOBI) return fail(IE_EINVAL, "bad scheme");
+  if (o.inner.form != IE_CONVENTIONAL && o.inner.form != IE_CIE)
+    return fail(IE_EINVAL, "bad inner form");
+  if (o.inner.precision != IE_FP64 && o.inner.precision != IE_MIXED)
+    return fail(IE_EINVAL, "bad inner precision");
+  if (o.inner.reorth < 0 || o.inner.reorth > 2) return fail(IE_EINVAL, "bad reorth");
+  if (o.inner.restart < 1 || o.inner.restart > MAXM)
+    return fail(IE_EINVAL, "restart must be in [1, %d]", MAXM);
+  if (o.inner.max_its < 1) return fail(IE_EINVAL, "max_its must be >= 1");
+  if (o.max_sweeps < 1 || o.max_sweeps > IE_MAX_SWEEPS)
+    return fail(IE_EINVAL, "max_sweeps must be in [1, %d]", IE_MAX_SWEEPS);
+  if (o.init == IE_INIT_LEARNED)
+    return fail(IE_EINVAL, "learned initial guess needs an ie_nn handle");
+  if (o.init != IE_INIT_BACKGROUND && o.init != IE_INIT_USER) return fail(IE_EINVAL, "bad init");
+  if (!(o.adaptive == 0 || o.adaptive == 1)) return fail(IE_EINVAL, "adaptive must be 0 or 1");
   for (int p = 0; p < nproblems; ++p) {
     if (ctxs[p] == nullptr) return fail(IE_EINVAL, "context %d is NULL", p);
-    ie_dd_stats local;
-    ie_dd_stats& st = stats ? stats[p] : local;
-    const int rc = dd_one(ctxs[p], problems[p], *opts, st, s);
-    if (rc < 0) return rc;
-    if (rc == IE_ENOCONV) worst = IE_ENOCONV;
+    if (!(ctxs[p]->prec_mask & o.inner.precision) || !(ctxs[p]->prec_mask & IE_FP64))
+      return fail(IE_EINVAL, "context %d lacks the spectra this precision needs", p);
   }
+  std::vector<ie_dd_stats> local;
+  if (stats == nullptr) {
+    local.resize(nproblems);
+    stats = local.data();
+  }
+  // group the problems by context (same spectra), in order of first appearance
+  std::vector<ie_ctx*> order;
+  std::map<ie_ctx*, std::vector<int>> groups;
+  for (int p = 0; p < nproblems; ++p) {
+    if (!groups.count(ctxs[p])) order.push_back(ctxs[p]);
+    groups[ctxs[p]].push_back(p);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  int worst = IE_OK;
+  for (ie_ctx* c : order) IE_TRY(dd_group(c, groups[c], problems, o, stats, s, &worst));
   if (worst == IE_ENOCONV) return fail(IE_ENOCONV, "at least one problem did not converge");
   return IE_OK;
 }

@@ -193,7 +193,8 @@ __global__ void __launch_bounds__(RB)
 template <int FIN, int CM>
 __global__ void __launch_bounds__(RB)
     k_fin(GmState* __restrict__ st, const double* __restrict__ part, int G, int count, int j,
-          int first, int* __restrict__ flags, int batch, double tol, int max_its) {
+          int first, int* __restrict__ flags, int batch, double tol, int max_its,
+          const double* __restrict__ tols) {
   const int b = blockIdx.x;
   GmState& S = st[b];
   if (FIN == FIN_H || FIN == FIN_GIVENS) {
@@ -230,7 +231,7 @@ __global__ void __launch_bounds__(RB)
     S.active = (beta > S.target && S.its < S.max_its) ? 1 : 0;
   } else if (FIN == FIN_BNORM) {
     S.bnorm = sqrt(fin[SL::NS]);
-    S.target = tol * S.bnorm;
+    S.target = (tols ? tols[b] : tol) * S.bnorm;
     S.its = 0;
     S.max_its = max_its;
     S.active = 0;
@@ -243,7 +244,7 @@ template <typename TA, typename TW, bool UPD, bool DOTS, bool NRM, int FIN>
 int launch_orth(const char* pname, const char* ptag, double pbytes, dim3 grid, hipStream_t s,
                 const cx<TA>* V, long vstride, long vbs, cx<TW>* w, long wbs, long n, int count,
                 int j, int first, GmState* st, double* part, int* flags, int batch, double tol,
-                int max_its) {
+                int max_its, const double* tols = nullptr) {
 #define IE_ORTH(CMV)                                                                             \
   do {                                                                                           \
     {                                                                                            \
@@ -256,7 +257,7 @@ int launch_orth(const char* pname, const char* ptag, double pbytes, dim3 grid, h
     if (FIN != FIN_NONE) {                                                                       \
       ProfScope ps(s, "finalise", ptag, 0);                                                      \
       hipLaunchKernelGGL((k_fin<FIN, CMV>), dim3(grid.z), dim3(RB), 0, s, st, part, int(grid.x),   \
-                         count, j, first, flags, batch, tol, max_its);                           \
+                         count, j, first, flags, batch, tol, max_its, tols);                     \
     }                                                                                            \
   } while (0)
   if (count <= 1)
@@ -604,12 +605,18 @@ static int gmres_impl(Plan& p, const OpDesc& op, const c128* rhs, c128* x, int b
     return exec;
   };
 
-  // ||b||, target, counters; first residual
+  // ||b||, target (per-problem tolerances if given), counters; first residual
+  const double* dtols = nullptr;
+  if (o.tols != nullptr) {
+    IE_TRY(w.tols.ensure(sizeof(double) * batch));
+    IE_HIP(hipMemcpyAsync(w.tols.p, o.tols, sizeof(double) * batch, hipMemcpyHostToDevice, s));
+    dtols = w.tols.as<double>();
+  }
   IE_TRY((launch_orth<TA, double, false, false, true, FIN_BNORM>("norm", tg, nb * 16, vgrid, s,
                                                                  nullptr, 0L, 0L,
                                                                  const_cast<c128*>(rhs), n, n, 0, 0,
                                                                  0, st, part, flags, batch, o.tol,
-                                                                 o.max_its)));
+                                                                 o.max_its, dtols)));
   IE_TRY(enqueue_residual());
   const bool graphs = g_use_graphs && w.use_graphs && !prof_enabled();
   for (int cycle = 0;; ++cycle) {
@@ -631,7 +638,7 @@ static int gmres_impl(Plan& p, const OpDesc& op, const c128* rhs, c128* x, int b
       const GmSummary& h = w.host[b];
       res[b].its = h.its;
       res[b].relres = h.bnorm > 0 ? h.beta / h.bnorm : 0.0;
-      res[b].converged = h.beta <= o.tol * h.bnorm;
+      res[b].converged = h.beta <= (o.tols ? o.tols[b] : o.tol) * h.bnorm;
       if (h.active) {
         any = 1;
         start_active += 1;

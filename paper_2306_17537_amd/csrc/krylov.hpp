@@ -44,6 +44,7 @@ struct OpDesc {
 
 struct GmOpts {
   double tol = 1e-6;
+  const double* tols = nullptr;  // optional HOST array of per-problem tolerances (overrides tol)
   int restart = 10;
   int max_its = 2000;
   int precision = IE_FP64;
@@ -63,7 +64,7 @@ struct CycleGraph {
 };
 
 struct KrylovWork {
-  DevBuf V, r, part, st, sum, flags;
+  DevBuf V, r, part, st, sum, flags, tols;
   GmSummary* host = nullptr;  // pinned
   int host_cap = 0;
   int* hflags = nullptr;      // pinned [MAXM][batch] active flags after each Arnoldi step

@@ -1,0 +1,125 @@
+"""Batched solves (many tool positions and frequencies in one ie_dd_solve call): each member of
+the batch equals its standalone solve, and matches the oracle."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import operator, solve
+from tests.gpu_common import banner, dev, field_shape, host, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _contexts(problems):
+    from paper_2306_17537_amd import ie
+    ctxs, grids = {}, {}
+    for p in problems:
+        key = (p.n, p.freq, p.z_bounds)
+        if key not in ctxs:
+            g = ie.make_grid(p.n, p.h, p.origin)
+            ctxs[key] = ie.ie_green_setup(g, ie.ie_medium(p.sigma0, p.freq, 0.0), p.z_bounds)
+            grids[key] = g
+    return ctxs, grids
+
+
+def _solve_and_compare(torch, probs, opts, ctxs, grids, expect_converged):
+    from paper_2306_17537_amd import ie
+
+    def mk(p):
+        key = (p.n, p.freq, p.z_bounds)
+        E = torch.zeros(field_shape(p), dtype=torch.complex128, device="cuda:0")
+        return ctxs[key], dict(grid=grids[key], sigma6=dev(p.sigma6), sources=p.sources,
+                               E_total=E, E_anom=torch.zeros_like(E))
+
+    pairs = [mk(p) for p in probs]
+    rc, stats = ie.ie_dd_solve([c for c, _ in pairs], [d for _, d in pairs], opts,
+                               allow_noconv=not expect_converged)
+    for k, (p, (c, d)) in enumerate(zip(probs, pairs)):
+        c1, d1 = mk(p)
+        ie.ie_dd_solve([c1], [d1], opts, allow_noconv=not expect_converged)
+        assert torch.equal(d["E_total"], d1["E_total"]), k
+        if expect_converged:
+            assert stats[k].relres[stats[k].sweeps] <= 1e-6
+    return pairs, stats
+
+
+@pytest.mark.parametrize("scheme,prec", [("gs", "mixed"), ("jacobi", "fp64")])
+def test_batched_dd_members_equal_standalone_solves(torch, scheme, prec):
+    """2 MHz members of the logging run (three grid shapes, two and three z slabs) in one call:
+    every member is bit-identical to its own standalone call."""
+    from paper_2306_17537_amd import ie
+    probs = [p for p in synth.config2()[:12] if p.freq == 2.0e6]
+    banner(f"batch of {len(probs)} {scheme} {prec}: shapes {sorted(set(p.n for p in probs))}")
+    ctxs, grids = _contexts(probs)
+    gs = scheme == "gs"
+    opts = ie.dd_opts(scheme=ie.IE_GS if gs else ie.IE_JACOBI, tol=1e-6, max_sweeps=100,
+                      precision=ie.IE_MIXED if prec == "mixed" else ie.IE_FP64)
+    try:
+        pairs, stats = _solve_and_compare(torch, probs, opts, ctxs, grids, expect_converged=gs)
+        if gs:
+            for k in (0, len(probs) - 1):
+                p = probs[k]
+                st = solve.setup(p)
+                E = host(pairs[k][1]["E_total"])
+                assert operator.relres(st.Ghat, st.dsig, E, st.E0, p.n) <= 1.01e-6
+    finally:
+        for c in ctxs.values():
+            ie.ie_ctx_destroy(c)
+
+
+def test_batched_single_block_members_converge_and_equal_standalone(torch):
+    """All members (400 kHz and 2 MHz) with one block each, i.e. batched full-domain
+    mixed-precision GMRES: converged, bit-identical to standalone calls, oracle residual."""
+    from paper_2306_17537_amd import ie
+    import dataclasses
+    probs = [dataclasses.replace(p, z_bounds=(0, p.n[2])) for p in synth.config2()[:8]]
+    ctxs, grids = _contexts(probs)
+    opts = ie.dd_opts(tol=1e-6, adaptive=False, inner_tol_fixed=5e-7, precision=ie.IE_MIXED,
+                      max_its=5000)
+    try:
+        pairs, stats = _solve_and_compare(torch, probs, opts, ctxs, grids, expect_converged=True)
+        assert all(s.sweeps == 1 for s in stats)
+        p = probs[0]
+        st = solve.setup(p)
+        E = host(pairs[0][1]["E_total"])
+        assert operator.relres(st.Ghat, st.dsig, E, st.E0, p.n) <= 1.01e-6
+    finally:
+        for c in ctxs.values():
+            ie.ie_ctx_destroy(c)
+
+
+def test_batch_with_converged_and_zero_contrast_members(torch):
+    """A batch mixing a zero-contrast problem (converged before the first sweep) with ordinary
+    ones: the zero-contrast member returns E0 with no sweeps, the others are unaffected."""
+    from paper_2306_17537_amd import ie
+    base = synth.random_problem((8, 8, 8), seed=41, contrast=2.0, freq=4e5, z_bounds=(0, 4, 8))
+    zero = synth.random_problem((8, 8, 8), seed=42, freq=4e5, z_bounds=(0, 4, 8))
+    zero.sigma6[:] = 0.0
+    zero.sigma6[:3] = zero.sigma0
+    other = synth.random_problem((8, 8, 8), seed=43, contrast=1.0, freq=4e5, z_bounds=(0, 4, 8))
+    g = ie.make_grid(base.n, base.h, base.origin)
+    ctx = ie.ie_green_setup(g, ie.ie_medium(base.sigma0, base.freq, 0.0), base.z_bounds)
+    try:
+        probs = [base, zero, other]
+        outs = [torch.zeros(field_shape(p), dtype=torch.complex128, device="cuda:0") for p in probs]
+        rc, stats = ie.ie_dd_solve([ctx] * 3, [dict(grid=g, sigma6=dev(p.sigma6), sources=p.sources,
+                                                    E_total=o) for p, o in zip(probs, outs)],
+                                   ie.dd_opts(tol=1e-8, precision=ie.IE_FP64))
+        assert stats[1].sweeps == 0 and stats[1].total_its == 0
+        st = solve.setup(zero)
+        assert rel(host(outs[1]), st.E0) < 1e-14
+        for k in (0, 2):
+            E1 = torch.zeros_like(outs[k])
+            _, s1 = ie.ie_dd_solve([ctx], [dict(grid=g, sigma6=dev(probs[k].sigma6),
+                                                sources=probs[k].sources, E_total=E1)],
+                                   ie.dd_opts(tol=1e-8, precision=ie.IE_FP64))
+            assert torch.equal(E1, outs[k])
+    finally:
+        ie.ie_ctx_destroy(ctx)
