@@ -239,6 +239,57 @@ int ie_profile_begin(void);
 int ie_profile_end(ie_kernel_stat* out, int32_t cap, int32_t* count);
 
 /*
+ * Learned initial guess (not in the paper, whose inner solves start from the previous sweep):
+ * a 3-D convolutional encoder-decoder with hand-written BF16 MFMA kernels (float32
+ * accumulation, float32 master weights, Adam).  Level l has base_ch * 2^l channels; 3x3x3
+ * convolutions with bias and ReLU; encoder levels joined by 2x2x2 average pooling, decoder
+ * levels by nearest 2x upsampling and concatenation with the encoder output of the same level;
+ * a 1x1x1 head.  Tensors are channels-last [batch][nz][ny][nx][ch]; network inputs are BF16
+ * (uint16 bit patterns), outputs and targets float32; all DEVICE pointers.  nz, ny, nx must be
+ * divisible by 2^(levels-1).  Parameters: per layer W[taps][c_in][c_out] then bias[c_out],
+ * layers in forward order.  A network is used by one thread at a time.
+ * For the solver the network maps 14 channels [ (sigma - sigma0 I)/sigma0 (xx,yy,zz,xy,xz,yz),
+ * (re, im) of b / rms(b) for x, y, z, (re, im) of k0 h ] to 6 channels (re, im of (E - b) / rms(b)).
+ */
+typedef struct ie_nn ie_nn;
+typedef struct {
+    int32_t  in_ch, out_ch, base_ch, levels;
+    uint64_t seed;       /* weight initialisation (He normal, zero bias) */
+} ie_nn_config;
+
+int ie_nn_create(const ie_nn_config* cfg, void* stream, ie_nn** out);
+int ie_nn_destroy(ie_nn* nn);
+int ie_nn_num_params(const ie_nn* nn, int64_t* count);
+/* which = 0: float32 master weights, 1: gradients of the last backward; HOST array */
+int ie_nn_get_params(const ie_nn* nn, float* host, int64_t count, int32_t which);
+int ie_nn_set_params(ie_nn* nn, const float* host, int64_t count);  /* resets Adam state */
+int ie_nn_forward(ie_nn* nn, const uint16_t* x, int32_t batch, int32_t nz, int32_t ny, int32_t nx,
+                  float* y, void* stream);
+/* forward, then parameter gradients of <dy, y> (read with ie_nn_get_params(..., 1)) */
+int ie_nn_backward(ie_nn* nn, const uint16_t* x, const float* dy, int32_t batch, int32_t nz,
+                   int32_t ny, int32_t nx, float* y, void* stream);
+/* one Adam step on the mean squared error to `target`; loss (HOST, nullable) is synchronised */
+int ie_nn_train_step(ie_nn* nn, const uint16_t* x, const float* target, int32_t batch, int32_t nz,
+                     int32_t ny, int32_t nx, float lr, float* loss, void* stream);
+/*
+ * The network's GEMM kernel alone (for tests of its matrix-core operand layout):
+ * C[M][N] = op(A) op(B), float32 row-major output, BF16 inputs; op(A) is A [M][K] (a_trans = 0)
+ * or A^T with A stored [K][M]; op(B) is B [K][N] (b_trans = 0) or B^T with B stored [N][K];
+ * the K range is split `splits` ways (1..64) and the partial products summed in fixed order.
+ * DEVICE pointers; synchronises with `stream`.
+ */
+int ie_nn_gemm(const uint16_t* A, const uint16_t* B, float* C, int32_t M, int32_t N, int32_t K,
+               int32_t a_trans, int32_t b_trans, int32_t splits, void* stream);
+/*
+ * Learned initial guess for (I - G dsigma) x = b on the context's full grid: features from
+ * sigma6 and b, the network, x_nn = b + rms(b) * output; x (DEVICE complex128, in: default guess,
+ * out: chosen guess) is replaced by x_nn only if ||b - A x_nn|| < ||b - A x|| (float64).
+ * accepted (HOST, nullable) reports the choice.  Synchronises with `stream`.
+ */
+int ie_nn_guess(ie_ctx* ctx, ie_nn* nn, const double* sigma6, const void* b, void* x,
+                int32_t* accepted, void* stream);
+
+/*
  * Library options (process-wide).
  *   IE_OPT_GRAPHS: 1 (default) replays each Krylov restart cycle as a captured hipGraph; 0 issues
  *                  every kernel launch directly (the launch profiler always uses direct launches).

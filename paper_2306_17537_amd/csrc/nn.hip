@@ -1,0 +1,868 @@
+// Learned initial guess: a 3-D convolutional encoder-decoder trained and run with hand-written
+// kernels.  Convolutions are im2col + a BF16 MFMA GEMM with float32 accumulation
+// (v_mfma_f32_16x16x16_bf16); backward passes use the same GEMM (data gradient through the
+// transposed weights, weight gradient with split K) and gather-form col2im (no atomics).
+// Activations are channels-last BF16; master weights, gradients and Adam moments are float32.
+//
+// Architecture (level l has base * 2^l channels; 3x3x3 convolutions with bias and ReLU):
+//   encoder  level 0: conv(in -> C0), conv(C0 -> C0); level l >= 1: 2x2x2 average pooling,
+//            conv(C_{l-1} -> C_l), conv(C_l -> C_l)
+//   decoder  l = L-2 .. 0: [nearest 2x upsampling of level l+1, skip l] -> conv -> conv
+//   head     1x1x1 conv C0 -> out (no ReLU)
+// Weights per layer: [taps][c_in][c_out] then bias [c_out], taps ordered (dz, dy, dx), z slowest.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <random>
+#include <vector>
+
+#include "context.hpp"
+#include "prof.hpp"
+
+using u16 = uint16_t;
+
+namespace ie {
+namespace nn {
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__host__ __device__ inline float bf2f(u16 h) {
+  union {
+    uint32_t u;
+    float f;
+  } v;
+  v.u = uint32_t(h) << 16;
+  return v.f;
+}
+__host__ __device__ inline u16 f2bf(float f) {  // round to nearest even
+  union {
+    uint32_t u;
+    float f;
+  } v;
+  v.f = f;
+  if ((v.u & 0x7f800000u) == 0x7f800000u) return u16((v.u >> 16) | ((v.u & 0xffff) ? 0x40 : 0));
+  v.u += 0x7fffu + ((v.u >> 16) & 1u);
+  return u16(v.u >> 16);
+}
+
+// ---------------------------------------------------------------------------------------
+// GEMM: C(M x N) = A(M x K) B(K x N), BF16 operands, float32 accumulation on MFMA.
+// A(m, k) = A[m sam + k sak], B(k, n) = B[k sbk + n sbn]; out of range reads are zero.
+// blockIdx.z handles K range [z kchunk, (z+1) kchunk).  Output: float32 partials
+// Cf[z cpart + m scm + n scn] (split K) or, with Cb, BF16 with optional bias and ReLU.
+// Tile 64 x 64 x 32, four wavefronts each owning a 32 x 32 quarter (2 x 2 MFMA tiles).
+// ---------------------------------------------------------------------------------------
+constexpr int GBM = 64, GBN = 64, GBK = 32, GPAD = 4;
+
+template <bool A_KC, bool B_NC>
+__global__ void __launch_bounds__(256)
+    k_gemm(const u16* __restrict__ A, long sam, long sak, const u16* __restrict__ B, long sbk,
+           long sbn, int M, int N, int K, int kchunk, float* __restrict__ Cf, long scm, long scn,
+           long cpart, u16* __restrict__ Cb, const float* __restrict__ bias, int relu) {
+  __shared__ u16 As[GBM][GBK + GPAD];
+  __shared__ u16 Bs[GBN][GBK + GPAD];
+  const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
+  const int kb = blockIdx.z * kchunk;
+  const int ke = min(K, kb + kchunk);
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  f4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = kb; k0 < ke; k0 += GBK) {
+#pragma unroll
+    for (int i = 0; i < (GBM * GBK) / 256; ++i) {
+      const int idx = t + i * 256;
+      int mm, kk;
+      if (A_KC) {
+        mm = idx / GBK;
+        kk = idx % GBK;
+      } else {
+        kk = idx / GBM;
+        mm = idx % GBM;
+      }
+      const int gm = m0 + mm, gk = k0 + kk;
+      As[mm][kk] = (gm < M && gk < ke) ? A[long(gm) * sam + long(gk) * sak] : u16(0);
+    }
+#pragma unroll
+    for (int i = 0; i < (GBN * GBK) / 256; ++i) {
+      const int idx = t + i * 256;
+      int nn, kk;
+      if (B_NC) {
+        kk = idx / GBN;
+        nn = idx % GBN;
+      } else {
+        nn = idx / GBK;
+        kk = idx % GBK;
+      }
+      const int gn = n0 + nn, gk = k0 + kk;
+      Bs[nn][kk] = (gn < N && gk < ke) ? B[long(gk) * sbk + long(gn) * sbn] : u16(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < GBK; ks += 16) {
+      s4 a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        a[i] = *reinterpret_cast<const s4*>(&As[wm + i * 16 + (lane & 15)][ks + 4 * (lane >> 4)]);
+        b[i] = *reinterpret_cast<const s4*>(&Bs[wn + i * 16 + (lane & 15)][ks + 4 * (lane >> 4)]);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // D layout of the 16x16 tile: lane l holds rows 4 (l / 16) + e, e = 0..3, column l % 16
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int m = m0 + wm + i * 16 + 4 * (lane >> 4) + e;
+        const int n = n0 + wn + j * 16 + (lane & 15);
+        if (m >= M || n >= N) continue;
+        float v = acc[i][j][e];
+        if (Cb != nullptr) {
+          if (bias) v += bias[n];
+          if (relu) v = fmaxf(v, 0.f);
+          Cb[long(m) * scm + long(n) * scn] = f2bf(v);
+        } else {
+          Cf[long(blockIdx.z) * cpart + long(m) * scm + long(n) * scn] = v;
+        }
+      }
+}
+
+// out[i] (+)= sum_z part[z][i], fixed order
+__global__ void k_splitk_sum(const float* __restrict__ part, long cpart, int splits, long n,
+                             float* __restrict__ out, int accumulate) {
+  for (long i = long(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += long(gridDim.x) * blockDim.x) {
+    float s = 0.f;
+    for (int z = 0; z < splits; ++z) s += part[z * cpart + i];
+    out[i] = accumulate ? out[i] + s : s;
+  }
+}
+
+// Col[m][tap C + ch], C = c1 + c2, over the fine grid (nb, Z, Y, X); ch < c1 from in1 (read at
+// half resolution when up1), ch >= c1 from in2; zero padding.
+__global__ void k_im2col(const u16* __restrict__ in1, int c1, int up1, const u16* __restrict__ in2,
+                         int c2, int nb, int Z, int Y, int X, int taps, u16* __restrict__ col) {
+  const int C = c1 + c2;
+  const long M = long(nb) * Z * Y * X;
+  const long total = M * taps * C;
+  for (long i = long(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+       i += long(gridDim.x) * blockDim.x) {
+    const int ch = int(i % C);
+    const int tap = int((i / C) % taps);
+    const long m = i / (long(C) * taps);
+    int x = int(m % X), y = int((m / X) % Y), z = int((m / (long(X) * Y)) % Z);
+    const int b = int(m / (long(X) * Y * Z));
+    if (taps == 27) {
+      z += tap / 9 - 1;
+      y += (tap / 3) % 3 - 1;
+      x += tap % 3 - 1;
+    }
+    u16 v = 0;
+    if (z >= 0 && z < Z && y >= 0 && y < Y && x >= 0 && x < X) {
+      if (ch < c1) {
+        if (up1)
+          v = in1[(((long(b) * (Z / 2) + z / 2) * (Y / 2) + y / 2) * (X / 2) + x / 2) * c1 + ch];
+        else
+          v = in1[(((long(b) * Z + z) * Y + y) * X + x) * c1 + ch];
+      } else {
+        v = in2[(((long(b) * Z + z) * Y + y) * X + x) * c2 + (ch - c1)];
+      }
+    }
+    col[i] = v;
+  }
+}
+
+// Gather-form col2im of dCol [M][taps C] (float32): gradient of the input channels
+// [ch0, ch0 + cn) at every fine-grid position, written (or added) to d [M][cn] (float32); with
+// down = 1 the fine-grid gradient is summed over the 8 children of each coarse cell (adjoint of
+// nearest upsampling) and d is [nb Z/2 Y/2 X/2][cn].
+__global__ void k_col2im(const float* __restrict__ dcol, int C, int ch0, int cn, int nb, int Z,
+                         int Y, int X, int taps, int down, float* __restrict__ d, int accumulate) {
+  const int Zc = down ? Z / 2 : Z, Yc = down ? Y / 2 : Y, Xc = down ? X / 2 : X;
+  const long total = long(nb) * Zc * Yc * Xc * cn;
+  for (long i = long(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+       i += long(gridDim.x) * blockDim.x) {
+    const int ch = int(i % cn);
+    const long p = i / cn;
+    const int xc = int(p % Xc), yc = int((p / Xc) % Yc), zc = int((p / (long(Xc) * Yc)) % Zc);
+    const int b = int(p / (long(Xc) * Yc * Zc));
+    float s = 0.f;
+    const int nch = down ? 8 : 1;
+    for (int q = 0; q < nch; ++q) {
+      const int z = down ? 2 * zc + (q >> 2) : zc;
+      const int y = down ? 2 * yc + ((q >> 1) & 1) : yc;
+      const int x = down ? 2 * xc + (q & 1) : xc;
+      for (int tap = 0; tap < taps; ++tap) {
+        int zz = z, yy = y, xx = x;
+        if (taps == 27) {
+          zz -= tap / 9 - 1;
+          yy -= (tap / 3) % 3 - 1;
+          xx -= tap % 3 - 1;
+        }
+        if (zz < 0 || zz >= Z || yy < 0 || yy >= Y || xx < 0 || xx >= X) continue;
+        const long m = ((long(b) * Z + zz) * Y + yy) * X + xx;
+        s += dcol[(m * taps + tap) * C + ch0 + ch];
+      }
+    }
+    d[i] = accumulate ? d[i] + s : s;
+  }
+}
+
+__global__ void k_pool(const u16* __restrict__ in, int c, int nb, int Z, int Y, int X,
+                       u16* __restrict__ out) {
+  const long total = long(nb) * (Z / 2) * (Y / 2) * (X / 2) * c;
+  for (long i = long(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+       i += long(gridDim.x) * blockDim.x) {
+    const int ch = int(i % c);
+    const long p = i / c;
+    const int X2 = X / 2, Y2 = Y / 2, Z2 = Z / 2;
+    const int x = int(p % X2), y = int((p / X2) % Y2), z = int((p / (long(X2) * Y2)) % Z2);
+    const int b = int(p / (long(X2) * Y2 * Z2));
+    float s = 0.f;
+    for (int q = 0; q < 8; ++q)
+      s += bf2f(in[(((long(b) * Z + 2 * z + (q >> 2)) * Y + 2 * y + ((q >> 1) & 1)) * X + 2 * x +
+                    (q & 1)) * c + ch]);
+    out[i] = f2bf(s * 0.125f);
+  }
+}
+
+// d_fine (+)= d_coarse / 8 (adjoint of 2x2x2 averaging), float32
+__global__ void k_pool_back(const float* __restrict__ dc, int c, int nb, int Z, int Y, int X,
+                            float* __restrict__ df, int accumulate) {
+  const long total = long(nb) * Z * Y * X * c;
+  for (long i = long(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+       i += long(gridDim.x) * blockDim.x) {
+    const int ch = int(i % c);
+    const long p = i / c;
+    const int x = int(p % X), y = int((p / X) % Y), z = int((p / (long(X) * Y)) % Z);
+    const int b = int(p / (long(X) * Y * Z));
+    const float v =
+        0.125f * dc[(((long(b) * (Z / 2) + z / 2) * (Y / 2) + y / 2) * (X / 2) + x / 2) * c + ch];
+    df[i] = accumulate ? df[i] + v : v;
+  }
+}
+
+// g16 = bf16(relu ? (out > 0 ? g : 0) : g), and the masked float gradient kept for the bias
+__global__ void k_relu_cast(const float* __restrict__ g, const u16* __restrict__ out, int relu,
+                            long n, u16* __restrict__ g16, float* __restrict__ gm) {
+  for (long i = long(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += long(gridDim.x) * blockDim.x) {
+    float v = g[i];
+    if (relu && !(bf2f(out[i]) > 0.f)) v = 0.f;
+    g16[i] = f2bf(v);
+    gm[i] = v;
+  }
+}
+
+// column sums (bias gradient): out[n] (+)= sum_m g[m][n]; one block per column, fixed order
+__global__ void __launch_bounds__(256) k_colsum(const float* __restrict__ g, long M, int N,
+                                                float* __restrict__ out) {
+  __shared__ float sh[256];
+  const int n = blockIdx.x;
+  float s = 0.f;
+  for (long m = threadIdx.x; m < M; m += 256) s += g[m * N + n];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[n] = sh[0];
+}
+
+// MSE: per-block partial sums of (y - t)^2 and the gradient 2 (y - t) / n
+__global__ void __launch_bounds__(256) k_mse(const float* __restrict__ y, const float* __restrict__ t,
+                                             long n, float* __restrict__ grad,
+                                             double* __restrict__ part) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (long i = long(blockIdx.x) * 256 + threadIdx.x; i < n; i += long(gridDim.x) * 256) {
+    const float d = y[i] - t[i];
+    grad[i] = 2.f * d / float(n);
+    s += double(d) * double(d);
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, u16* __restrict__ p16, long n, float lr, float b1,
+                       float b2, float eps, float c1, float c2) {
+  for (long i = long(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += long(gridDim.x) * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    p[i] = pi;
+    p16[i] = f2bf(pi);
+  }
+}
+
+__global__ void k_to_bf16(const float* __restrict__ a, u16* __restrict__ b, long n) {
+  for (long i = long(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += long(gridDim.x) * blockDim.x)
+    b[i] = f2bf(a[i]);
+}
+
+// Network input for one block: [dsigma / sigma0 (6), (re, im) of b / rms (6), (re, im) k0 h (2)]
+// from sigma6 (float64 [6][nz][ny][nx] view with component stride cs) and b (complex128
+// contiguous [3][nzb][ny][nx]); output BF16 channels-last [nzb][ny][nx][14].
+__global__ void k_features(const double* __restrict__ s6, long cs, const c128* __restrict__ b,
+                           long nb, double sigma0, double inv_rms, double k0h_re, double k0h_im,
+                           u16* __restrict__ x) {
+  const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  u16* o = x + i * 14;
+  for (int c = 0; c < 6; ++c) o[c] = f2bf(float((s6[c * cs + i] - (c < 3 ? sigma0 : 0.0)) / sigma0));
+  for (int c = 0; c < 3; ++c) {
+    const c128 v = b[c * nb + i];
+    o[6 + 2 * c] = f2bf(float(v.re * inv_rms));
+    o[7 + 2 * c] = f2bf(float(v.im * inv_rms));
+  }
+  o[12] = f2bf(float(k0h_re));
+  o[13] = f2bf(float(k0h_im));
+}
+
+// x0 = b + rms (y_re + i y_im) per component (the network predicts E - b, scaled by 1 / rms)
+__global__ void k_apply_guess(const c128* __restrict__ b, const float* __restrict__ y, long nb,
+                              double rms, c128* __restrict__ x0) {
+  const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  for (int c = 0; c < 3; ++c) {
+    const c128 v = b[c * nb + i];
+    x0[c * nb + i] = c128{v.re + rms * double(y[i * 6 + 2 * c]), v.im + rms * double(y[i * 6 + 2 * c + 1])};
+  }
+}
+
+// grid for the element-wise grid-stride kernels (x extent times 256 stays below 2^32)
+int grid1(long n) { return int(std::min<long>((1L << 24) - 1, (n + 255) / 256)); }
+
+}  // namespace nn
+}  // namespace ie
+
+// ---------------------------------------------------------------------------------------
+// host side: the network object
+// ---------------------------------------------------------------------------------------
+using namespace ie;
+using namespace ie::nn;
+
+struct NnLayer {
+  int ci, co, taps, relu;
+  long w_off, b_off;  // offsets into the flat parameter vector
+  // per-forward state
+  int Z = 0, Y = 0, X = 0;  // fine grid of the layer's output
+  long M = 0;
+  DevBuf col, out;   // im2col (bf16 [M][taps ci]) and output (bf16 [M][co]; head float32)
+};
+
+struct ie_nn {
+  int in_ch, out_ch, base, levels;
+  std::vector<NnLayer> L;
+  long np = 0;
+  DevBuf p32, g32, m32, v32, p16;
+  long step = 0;
+  // forward state
+  int nb = 0, Z = 0, Y = 0, X = 0;
+  DevBuf x16;                               // network input copy (bf16)
+  std::vector<DevBuf> pooled;               // pooled inputs per level >= 1
+  DevBuf gcur, gtmp, gsk[8], g16, gmask, dcol, part, mse_part, gy;
+  std::vector<double> hpart;
+};
+
+namespace {
+
+int gemm(hipStream_t s, bool akc, bool bnc, const u16* A, long sam, long sak, const u16* B,
+         long sbk, long sbn, int M, int N, int K, int splits, float* Cf, long scm, long scn,
+         long cpart, u16* Cb, const float* bias, int relu) {
+  const int kchunk = ((K + splits - 1) / splits + GBK - 1) / GBK * GBK;
+  const int z = (K + kchunk - 1) / kchunk;
+  dim3 grid(ceil_div(M, GBM), ceil_div(N, GBN), z);
+  ProfScope ps(s, "nn_gemm", "bf16", 2.0 * (double(M) * K + double(K) * N) + 4.0 * double(M) * N);
+#define IE_GEMM(AK, BN)                                                                          \
+  hipLaunchKernelGGL((k_gemm<AK, BN>), grid, dim3(256), 0, s, A, sam, sak, B, sbk, sbn, M, N, K, \
+                     kchunk, Cf, scm, scn, cpart, Cb, bias, relu)
+  if (akc && bnc)
+    IE_GEMM(true, true);
+  else if (akc)
+    IE_GEMM(true, false);
+  else if (bnc)
+    IE_GEMM(false, true);
+  else
+    IE_GEMM(false, false);
+#undef IE_GEMM
+  IE_LAUNCH_CHECK();
+  return z;
+}
+
+void build_layers(ie_nn* n) {
+  const int Lv = n->levels;
+  std::vector<int> ch(Lv);
+  for (int l = 0; l < Lv; ++l) ch[l] = n->base << l;
+  auto add = [&](int ci, int co, int taps, int relu) {
+    NnLayer y;
+    y.ci = ci;
+    y.co = co;
+    y.taps = taps;
+    y.relu = relu;
+    y.w_off = n->np;
+    n->np += long(taps) * ci * co;
+    y.b_off = n->np;
+    n->np += co;
+    n->L.push_back(std::move(y));
+  };
+  add(n->in_ch, ch[0], 27, 1);
+  add(ch[0], ch[0], 27, 1);
+  for (int l = 1; l < Lv; ++l) {
+    add(ch[l - 1], ch[l], 27, 1);
+    add(ch[l], ch[l], 27, 1);
+  }
+  for (int l = Lv - 2; l >= 0; --l) {
+    add(ch[l + 1] + ch[l], ch[l], 27, 1);
+    add(ch[l], ch[l], 27, 1);
+  }
+  add(ch[0], n->out_ch, 1, 0);
+}
+
+// conv layer forward: im2col of (in1 [upsampled], in2) then GEMM with bias / ReLU
+int conv_fwd(ie_nn* n, NnLayer& y, const u16* in1, int c1, int up1, const u16* in2, int c2,
+             int Z, int Y, int X, hipStream_t s, float* out32) {
+  y.Z = Z;
+  y.Y = Y;
+  y.X = X;
+  y.M = long(n->nb) * Z * Y * X;
+  const long K = long(y.taps) * (c1 + c2);
+  IE_TRY(y.col.ensure(sizeof(u16) * y.M * K));
+  if (!out32) IE_TRY(y.out.ensure(sizeof(u16) * y.M * y.co));
+  {
+    ProfScope ps(s, "nn_im2col", "", 2.0 * y.M * K);
+    hipLaunchKernelGGL(k_im2col, dim3(grid1(y.M * K)), dim3(256), 0, s, in1, c1, up1, in2, c2,
+                       n->nb, Z, Y, X, y.taps, y.col.as<u16>());
+    IE_LAUNCH_CHECK();
+  }
+  const u16* W = n->p16.as<u16>() + y.w_off;
+  const float* bias = n->p32.as<float>() + y.b_off;
+  if (out32) {
+    gemm(s, true, true, y.col.as<u16>(), K, 1, W, y.co, 1, int(y.M), y.co, int(K), 1, out32, y.co,
+         1, 0, nullptr, nullptr, 0);
+    // bias for the float32 head output: out += b (done by a tiny pass below)
+    return IE_OK;
+  }
+  gemm(s, true, true, y.col.as<u16>(), K, 1, W, y.co, 1, int(y.M), y.co, int(K), 1, nullptr, y.co,
+       1, 0, y.out.as<u16>(), bias, y.relu);
+  return IE_OK;
+}
+
+__global__ void k_add_bias(float* __restrict__ y, const float* __restrict__ b, long M, int N) {
+  for (long i = long(blockIdx.x) * blockDim.x + threadIdx.x; i < M * N; i += long(gridDim.x) * blockDim.x)
+    y[i] += b[i % N];
+}
+
+int forward(ie_nn* n, const u16* x, int nb, int Z, int Y, int X, float* y, hipStream_t s) {
+  if (Z % (1 << (n->levels - 1)) || Y % (1 << (n->levels - 1)) || X % (1 << (n->levels - 1)))
+    return fail(IE_EINVAL, "grid sizes must be divisible by 2^(levels-1)");
+  n->nb = nb;
+  n->Z = Z;
+  n->Y = Y;
+  n->X = X;
+  const int Lv = n->levels;
+  n->pooled.resize(Lv);
+  int k = 0;
+  std::vector<const u16*> skip(Lv);
+  std::vector<int> dims(3 * Lv);
+  for (int l = 0; l < Lv; ++l) {
+    dims[3 * l] = Z >> l;
+    dims[3 * l + 1] = Y >> l;
+    dims[3 * l + 2] = X >> l;
+  }
+  // encoder
+  const u16* h = x;
+  int hc = n->in_ch;
+  for (int l = 0; l < Lv; ++l) {
+    const int Zl = dims[3 * l], Yl = dims[3 * l + 1], Xl = dims[3 * l + 2];
+    if (l > 0) {
+      const long np_ = long(nb) * Zl * Yl * Xl * hc;
+      IE_TRY(n->pooled[l].ensure(sizeof(u16) * np_));
+      hipLaunchKernelGGL(k_pool, dim3(grid1(np_)), dim3(256), 0, s, h, hc, nb, dims[3 * l - 3],
+                         dims[3 * l - 2], dims[3 * l - 1], n->pooled[l].as<u16>());
+      IE_LAUNCH_CHECK();
+      h = n->pooled[l].as<u16>();
+    }
+    IE_TRY(conv_fwd(n, n->L[k], h, hc, 0, nullptr, 0, Zl, Yl, Xl, s, nullptr));
+    h = n->L[k].out.as<u16>();
+    hc = n->L[k].co;
+    ++k;
+    IE_TRY(conv_fwd(n, n->L[k], h, hc, 0, nullptr, 0, Zl, Yl, Xl, s, nullptr));
+    h = n->L[k].out.as<u16>();
+    hc = n->L[k].co;
+    ++k;
+    skip[l] = h;
+  }
+  // decoder
+  for (int l = Lv - 2; l >= 0; --l) {
+    const int Zl = dims[3 * l], Yl = dims[3 * l + 1], Xl = dims[3 * l + 2];
+    const int cs = n->base << l;
+    IE_TRY(conv_fwd(n, n->L[k], h, hc, 1, skip[l], cs, Zl, Yl, Xl, s, nullptr));
+    h = n->L[k].out.as<u16>();
+    hc = n->L[k].co;
+    ++k;
+    IE_TRY(conv_fwd(n, n->L[k], h, hc, 0, nullptr, 0, Zl, Yl, Xl, s, nullptr));
+    h = n->L[k].out.as<u16>();
+    hc = n->L[k].co;
+    ++k;
+  }
+  // head (float32 output)
+  NnLayer& hd = n->L[k];
+  IE_TRY(conv_fwd(n, hd, h, hc, 0, nullptr, 0, Z, Y, X, s, y));
+  hipLaunchKernelGGL(k_add_bias, dim3(grid1(hd.M * hd.co)), dim3(256), 0, s, y,
+                     n->p32.as<float>() + hd.b_off, hd.M, hd.co);
+  IE_LAUNCH_CHECK();
+  return IE_OK;
+}
+
+// Backward of one conv layer from the float32 gradient of its output (gout); writes parameter
+// gradients (accumulated) and returns the float32 gradient of the im2col input (dcol) for the
+// caller's col2im.
+int conv_back(ie_nn* n, NnLayer& y, const float* gout, int cin, hipStream_t s) {
+  const long K = long(y.taps) * cin;
+  const long MN = y.M * y.co;
+  IE_TRY(n->g16.ensure(sizeof(u16) * MN));
+  IE_TRY(n->gmask.ensure(sizeof(float) * MN));
+  // relu mask (the head has none) and BF16 copy
+  hipLaunchKernelGGL(k_relu_cast, dim3(grid1(MN)), dim3(256), 0, s, gout,
+                     y.relu ? y.out.as<u16>() : nullptr, y.relu, MN, n->g16.as<u16>(),
+                     n->gmask.as<float>());
+  IE_LAUNCH_CHECK();
+  // bias gradient
+  hipLaunchKernelGGL(k_colsum, dim3(y.co), dim3(256), 0, s, n->gmask.as<float>(), y.M, y.co,
+                     n->g32.as<float>() + y.b_off);
+  IE_LAUNCH_CHECK();
+  // weight gradient dW[K][co] = Col^T g16, split over the spatial dimension
+  const int splits = int(std::max<long>(1, std::min<long>(256, y.M / 2048)));
+  const long cpart = K * y.co;
+  IE_TRY(n->part.ensure(sizeof(float) * cpart * splits));
+  const int z = gemm(s, false, true, y.col.as<u16>(), 1, K, n->g16.as<u16>(), y.co, 1, int(K),
+                     y.co, int(y.M), splits, n->part.as<float>(), y.co, 1, cpart, nullptr, nullptr, 0);
+  hipLaunchKernelGGL(k_splitk_sum, dim3(grid1(cpart)), dim3(256), 0, s, n->part.as<float>(), cpart,
+                     z, cpart, n->g32.as<float>() + y.w_off, 0);
+  IE_LAUNCH_CHECK();
+  // input gradient through the transposed weights: dCol[M][K] = g16 W^T
+  IE_TRY(n->dcol.ensure(sizeof(float) * y.M * K));
+  const u16* W = n->p16.as<u16>() + y.w_off;
+  gemm(s, true, false, n->g16.as<u16>(), y.co, 1, W, 1, y.co, int(y.M), int(K), y.co, 1,
+       n->dcol.as<float>(), K, 1, 0, nullptr, nullptr, 0);
+  return IE_OK;
+}
+
+int col2im(ie_nn* n, const NnLayer& y, int C, int ch0, int cn, int down, float* d, int acc,
+           hipStream_t s) {
+  const long tot = (down ? y.M / 8 : y.M) * cn;
+  hipLaunchKernelGGL(k_col2im, dim3(grid1(tot)), dim3(256), 0, s, n->dcol.as<float>(), C, ch0, cn,
+                     n->nb, y.Z, y.Y, y.X, y.taps, down, d, acc);
+  IE_LAUNCH_CHECK();
+  return IE_OK;
+}
+
+// Backward through the whole network from gy = dLoss/dy (float32, [M][out]); parameter
+// gradients land in g32 (overwritten).
+int backward(ie_nn* n, const float* gy, hipStream_t s) {
+  const int Lv = n->levels;
+  IE_HIP(hipMemsetAsync(n->g32.p, 0, sizeof(float) * n->np, s));
+  long maxa = 0;
+  for (auto& y : n->L) maxa = std::max(maxa, y.M * std::max(y.ci, y.co));
+  IE_TRY(n->gcur.ensure(sizeof(float) * maxa));
+  IE_TRY(n->gtmp.ensure(sizeof(float) * maxa));
+  for (int l = 0; l < Lv; ++l) IE_TRY(n->gsk[l].ensure(sizeof(float) * maxa));
+  float* A = n->gcur.as<float>();
+  float* Bf = n->gtmp.as<float>();
+  auto tmp = [&](const float* busy) { return busy == A ? Bf : A; };
+  int k = int(n->L.size()) - 1;
+  float* gc = A;
+  {  // head
+    NnLayer& y = n->L[k--];
+    IE_TRY(conv_back(n, y, gy, y.ci, s));
+    IE_TRY(col2im(n, y, y.ci, 0, y.ci, 0, gc, 0, s));
+  }
+  // decoder: forward order l = L-2 .. 0, so backward visits l = 0 .. L-2
+  for (int l = 0; l <= Lv - 2; ++l) {
+    NnLayer& yb = n->L[k--];
+    IE_TRY(conv_back(n, yb, gc, yb.ci, s));
+    float* t = tmp(gc);
+    IE_TRY(col2im(n, yb, yb.ci, 0, yb.ci, 0, t, 0, s));
+    gc = t;
+    NnLayer& ya = n->L[k--];
+    const int cu = n->base << (l + 1), cs = n->base << l;
+    IE_TRY(conv_back(n, ya, gc, ya.ci, s));
+    IE_TRY(col2im(n, ya, cu + cs, cu, cs, 0, n->gsk[l].as<float>(), 0, s));  // skip channels
+    t = tmp(gc);
+    IE_TRY(col2im(n, ya, cu + cs, 0, cu, 1, t, 0, s));  // upsampled channels -> coarse level
+    gc = t;
+  }
+  // encoder: l = L-1 .. 0; gc holds the gradient of level l's output
+  for (int l = Lv - 1; l >= 0; --l) {
+    NnLayer& yb = n->L[k--];
+    IE_TRY(conv_back(n, yb, gc, yb.ci, s));
+    float* t = tmp(gc);
+    IE_TRY(col2im(n, yb, yb.ci, 0, yb.ci, 0, t, 0, s));
+    gc = t;
+    NnLayer& ya = n->L[k--];
+    IE_TRY(conv_back(n, ya, gc, ya.ci, s));
+    if (l == 0) break;  // no gradient for the network input
+    t = tmp(gc);
+    IE_TRY(col2im(n, ya, ya.ci, 0, ya.ci, 0, t, 0, s));  // w.r.t. the pooled input of level l
+    const NnLayer& prev = n->L[k];                        // second conv of level l-1
+    hipLaunchKernelGGL(k_pool_back, dim3(grid1(prev.M * prev.co)), dim3(256), 0, s, t, prev.co,
+                       n->nb, prev.Z, prev.Y, prev.X, n->gsk[l - 1].as<float>(), 1);
+    IE_LAUNCH_CHECK();
+    gc = n->gsk[l - 1].as<float>();  // skip contribution + pooling adjoint
+  }
+  return IE_OK;
+}
+
+int check_nn(const ie_nn* n) {
+  if (n == nullptr) return fail(IE_EINVAL, "network handle is NULL");
+  return IE_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+// C entry points
+// ---------------------------------------------------------------------------------------
+extern "C" {
+
+int ie_nn_create(const ie_nn_config* cfg, void* stream, ie_nn** out) {
+  if (cfg == nullptr || out == nullptr) return fail(IE_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (cfg->in_ch < 1 || cfg->out_ch < 1 || cfg->base_ch < 1 || cfg->levels < 1 || cfg->levels > 6)
+    return fail(IE_EINVAL, "bad network configuration");
+  auto n = std::make_unique<ie_nn>();
+  n->in_ch = cfg->in_ch;
+  n->out_ch = cfg->out_ch;
+  n->base = cfg->base_ch;
+  n->levels = cfg->levels;
+  build_layers(n.get());
+  // He-normal weights (seeded), zero biases
+  std::vector<float> h(n->np, 0.f);
+  std::mt19937_64 rng(cfg->seed);
+  std::normal_distribution<double> nd(0.0, 1.0);
+  for (auto& y : n->L) {
+    const double sd = std::sqrt(2.0 / (double(y.taps) * y.ci));
+    for (long i = 0; i < long(y.taps) * y.ci * y.co; ++i) h[y.w_off + i] = float(sd * nd(rng));
+  }
+  IE_TRY(n->p32.ensure(sizeof(float) * n->np));
+  IE_TRY(n->g32.ensure(sizeof(float) * n->np));
+  IE_TRY(n->m32.ensure(sizeof(float) * n->np));
+  IE_TRY(n->v32.ensure(sizeof(float) * n->np));
+  IE_TRY(n->p16.ensure(sizeof(u16) * n->np));
+  hipStream_t s = (hipStream_t)stream;
+  IE_HIP(hipMemcpyAsync(n->p32.p, h.data(), sizeof(float) * n->np, hipMemcpyHostToDevice, s));
+  IE_HIP(hipMemsetAsync(n->m32.p, 0, sizeof(float) * n->np, s));
+  IE_HIP(hipMemsetAsync(n->v32.p, 0, sizeof(float) * n->np, s));
+  hipLaunchKernelGGL(k_to_bf16, dim3(grid1(n->np)), dim3(256), 0, s, n->p32.as<float>(),
+                     n->p16.as<u16>(), n->np);
+  IE_LAUNCH_CHECK();
+  IE_HIP(hipStreamSynchronize(s));
+  *out = n.release();
+  return IE_OK;
+}
+
+int ie_nn_destroy(ie_nn* n) {
+  if (n == nullptr) return IE_OK;
+  (void)hipDeviceSynchronize();
+  delete n;
+  return IE_OK;
+}
+
+int ie_nn_num_params(const ie_nn* n, int64_t* count) {
+  IE_TRY(check_nn(n));
+  if (count == nullptr) return fail(IE_EINVAL, "count is NULL");
+  *count = n->np;
+  return IE_OK;
+}
+
+int ie_nn_get_params(const ie_nn* n, float* host, int64_t count, int32_t which) {
+  IE_TRY(check_nn(n));
+  if (host == nullptr || count != n->np) return fail(IE_EINVAL, "need a host array of %ld floats", n->np);
+  const DevBuf& b = which == 1 ? n->g32 : n->p32;
+  IE_HIP(hipDeviceSynchronize());
+  IE_HIP(hipMemcpy(host, b.p, sizeof(float) * n->np, hipMemcpyDeviceToHost));
+  return IE_OK;
+}
+
+int ie_nn_set_params(ie_nn* n, const float* host, int64_t count) {
+  IE_TRY(check_nn(n));
+  if (host == nullptr || count != n->np) return fail(IE_EINVAL, "need a host array of %ld floats", n->np);
+  IE_HIP(hipDeviceSynchronize());
+  IE_HIP(hipMemcpy(n->p32.p, host, sizeof(float) * n->np, hipMemcpyHostToDevice));
+  hipLaunchKernelGGL(k_to_bf16, dim3(grid1(n->np)), dim3(256), 0, 0, n->p32.as<float>(),
+                     n->p16.as<u16>(), n->np);
+  IE_LAUNCH_CHECK();
+  IE_HIP(hipDeviceSynchronize());
+  n->step = 0;
+  IE_HIP(hipMemset(n->m32.p, 0, sizeof(float) * n->np));
+  IE_HIP(hipMemset(n->v32.p, 0, sizeof(float) * n->np));
+  return IE_OK;
+}
+
+int ie_nn_forward(ie_nn* n, const uint16_t* x, int32_t batch, int32_t nz, int32_t ny, int32_t nx,
+                  float* y, void* stream) {
+  IE_TRY(check_nn(n));
+  if (x == nullptr || y == nullptr || batch < 1 || nz < 1 || ny < 1 || nx < 1)
+    return fail(IE_EINVAL, "bad forward arguments");
+  return forward(n, x, batch, nz, ny, nx, y, (hipStream_t)stream);
+}
+
+int ie_nn_backward(ie_nn* n, const uint16_t* x, const float* dy, int32_t batch, int32_t nz,
+                   int32_t ny, int32_t nx, float* y, void* stream) {
+  IE_TRY(check_nn(n));
+  if (x == nullptr || dy == nullptr || y == nullptr) return fail(IE_EINVAL, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  IE_TRY(forward(n, x, batch, nz, ny, nx, y, s));
+  return backward(n, dy, s);
+}
+
+int ie_nn_train_step(ie_nn* n, const uint16_t* x, const float* target, int32_t batch, int32_t nz,
+                     int32_t ny, int32_t nx, float lr, float* loss, void* stream) {
+  IE_TRY(check_nn(n));
+  if (x == nullptr || target == nullptr || !(lr > 0)) return fail(IE_EINVAL, "bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  const long cnt = long(batch) * nz * ny * nx * n->out_ch;
+  IE_TRY(n->gy.ensure(sizeof(float) * 2 * cnt));
+  float* y = n->gy.as<float>();
+  float* g = y + cnt;
+  IE_TRY(forward(n, x, batch, nz, ny, nx, y, s));
+  const int nbk = 256;
+  IE_TRY(n->mse_part.ensure(sizeof(double) * nbk));
+  hipLaunchKernelGGL(k_mse, dim3(nbk), dim3(256), 0, s, y, target, cnt, g,
+                     n->mse_part.as<double>());
+  IE_LAUNCH_CHECK();
+  IE_TRY(backward(n, g, s));
+  n->step += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.f - std::pow(b1, float(n->step)), c2 = 1.f - std::pow(b2, float(n->step));
+  hipLaunchKernelGGL(k_adam, dim3(grid1(n->np)), dim3(256), 0, s, n->p32.as<float>(),
+                     n->g32.as<float>(), n->m32.as<float>(), n->v32.as<float>(), n->p16.as<u16>(),
+                     n->np, lr, b1, b2, 1e-8f, c1, c2);
+  IE_LAUNCH_CHECK();
+  if (loss != nullptr) {
+    n->hpart.resize(nbk);
+    IE_HIP(hipMemcpyAsync(n->hpart.data(), n->mse_part.p, sizeof(double) * nbk,
+                          hipMemcpyDeviceToHost, s));
+    IE_HIP(hipStreamSynchronize(s));
+    double t = 0;
+    for (double v : n->hpart) t += v;
+    *loss = float(t / double(cnt));
+  }
+  return IE_OK;
+}
+
+int ie_nn_gemm(const uint16_t* A, const uint16_t* B, float* Cm, int32_t M, int32_t N, int32_t K,
+               int32_t a_trans, int32_t b_trans, int32_t splits, void* stream) {
+  if (A == nullptr || B == nullptr || Cm == nullptr || M < 1 || N < 1 || K < 1 || splits < 1 ||
+      splits > 64)
+    return fail(IE_EINVAL, "bad GEMM arguments");
+  hipStream_t s = (hipStream_t)stream;
+  const long sam = a_trans ? 1 : K, sak = a_trans ? M : 1;
+  const long sbk = b_trans ? 1 : N, sbn = b_trans ? K : 1;
+  const long cpart = long(M) * N;
+  DevBuf part;
+  IE_TRY(part.ensure(sizeof(float) * cpart * splits));
+  const int z = gemm(s, !a_trans, !b_trans, A, sam, sak, B, sbk, sbn, M, N, K, splits,
+                     part.as<float>(), N, 1, cpart, nullptr, nullptr, 0);
+  hipLaunchKernelGGL(k_splitk_sum, dim3(grid1(cpart)), dim3(256), 0, s, part.as<float>(), cpart, z,
+                     cpart, Cm, 0);
+  IE_LAUNCH_CHECK();
+  IE_HIP(hipStreamSynchronize(s));
+  return IE_OK;
+}
+
+}  // extern "C"
+
+namespace ie {
+
+// Learned guesses for `batch` blocks: x0 = b + rms (network output) with the block features;
+// then, per block, keep whichever of x0 and the default guess xdef has the smaller residual
+// ||b - A x|| (one float64 operator application each).  accepted[b] = 1 if x0 was kept.
+int nn_guess_blocks(ie_nn* n, ie_ctx* c, Plan& B, const double* sigma6, long s_cs, long s_bs,
+                    const c128* rhs, c128* x, int batch, const OpDesc& op, int* accepted,
+                    hipStream_t s) {
+  const long nb = B.ncell();
+  std::vector<double> bn(batch);
+  IE_TRY(norms_host(rhs, 3 * nb, batch, bn.data(), c->kw_blk, s));
+  IE_TRY(n->x16.ensure(sizeof(u16) * 14 * nb * batch));
+  const double h = c->grid.h;
+  for (int b = 0; b < batch; ++b) {
+    const double rms = bn[b] / std::sqrt(3.0 * double(nb));
+    hipLaunchKernelGGL(k_features, dim3(ceil_div(nb, 256)), dim3(256), 0, s, sigma6 + b * s_bs,
+                       s_cs, rhs + b * 3 * nb, nb, c->med.sigma0, rms > 0 ? 1.0 / rms : 0.0,
+                       c->med.k0re * h, c->med.k0im * h, n->x16.as<u16>() + b * 14 * nb);
+    IE_LAUNCH_CHECK();
+  }
+  DevBuf y32, xg, r;
+  IE_TRY(y32.ensure(sizeof(float) * 6 * nb * batch));
+  IE_TRY(forward(n, n->x16.as<u16>(), batch, B.nz, B.ny, B.nx, y32.as<float>(), s));
+  IE_TRY(xg.ensure(sizeof(c128) * 3 * nb * batch));
+  IE_TRY(r.ensure(sizeof(c128) * 3 * nb * batch));
+  for (int b = 0; b < batch; ++b) {
+    const double rms = bn[b] / std::sqrt(3.0 * double(nb));
+    hipLaunchKernelGGL(k_apply_guess, dim3(ceil_div(nb, 256)), dim3(256), 0, s,
+                       rhs + b * 3 * nb, y32.as<float>() + b * 6 * nb, nb, rms,
+                       xg.as<c128>() + b * 3 * nb);
+    IE_LAUNCH_CHECK();
+  }
+  // judge: residual of the learned guess vs the default guess (conventional operator)
+  std::vector<double> rl(batch), rd(batch);
+  IE_TRY(apply_op<double>(B, op, xg.as<c128>(), r.as<c128>(), rhs, true, batch, nullptr, 0, s,
+                          tw64(c)));
+  IE_TRY(norms_host(r.as<c128>(), 3 * nb, batch, rl.data(), c->kw_blk, s));
+  IE_TRY(apply_op<double>(B, op, x, r.as<c128>(), rhs, true, batch, nullptr, 0, s, tw64(c)));
+  IE_TRY(norms_host(r.as<c128>(), 3 * nb, batch, rd.data(), c->kw_blk, s));
+  for (int b = 0; b < batch; ++b) {
+    accepted[b] = rl[b] < rd[b];
+    if (accepted[b])
+      IE_HIP(hipMemcpyAsync(x + b * 3 * nb, xg.as<c128>() + b * 3 * nb, sizeof(c128) * 3 * nb,
+                            hipMemcpyDeviceToDevice, s));
+  }
+  IE_HIP(hipStreamSynchronize(s));
+  return IE_OK;
+}
+
+}  // namespace ie
+
+extern "C" int ie_nn_guess(ie_ctx* ctx, ie_nn* n, const double* sigma6, const void* b, void* x,
+                           int32_t* accepted, void* stream) {
+  if (ctx == nullptr || n == nullptr || sigma6 == nullptr || b == nullptr || x == nullptr)
+    return fail(IE_EINVAL, "NULL argument");
+  if (n->in_ch != 14 || n->out_ch != 6)
+    return fail(IE_EINVAL, "the network must map 14 feature channels to 6 field channels");
+  hipStream_t s = (hipStream_t)stream;
+  Plan& F = *ctx->full;
+  IE_TRY(prepare_contrast(ctx, sigma6, IE_CONVENTIONAL, s));
+  OpDesc op;
+  op.form = IE_CONVENTIONAL;
+  op.M64 = ctx->M64.as<const double>();
+  op.M_cs = F.ncell();
+  op.M_bs = 6 * F.ncell();
+  int acc = 0;
+  IE_TRY(nn_guess_blocks(n, ctx, F, sigma6, F.ncell(), 6 * F.ncell(), (const c128*)b, (c128*)x, 1,
+                         op, &acc, s));
+  if (accepted) *accepted = acc;
+  return IE_OK;
+}

@@ -77,6 +77,11 @@ class ie_kernel_stat(C.Structure):
                 ("min_ms", C.c_double), ("max_ms", C.c_double), ("bytes_per_launch", C.c_double)]
 
 
+class ie_nn_config(C.Structure):
+    _fields_ = [("in_ch", C.c_int32), ("out_ch", C.c_int32), ("base_ch", C.c_int32),
+                ("levels", C.c_int32), ("seed", C.c_uint64)]
+
+
 _lib = None
 
 
@@ -101,8 +106,22 @@ def lib():
         L.ie_set_option.restype = C.c_int
         L.ie_profile_begin.argtypes = []
         L.ie_profile_end.argtypes = [C.POINTER(ie_kernel_stat), i32, C.POINTER(i32)]
+        L.ie_nn_create.argtypes = [C.POINTER(ie_nn_config), vp, C.POINTER(vp)]
+        L.ie_nn_destroy.argtypes = [vp]
+        L.ie_nn_num_params.argtypes = [vp, C.POINTER(C.c_int64)]
+        L.ie_nn_get_params.argtypes = [vp, vp, C.c_int64, i32]
+        L.ie_nn_set_params.argtypes = [vp, vp, C.c_int64]
+        L.ie_nn_forward.argtypes = [vp, vp, i32, i32, i32, i32, vp, vp]
+        L.ie_nn_backward.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp, vp]
+        L.ie_nn_train_step.argtypes = [vp, vp, vp, i32, i32, i32, i32, C.c_float,
+                                       C.POINTER(C.c_float), vp]
+        L.ie_nn_gemm.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, i32, vp]
+        L.ie_nn_guess.argtypes = [vp, vp, vp, vp, vp, C.POINTER(i32), vp]
         for f in ("ie_green_setup", "ie_ctx_destroy", "ie_background_field", "ie_matvec",
-                  "ie_gmres", "ie_dd_solve", "ie_profile_begin", "ie_profile_end"):
+                  "ie_gmres", "ie_dd_solve", "ie_profile_begin", "ie_profile_end",
+                  "ie_nn_create", "ie_nn_destroy", "ie_nn_num_params", "ie_nn_get_params",
+                  "ie_nn_set_params", "ie_nn_forward", "ie_nn_backward", "ie_nn_train_step",
+                  "ie_nn_gemm", "ie_nn_guess"):
             getattr(L, f).restype = C.c_int
         L.ie_last_error.restype = C.c_char_p
         L.ie_version.restype = C.c_char_p
@@ -241,3 +260,73 @@ def ie_profile_end(cap=256):
 
 def ie_set_option(option, value):
     return _check(lib().ie_set_option(option, value), "ie_set_option")
+
+
+# ----------------------------------------------------------------------------------------
+# learned initial guess (network); x / dy / target / y are device tensors: x bfloat16
+# channels-last [batch, nz, ny, nx, in_ch], the others float32 [batch, nz, ny, nx, out_ch]
+# ----------------------------------------------------------------------------------------
+def ie_nn_create(in_ch=14, out_ch=6, base_ch=32, levels=4, seed=0, stream=None):
+    cfg = ie_nn_config(in_ch, out_ch, base_ch, levels, seed)
+    out = C.c_void_p()
+    _check(lib().ie_nn_create(C.byref(cfg), _stream(stream), C.byref(out)), "ie_nn_create")
+    return out.value
+
+
+def ie_nn_destroy(nn):
+    return _check(lib().ie_nn_destroy(C.c_void_p(nn)), "ie_nn_destroy")
+
+
+def ie_nn_num_params(nn):
+    n = C.c_int64()
+    _check(lib().ie_nn_num_params(C.c_void_p(nn), C.byref(n)), "ie_nn_num_params")
+    return n.value
+
+
+def ie_nn_get_params(nn, which=0):
+    """float32 numpy copy: which = 0 weights, 1 gradients of the last backward."""
+    import numpy as np
+    a = np.empty(ie_nn_num_params(nn), dtype=np.float32)
+    _check(lib().ie_nn_get_params(C.c_void_p(nn), a.ctypes.data, a.size, which), "ie_nn_get_params")
+    return a
+
+
+def ie_nn_set_params(nn, params):
+    import numpy as np
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    _check(lib().ie_nn_set_params(C.c_void_p(nn), a.ctypes.data, a.size), "ie_nn_set_params")
+
+
+def ie_nn_forward(nn, x, y, stream=None):
+    b, nz, ny, nx = x.shape[:4]
+    return _check(lib().ie_nn_forward(C.c_void_p(nn), _ptr(x), b, nz, ny, nx, _ptr(y),
+                                      _stream(stream)), "ie_nn_forward")
+
+
+def ie_nn_backward(nn, x, dy, y, stream=None):
+    b, nz, ny, nx = x.shape[:4]
+    return _check(lib().ie_nn_backward(C.c_void_p(nn), _ptr(x), _ptr(dy), b, nz, ny, nx, _ptr(y),
+                                       _stream(stream)), "ie_nn_backward")
+
+
+def ie_nn_train_step(nn, x, target, lr, stream=None):
+    """One Adam step on the mean squared error; returns the loss before the step."""
+    b, nz, ny, nx = x.shape[:4]
+    loss = C.c_float()
+    _check(lib().ie_nn_train_step(C.c_void_p(nn), _ptr(x), _ptr(target), b, nz, ny, nx,
+                                  C.c_float(lr), C.byref(loss), _stream(stream)),
+           "ie_nn_train_step")
+    return loss.value
+
+
+def ie_nn_gemm(A, B, Cout, M, N, K, a_trans=0, b_trans=0, splits=1, stream=None):
+    return _check(lib().ie_nn_gemm(_ptr(A), _ptr(B), _ptr(Cout), M, N, K, a_trans, b_trans, splits,
+                                   _stream(stream)), "ie_nn_gemm")
+
+
+def ie_nn_guess(ctx, nn, sigma6, b, x, stream=None):
+    """Learned guess on the full grid; returns 1 if it replaced the default guess held in x."""
+    acc = C.c_int32(0)
+    _check(lib().ie_nn_guess(C.c_void_p(ctx), C.c_void_p(nn), _ptr(sigma6), _ptr(b), _ptr(x),
+                             C.byref(acc), _stream(stream)), "ie_nn_guess")
+    return acc.value
