@@ -66,6 +66,7 @@ extern "C" {
 #define IE_INIT_BACKGROUND 0  /* E := E0, as Alg. 1 */
 #define IE_INIT_USER       1  /* E_total holds the initial guess on entry (resume) */
 #define IE_INIT_LEARNED    2  /* first-sweep block guesses from a trained network (ie_nn_*) */
+#define IE_INIT_ZERO       3  /* E := 0 (first sweep: zero coupling and zero block starts) */
 
 /* source kinds */
 #define IE_MAG_DIPOLE   0   /* magnetic dipole, J^H = i omega mu0 m delta (eq. 1) */
@@ -161,8 +162,8 @@ typedef struct ie_ctx ie_ctx;
  *   precision_mask: IE_FP64 | IE_MIXED - which spectra to keep (complex128, complex64).
  *   stream        : work is queued on it; the call synchronises before returning.
  *   out           : receives the new context (NULL on error).
- * Memory: about 6 (nx+1)(ny+1)(nz+1) complex values per spectrum (octant storage) plus
- * padded work buffers of about 30 nx ny nz complex values per precision.
+ * Memory: about 12 nx (ny+1)(nz+1) complex values per spectrum (all kx, half of ky and kz)
+ * plus padded work buffers of about 30 nx ny nz complex values per precision.
  */
 int ie_green_setup(const ie_grid* grid, const ie_medium* medium, const ie_partition* partition,
                    int32_t precision_mask, void* stream, ie_ctx** out);
@@ -281,10 +282,24 @@ int ie_nn_train_step(ie_nn* nn, const uint16_t* x, const float* target, int32_t 
 int ie_nn_gemm(const uint16_t* A, const uint16_t* B, float* C, int32_t M, int32_t N, int32_t K,
                int32_t a_trans, int32_t b_trans, int32_t splits, void* stream);
 /*
- * Learned initial guess for (I - G dsigma) x = b on the context's full grid: features from
- * sigma6 and b, the network, x_nn = b + rms(b) * output; x (DEVICE complex128, in: default guess,
- * out: chosen guess) is replaced by x_nn only if ||b - A x_nn|| < ||b - A x|| (float64).
- * accepted (HOST, nullable) reports the choice.  Synchronises with `stream`.
+ * Solver features and targets on the context's full grid (nx*ny*nz = N cells).
+ * ie_nn_features: x (DEVICE BF16 [N][14]) from sigma6 (DEVICE float64 [6][N]) and the
+ * right-hand side b (DEVICE complex128 [3][N]): channels 0-5 the contraction-form tensor
+ * I - 2 sigma0 (sigma + sigma0 I)^-1 (xx, yy, zz, xy, xz, yz), 6-11 re/im of b / rms(b) for
+ * x, y, z, 12-13 re/im of k0 h; rms(b) = ||b|| / sqrt(3N) goes to *rms (HOST, nullable).
+ * ie_nn_target: y (DEVICE float32 [N][6]) = re/im of (E - b) / rms(b).
+ * Both synchronise with `stream`.
+ */
+int ie_nn_features(ie_ctx* ctx, const double* sigma6, const void* b, uint16_t* x, double* rms,
+                   void* stream);
+int ie_nn_target(ie_ctx* ctx, const void* b, const void* E, float* y, void* stream);
+/*
+ * Learned initial guess for (I - G dsigma) x = b on the context's full grid:
+ * x_nn = b + rms(b) * network(features).  x (DEVICE complex128, in: default guess, out: chosen
+ * guess) becomes whichever of x_nn, the default guess and zero has the smallest float64
+ * residual ||b - (I - G dsigma) x||; *accepted (HOST, nullable) = 1 learned, 0 default, 2 zero.
+ * ie_dd_solve with init = IE_INIT_LEARNED applies the same choice to every block of the first
+ * sweep (the network must then divide each block's grid).  Synchronises with `stream`.
  */
 int ie_nn_guess(ie_ctx* ctx, ie_nn* nn, const double* sigma6, const void* b, void* x,
                 int32_t* accepted, void* stream);
@@ -293,10 +308,22 @@ int ie_nn_guess(ie_ctx* ctx, ie_nn* nn, const double* sigma6, const void* b, voi
  * Library options (process-wide).
  *   IE_OPT_GRAPHS: 1 (default) replays each Krylov restart cycle as a captured hipGraph; 0 issues
  *                  every kernel launch directly (the launch profiler always uses direct launches).
+ *   IE_OPT_AUTOTUNE: 1 (default) makes ie_green_setup time the launch variants of each FFT pass
+ *                  (values per thread, columns or rows per block) on every grid it builds and keep
+ *                  the fastest (cached per device, precision and grid for the process); 0 uses
+ *                  the default variant.  Affects contexts set up afterwards.
  * Returns IE_EINVAL for an unknown option or value.
  */
 #define IE_OPT_GRAPHS 1
+#define IE_OPT_AUTOTUNE 2
 int ie_set_option(int32_t option, int32_t value);
+
+/*
+ * The autotuner's decisions for a context as JSON text in buf (HOST, len bytes): one object per
+ * (grid, precision, pass) with the chosen variant and the measured microseconds per variant.
+ * IE_EINVAL if buf is too small.
+ */
+int ie_ctx_tuning(const ie_ctx* ctx, char* buf, int32_t len);
 
 /* Description of the last error on this thread (never NULL). */
 const char* ie_last_error(void);

@@ -125,6 +125,10 @@ static std::unique_ptr<Plan> make_plan(int nx, int ny, int nz) {
 
 using namespace ie;
 
+namespace {
+bool g_autotune = true;
+}  // namespace
+
 extern "C" {
 
 const char* ie_last_error(void) { return g_err.c_str(); }
@@ -135,6 +139,11 @@ int ie_set_option(int32_t option, int32_t value) {
   if (option == IE_OPT_GRAPHS) {
     if (value != 0 && value != 1) return fail(IE_EINVAL, "IE_OPT_GRAPHS takes 0 or 1");
     g_use_graphs = value != 0;
+    return IE_OK;
+  }
+  if (option == IE_OPT_AUTOTUNE) {
+    if (value != 0 && value != 1) return fail(IE_EINVAL, "IE_OPT_AUTOTUNE takes 0 or 1");
+    g_autotune = value != 0;
     return IE_OK;
   }
   return fail(IE_EINVAL, "unknown option %d", option);
@@ -196,16 +205,46 @@ int ie_green_setup(const ie_grid* grid, const ie_medium* medium, const ie_partit
   }
   c->full = make_plan(grid->nx, grid->ny, grid->nz);
   IE_TRY(build_green(*c->full, grid->h, m, precision_mask, tw64(c.get()), tw32(c.get()), s));
+  if (g_autotune)
+    IE_TRY(autotune(*c->full, precision_mask, tw64(c.get()), tw32(c.get()), s));
   if (partition != nullptr) {
     for (size_t i = 0; i + 1 < c->zb.size(); ++i) {
       const int nzb = c->zb[i + 1] - c->zb[i];
       if (c->blocks.count(nzb)) continue;
       auto p = make_plan(grid->nx, grid->ny, nzb);
       IE_TRY(build_green(*p, grid->h, m, precision_mask, tw64(c.get()), tw32(c.get()), s));
+      if (g_autotune) IE_TRY(autotune(*p, precision_mask, tw64(c.get()), tw32(c.get()), s));
       c->blocks[nzb] = std::move(p);
     }
   }
   *out = c.release();
+  return IE_OK;
+}
+
+int ie_ctx_tuning(const ie_ctx* ctx, char* buf, int32_t len) {
+  if (ctx == nullptr || buf == nullptr || len < 1) return fail(IE_EINVAL, "bad arguments");
+  static const char* pass_names[5] = {"xfwd", "yfwd", "zconv", "yinv", "xinv"};
+  std::string o = "[";
+  auto plan = [&](const Plan& p) {
+    for (int pi = 0; pi < 2; ++pi) {
+      if (!(ctx->prec_mask & (pi == 0 ? IE_FP64 : IE_MIXED))) continue;
+      for (int q = 0; q < 5; ++q) {
+        char t[256];
+        snprintf(t, sizeof(t),
+                 "%s{\"grid\": [%d, %d, %d], \"precision\": \"%s\", \"pass\": \"%s\", "
+                 "\"variant\": %d, \"us\": [%.2f, %.2f, %.2f, %.2f]}",
+                 o.size() > 1 ? ", " : "", p.nx, p.ny, p.nz, pi == 0 ? "c128" : "c64",
+                 pass_names[q], p.var[pi][q], p.tune_us[pi][q][0], p.tune_us[pi][q][1],
+                 p.tune_us[pi][q][2], p.tune_us[pi][q][3]);
+        o += t;
+      }
+    }
+  };
+  plan(*ctx->full);
+  for (const auto& kv : ctx->blocks) plan(*kv.second);
+  o += "]";
+  if (int(o.size()) + 1 > len) return fail(IE_EINVAL, "buffer needs %zu bytes", o.size() + 1);
+  std::memcpy(buf, o.c_str(), o.size() + 1);
   return IE_OK;
 }
 

@@ -43,17 +43,21 @@ struct DevBuf {
   T* as() const { return static_cast<T*>(p); }
 };
 
-// FFT geometry, octant spectra and padded work buffers of one grid shape.
+// FFT geometry, the stored part of the spectra and padded work buffers of one grid shape.
 struct Plan {
   int nx = 0, ny = 0, nz = 0;
   int LX = 0, LY = 0, LZ = 0;
-  DevBuf ghat64, ghat32;  // [6][LZ/2+1][LY/2+1][LX/2+1]
+  DevBuf ghat64, ghat32;  // [6][LZ/2+1][LY/2+1][LX]
   DevBuf t1_64, t2_64, t1_32, t2_32;  // padded work, capacity `cap` problems
   int cap64 = 0, cap32 = 0;
+  // launch variant per [precision: 0 float64, 1 complex64][pass: xfwd, yfwd, zconv, yinv, xinv],
+  // set by the autotuner (0 when tuning is off)
+  int8_t var[2][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
+  float tune_us[2][5][4] = {};  // measured average duration per variant (0: not measured)
   long ncell() const { return long(nx) * ny * nz; }
   long t1_elems() const { return 3L * nz * ny * LX; }
   long t2_elems() const { return 3L * nz * LY * LX; }
-  long oct_elems() const { return 6L * (LZ / 2 + 1) * (LY / 2 + 1) * (LX / 2 + 1); }
+  long spec_elems() const { return 6L * (LZ / 2 + 1) * (LY / 2 + 1) * LX; }
   int work(int prec, int batch);  // make sure work buffers hold `batch` problems
 };
 
@@ -68,8 +72,14 @@ struct ie_ctx_impl;
 
 // Operator launch: y = a_e e + a_x x - a_m M x + a_s G (M x) on plan p.
 // Fields in MvArgs that are geometry (sizes, work, ghat, tw) are filled in by the launcher.
+// only >= 0 launches that pass alone (0 xfwd, 1 yfwd, 2 zconv, 3 yinv, 4 xinv); vover >= 0
+// replaces the plan's variant (both for the autotuner).
 template <typename T>
-int launch_matvec(Plan& p, MvArgs<T> a, int batch, hipStream_t s, const cx<T>* tw);
+int launch_matvec(Plan& p, MvArgs<T> a, int batch, hipStream_t s, const cx<T>* tw, int only = -1,
+                  int vover = -1);
+
+// Times every launch variant of every pass on the plan's own buffers and keeps the fastest.
+int autotune(Plan& p, int prec_mask, const c128* tw64, const c64* tw32, hipStream_t s);
 
 // Green setup of one plan (both precisions as requested).
 int build_green(Plan& p, double h, const Medium& m, int prec_mask, const c128* tw64,

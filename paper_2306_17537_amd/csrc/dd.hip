@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "context.hpp"
+#include "nn.hpp"
 
 namespace ie {
 
@@ -255,9 +256,13 @@ int dd_group(ie_ctx* c, const std::vector<int>& idx, const ie_problem* problems,
     IE_LAUNCH_CHECK();
     IE_TRY(launch_background(gr.nx, gr.ny, gr.nz, gr.h, gr.origin, c->med, pr.sources,
                              pr.nsources, g.E0 + b * 3 * N, s));
-    const c128* init = o.init == IE_INIT_USER ? (const c128*)pr.E_total : g.E0 + b * 3 * N;
-    IE_HIP(hipMemcpyAsync(g.E + b * 3 * N, init, sizeof(c128) * 3 * N, hipMemcpyDeviceToDevice,
-                          s));
+    if (o.init == IE_INIT_ZERO) {
+      IE_HIP(hipMemsetAsync(g.E + b * 3 * N, 0, sizeof(c128) * 3 * N, s));
+    } else {
+      const c128* init = o.init == IE_INIT_USER ? (const c128*)pr.E_total : g.E0 + b * 3 * N;
+      IE_HIP(hipMemcpyAsync(g.E + b * 3 * N, init, sizeof(c128) * 3 * N,
+                            hipMemcpyDeviceToDevice, s));
+    }
   }
   int bad = 0;
   std::vector<int> pflag(size_t(gr.nz) * B);
@@ -291,7 +296,9 @@ int dd_group(ie_ctx* c, const std::vector<int>& idx, const ie_problem* problems,
   c128* x = gb.x.as<c128>();
   std::vector<double> tols(B);
   std::vector<GmResult> res(B);
+  std::vector<int> accepted(B);
   const double inf = std::numeric_limits<double>::infinity();
+  bool first = true;
 
   while (true) {
     bool any = false;
@@ -319,6 +326,13 @@ int dd_group(ie_ctx* c, const std::vector<int>& idx, const ie_problem* problems,
         tols[b] = live ? (o.adaptive ? e[b] / 10.0 : o.inner_tol_fixed) : inf;
         solve = solve || live;
       }
+      if (solve && first && o.init == IE_INIT_LEARNED) {
+        // first sweep: learned guesses, judged against the default and a zero start
+        IE_TRY(nn_guess_blocks((ie_nn*)o.nn, c, *c->block_plan(nzb), g.D64 + long(z0) * plane, N,
+                               6 * N, rhs, x, B, accepted.data(), s));
+        for (int b = 0; b < B; ++b)
+          if (act[b] && has[b][i] && accepted[b] == 1) stats[idx[b]].learned_used += 1;
+      }
       if (solve)
         IE_TRY(block_solve(g, *c->block_plan(nzb), z0, rhs, x, tols.data(), o.inner, res.data()));
       for (int b = 0; b < B; ++b) {
@@ -339,6 +353,7 @@ int dd_group(ie_ctx* c, const std::vector<int>& idx, const ie_problem* problems,
         }
       }
     }
+    first = false;
     IE_TRY(full_relres(g, e0norm.data(), e.data()));
     for (int b = 0; b < B; ++b) {
       if (!act[b]) continue;
@@ -391,14 +406,22 @@ extern "C" int ie_dd_solve(ie_ctx* const* ctxs, int32_t nproblems, const ie_prob
   if (o.inner.max_its < 1) return fail(IE_EINVAL, "max_its must be >= 1");
   if (o.max_sweeps < 1 || o.max_sweeps > IE_MAX_SWEEPS)
     return fail(IE_EINVAL, "max_sweeps must be in [1, %d]", IE_MAX_SWEEPS);
-  if (o.init == IE_INIT_LEARNED)
+  if (o.init == IE_INIT_LEARNED && o.nn == nullptr)
     return fail(IE_EINVAL, "learned initial guess needs an ie_nn handle");
-  if (o.init != IE_INIT_BACKGROUND && o.init != IE_INIT_USER) return fail(IE_EINVAL, "bad init");
+  if (o.init != IE_INIT_BACKGROUND && o.init != IE_INIT_USER && o.init != IE_INIT_LEARNED &&
+      o.init != IE_INIT_ZERO)
+    return fail(IE_EINVAL, "bad init");
   if (!(o.adaptive == 0 || o.adaptive == 1)) return fail(IE_EINVAL, "adaptive must be 0 or 1");
   for (int p = 0; p < nproblems; ++p) {
     if (ctxs[p] == nullptr) return fail(IE_EINVAL, "context %d is NULL", p);
     if (!(ctxs[p]->prec_mask & o.inner.precision) || !(ctxs[p]->prec_mask & IE_FP64))
       return fail(IE_EINVAL, "context %d lacks the spectra this precision needs", p);
+    if (o.init == IE_INIT_LEARNED) {
+      const ie_ctx* c = ctxs[p];
+      for (size_t i = 0; i + 1 < c->zb.size(); ++i)
+        IE_TRY(nn_check_shape((const ie_nn*)o.nn, c->zb[i + 1] - c->zb[i], c->grid.ny,
+                              c->grid.nx));
+    }
   }
   std::vector<ie_dd_stats> local;
   if (stats == nullptr) {

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "context.hpp"
+#include "nn.hpp"
 #include "prof.hpp"
 
 using u16 = uint16_t;
@@ -321,34 +322,62 @@ __global__ void k_to_bf16(const float* __restrict__ a, u16* __restrict__ b, long
     b[i] = f2bf(a[i]);
 }
 
-// Network input for one block: [dsigma / sigma0 (6), (re, im) of b / rms (6), (re, im) k0 h (2)]
-// from sigma6 (float64 [6][nz][ny][nx] view with component stride cs) and b (complex128
-// contiguous [3][nzb][ny][nx]); output BF16 channels-last [nzb][ny][nx][14].
-__global__ void k_features(const double* __restrict__ s6, long cs, const c128* __restrict__ b,
+// Network input for one block, 14 channels: the contraction-form tensor
+// I - 2 sigma0 (dsigma + 2 sigma0 I)^-1 (bounded in (-1, 1); xx, yy, zz, xy, xz, yz), the field
+// b / rms(b) (re, im of x, y, z) and k0 h (re, im).  D: float64 dsigma [6][nb] with component
+// stride cs; b: complex128 [3][nb]; output BF16 channels-last [nb][14].
+__global__ void k_features(const double* __restrict__ D, long cs, const c128* __restrict__ b,
                            long nb, double sigma0, double inv_rms, double k0h_re, double k0h_im,
                            u16* __restrict__ x) {
-  const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= nb) return;
-  u16* o = x + i * 14;
-  for (int c = 0; c < 6; ++c) o[c] = f2bf(float((s6[c * cs + i] - (c < 3 ? sigma0 : 0.0)) / sigma0));
-  for (int c = 0; c < 3; ++c) {
-    const c128 v = b[c * nb + i];
-    o[6 + 2 * c] = f2bf(float(v.re * inv_rms));
-    o[7 + 2 * c] = f2bf(float(v.im * inv_rms));
+  for (long i = long(blockIdx.x) * blockDim.x + threadIdx.x; i < nb;
+       i += long(gridDim.x) * blockDim.x) {
+    const double t = 2.0 * sigma0;
+    const double xx = D[i] + t, yy = D[cs + i] + t, zz = D[2 * cs + i] + t;
+    const double xy = D[3 * cs + i], xz = D[4 * cs + i], yz = D[5 * cs + i];
+    // adjugate / determinant of the symmetric matrix
+    const double cxx = yy * zz - yz * yz, cyy = xx * zz - xz * xz, czz = xx * yy - xy * xy;
+    const double cxy = xz * yz - xy * zz, cxz = xy * yz - xz * yy, cyz = xy * xz - xx * yz;
+    const double det = xx * cxx + xy * cxy + xz * cxz;
+    const double f = t / det;
+    u16* o = x + i * 14;
+    o[0] = f2bf(float(1.0 - f * cxx));
+    o[1] = f2bf(float(1.0 - f * cyy));
+    o[2] = f2bf(float(1.0 - f * czz));
+    o[3] = f2bf(float(-f * cxy));
+    o[4] = f2bf(float(-f * cxz));
+    o[5] = f2bf(float(-f * cyz));
+    for (int c = 0; c < 3; ++c) {
+      const c128 v = b[c * nb + i];
+      o[6 + 2 * c] = f2bf(float(v.re * inv_rms));
+      o[7 + 2 * c] = f2bf(float(v.im * inv_rms));
+    }
+    o[12] = f2bf(float(k0h_re));
+    o[13] = f2bf(float(k0h_im));
   }
-  o[12] = f2bf(float(k0h_re));
-  o[13] = f2bf(float(k0h_im));
+}
+
+// training target: y = (E - b) / rms(b), float32 channels-last [nb][6]
+__global__ void k_target(const c128* __restrict__ b, const c128* __restrict__ E, long nb,
+                         double inv_rms, float* __restrict__ y) {
+  for (long i = long(blockIdx.x) * blockDim.x + threadIdx.x; i < nb;
+       i += long(gridDim.x) * blockDim.x)
+    for (int c = 0; c < 3; ++c) {
+      const c128 v = b[c * nb + i], e = E[c * nb + i];
+      y[i * 6 + 2 * c] = float((e.re - v.re) * inv_rms);
+      y[i * 6 + 2 * c + 1] = float((e.im - v.im) * inv_rms);
+    }
 }
 
 // x0 = b + rms (y_re + i y_im) per component (the network predicts E - b, scaled by 1 / rms)
 __global__ void k_apply_guess(const c128* __restrict__ b, const float* __restrict__ y, long nb,
                               double rms, c128* __restrict__ x0) {
-  const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= nb) return;
-  for (int c = 0; c < 3; ++c) {
-    const c128 v = b[c * nb + i];
-    x0[c * nb + i] = c128{v.re + rms * double(y[i * 6 + 2 * c]), v.im + rms * double(y[i * 6 + 2 * c + 1])};
-  }
+  for (long i = long(blockIdx.x) * blockDim.x + threadIdx.x; i < nb;
+       i += long(gridDim.x) * blockDim.x)
+    for (int c = 0; c < 3; ++c) {
+      const c128 v = b[c * nb + i];
+      x0[c * nb + i] = c128{v.re + rms * double(y[i * 6 + 2 * c]),
+                            v.im + rms * double(y[i * 6 + 2 * c + 1])};
+    }
 }
 
 // grid for the element-wise grid-stride kernels (x extent times 256 stays below 2^32)
@@ -383,6 +412,9 @@ struct ie_nn {
   DevBuf x16;                               // network input copy (bf16)
   std::vector<DevBuf> pooled;               // pooled inputs per level >= 1
   DevBuf gcur, gtmp, gsk[8], g16, gmask, dcol, part, mse_part, gy;
+  DevBuf xg, res;          // learned guesses and their residuals
+  bool keep_cols = true;  // training keeps every layer's im2col for the backward pass
+  DevBuf icol;            // shared im2col buffer for inference
   std::vector<double> hpart;
 };
 
@@ -448,24 +480,25 @@ int conv_fwd(ie_nn* n, NnLayer& y, const u16* in1, int c1, int up1, const u16* i
   y.X = X;
   y.M = long(n->nb) * Z * Y * X;
   const long K = long(y.taps) * (c1 + c2);
-  IE_TRY(y.col.ensure(sizeof(u16) * y.M * K));
+  DevBuf& colb = n->keep_cols ? y.col : n->icol;
+  IE_TRY(colb.ensure(sizeof(u16) * y.M * K));
+  u16* col = colb.as<u16>();
   if (!out32) IE_TRY(y.out.ensure(sizeof(u16) * y.M * y.co));
   {
     ProfScope ps(s, "nn_im2col", "", 2.0 * y.M * K);
     hipLaunchKernelGGL(k_im2col, dim3(grid1(y.M * K)), dim3(256), 0, s, in1, c1, up1, in2, c2,
-                       n->nb, Z, Y, X, y.taps, y.col.as<u16>());
+                       n->nb, Z, Y, X, y.taps, col);
     IE_LAUNCH_CHECK();
   }
   const u16* W = n->p16.as<u16>() + y.w_off;
   const float* bias = n->p32.as<float>() + y.b_off;
-  if (out32) {
-    gemm(s, true, true, y.col.as<u16>(), K, 1, W, y.co, 1, int(y.M), y.co, int(K), 1, out32, y.co,
-         1, 0, nullptr, nullptr, 0);
-    // bias for the float32 head output: out += b (done by a tiny pass below)
+  if (out32) {  // head: float32 output, bias added by the caller
+    gemm(s, true, true, col, K, 1, W, y.co, 1, int(y.M), y.co, int(K), 1, out32, y.co, 1, 0,
+         nullptr, nullptr, 0);
     return IE_OK;
   }
-  gemm(s, true, true, y.col.as<u16>(), K, 1, W, y.co, 1, int(y.M), y.co, int(K), 1, nullptr, y.co,
-       1, 0, y.out.as<u16>(), bias, y.relu);
+  gemm(s, true, true, col, K, 1, W, y.co, 1, int(y.M), y.co, int(K), 1, nullptr, y.co, 1, 0,
+       y.out.as<u16>(), bias, y.relu);
   return IE_OK;
 }
 
@@ -726,6 +759,7 @@ int ie_nn_forward(ie_nn* n, const uint16_t* x, int32_t batch, int32_t nz, int32_
   IE_TRY(check_nn(n));
   if (x == nullptr || y == nullptr || batch < 1 || nz < 1 || ny < 1 || nx < 1)
     return fail(IE_EINVAL, "bad forward arguments");
+  n->keep_cols = false;
   return forward(n, x, batch, nz, ny, nx, y, (hipStream_t)stream);
 }
 
@@ -734,6 +768,7 @@ int ie_nn_backward(ie_nn* n, const uint16_t* x, const float* dy, int32_t batch, 
   IE_TRY(check_nn(n));
   if (x == nullptr || dy == nullptr || y == nullptr) return fail(IE_EINVAL, "NULL argument");
   hipStream_t s = (hipStream_t)stream;
+  n->keep_cols = true;
   IE_TRY(forward(n, x, batch, nz, ny, nx, y, s));
   return backward(n, dy, s);
 }
@@ -747,6 +782,7 @@ int ie_nn_train_step(ie_nn* n, const uint16_t* x, const float* target, int32_t b
   IE_TRY(n->gy.ensure(sizeof(float) * 2 * cnt));
   float* y = n->gy.as<float>();
   float* g = y + cnt;
+  n->keep_cols = true;
   IE_TRY(forward(n, x, batch, nz, ny, nx, y, s));
   const int nbk = 256;
   IE_TRY(n->mse_part.ensure(sizeof(double) * nbk));
@@ -797,48 +833,87 @@ int ie_nn_gemm(const uint16_t* A, const uint16_t* B, float* Cm, int32_t M, int32
 
 namespace ie {
 
-// Learned guesses for `batch` blocks: x0 = b + rms (network output) with the block features;
-// then, per block, keep whichever of x0 and the default guess xdef has the smaller residual
-// ||b - A x|| (one float64 operator application each).  accepted[b] = 1 if x0 was kept.
-int nn_guess_blocks(ie_nn* n, ie_ctx* c, Plan& B, const double* sigma6, long s_cs, long s_bs,
-                    const c128* rhs, c128* x, int batch, const OpDesc& op, int* accepted,
+int nn_check_shape(const ie_nn* n, int nz, int ny, int nx) {
+  const int q = 1 << (n->levels - 1);
+  if (n->in_ch != 14 || n->out_ch != 6)
+    return fail(IE_EINVAL, "the guess network must map 14 feature channels to 6 field channels");
+  if (nz % q || ny % q || nx % q)
+    return fail(IE_EINVAL, "grid %dx%dx%d is not divisible by 2^(levels-1) = %d", nx, ny, nz, q);
+  return IE_OK;
+}
+
+namespace {
+
+void k0h(const ie_ctx* c, double* re, double* im) {
+  *re = c->med.k0re * c->grid.h;
+  *im = c->med.k0im * c->grid.h;
+}
+
+// network forward over `batch` blocks of nb cells in chunks of about 2^20 cells
+int forward_chunked(ie_nn* n, const u16* x, int batch, int nz, int ny, int nx, float* y,
                     hipStream_t s) {
+  const long nb = long(nz) * ny * nx;
+  const int per = int(std::max<long>(1, (1L << 20) / nb));
+  n->keep_cols = false;
+  for (int b0 = 0; b0 < batch; b0 += per) {
+    const int k = std::min(per, batch - b0);
+    IE_TRY(forward(n, x + long(b0) * nb * 14, k, nz, ny, nx, y + long(b0) * nb * 6, s));
+  }
+  return IE_OK;
+}
+
+}  // namespace
+
+int nn_guess_blocks(ie_nn* n, ie_ctx* c, Plan& B, const double* D, long d_cs, long d_bs,
+                    const c128* rhs, c128* x, int batch, int* accepted, hipStream_t s) {
   const long nb = B.ncell();
-  std::vector<double> bn(batch);
+  IE_TRY(nn_check_shape(n, B.nz, B.ny, B.nx));
+  std::vector<double> bn(batch), rl(batch), rd(batch);
   IE_TRY(norms_host(rhs, 3 * nb, batch, bn.data(), c->kw_blk, s));
   IE_TRY(n->x16.ensure(sizeof(u16) * 14 * nb * batch));
-  const double h = c->grid.h;
+  double kr, ki;
+  k0h(c, &kr, &ki);
   for (int b = 0; b < batch; ++b) {
     const double rms = bn[b] / std::sqrt(3.0 * double(nb));
-    hipLaunchKernelGGL(k_features, dim3(ceil_div(nb, 256)), dim3(256), 0, s, sigma6 + b * s_bs,
-                       s_cs, rhs + b * 3 * nb, nb, c->med.sigma0, rms > 0 ? 1.0 / rms : 0.0,
-                       c->med.k0re * h, c->med.k0im * h, n->x16.as<u16>() + b * 14 * nb);
+    hipLaunchKernelGGL(k_features, dim3(grid1(nb)), dim3(256), 0, s, D + b * d_bs, d_cs,
+                       rhs + b * 3 * nb, nb, c->med.sigma0, rms > 0 ? 1.0 / rms : 0.0, kr, ki,
+                       n->x16.as<u16>() + b * 14 * nb);
     IE_LAUNCH_CHECK();
   }
-  DevBuf y32, xg, r;
-  IE_TRY(y32.ensure(sizeof(float) * 6 * nb * batch));
-  IE_TRY(forward(n, n->x16.as<u16>(), batch, B.nz, B.ny, B.nx, y32.as<float>(), s));
-  IE_TRY(xg.ensure(sizeof(c128) * 3 * nb * batch));
-  IE_TRY(r.ensure(sizeof(c128) * 3 * nb * batch));
+  IE_TRY(n->gy.ensure(sizeof(float) * 6 * nb * batch));
+  IE_TRY(forward_chunked(n, n->x16.as<u16>(), batch, B.nz, B.ny, B.nx, n->gy.as<float>(), s));
+  IE_TRY(n->xg.ensure(sizeof(c128) * 3 * nb * batch));
+  IE_TRY(n->res.ensure(sizeof(c128) * 3 * nb * batch));
+  c128* xg = n->xg.as<c128>();
+  c128* r = n->res.as<c128>();
   for (int b = 0; b < batch; ++b) {
     const double rms = bn[b] / std::sqrt(3.0 * double(nb));
-    hipLaunchKernelGGL(k_apply_guess, dim3(ceil_div(nb, 256)), dim3(256), 0, s,
-                       rhs + b * 3 * nb, y32.as<float>() + b * 6 * nb, nb, rms,
-                       xg.as<c128>() + b * 3 * nb);
+    hipLaunchKernelGGL(k_apply_guess, dim3(grid1(nb)), dim3(256), 0, s, rhs + b * 3 * nb,
+                       n->gy.as<float>() + b * 6 * nb, nb, rms, xg + b * 3 * nb);
     IE_LAUNCH_CHECK();
   }
-  // judge: residual of the learned guess vs the default guess (conventional operator)
-  std::vector<double> rl(batch), rd(batch);
-  IE_TRY(apply_op<double>(B, op, xg.as<c128>(), r.as<c128>(), rhs, true, batch, nullptr, 0, s,
-                          tw64(c)));
-  IE_TRY(norms_host(r.as<c128>(), 3 * nb, batch, rl.data(), c->kw_blk, s));
-  IE_TRY(apply_op<double>(B, op, x, r.as<c128>(), rhs, true, batch, nullptr, 0, s, tw64(c)));
-  IE_TRY(norms_host(r.as<c128>(), 3 * nb, batch, rd.data(), c->kw_blk, s));
+  // judge: float64 residuals ||rhs - (I - G dsigma) x|| of the learned and the default guess;
+  // a zero start has residual ||rhs||
+  OpDesc op;
+  op.form = IE_CONVENTIONAL;
+  op.M64 = D;
+  op.M_cs = d_cs;
+  op.M_bs = d_bs;
+  IE_TRY(apply_op<double>(B, op, xg, r, rhs, true, batch, nullptr, 0, s, tw64(c)));
+  IE_TRY(norms_host(r, 3 * nb, batch, rl.data(), c->kw_blk, s));
+  IE_TRY(apply_op<double>(B, op, x, r, rhs, true, batch, nullptr, 0, s, tw64(c)));
+  IE_TRY(norms_host(r, 3 * nb, batch, rd.data(), c->kw_blk, s));
   for (int b = 0; b < batch; ++b) {
-    accepted[b] = rl[b] < rd[b];
-    if (accepted[b])
-      IE_HIP(hipMemcpyAsync(x + b * 3 * nb, xg.as<c128>() + b * 3 * nb, sizeof(c128) * 3 * nb,
+    if (rl[b] < rd[b] && rl[b] < bn[b]) {
+      accepted[b] = 1;
+      IE_HIP(hipMemcpyAsync(x + b * 3 * nb, xg + b * 3 * nb, sizeof(c128) * 3 * nb,
                             hipMemcpyDeviceToDevice, s));
+    } else if (bn[b] < rd[b]) {
+      accepted[b] = 2;
+      IE_HIP(hipMemsetAsync(x + b * 3 * nb, 0, sizeof(c128) * 3 * nb, s));
+    } else {
+      accepted[b] = 0;
+    }
   }
   IE_HIP(hipStreamSynchronize(s));
   return IE_OK;
@@ -846,23 +921,56 @@ int nn_guess_blocks(ie_nn* n, ie_ctx* c, Plan& B, const double* sigma6, long s_c
 
 }  // namespace ie
 
-extern "C" int ie_nn_guess(ie_ctx* ctx, ie_nn* n, const double* sigma6, const void* b, void* x,
-                           int32_t* accepted, void* stream) {
+extern "C" {
+
+int ie_nn_features(ie_ctx* ctx, const double* sigma6, const void* b, uint16_t* x, double* rms,
+                   void* stream) {
+  if (ctx == nullptr || sigma6 == nullptr || b == nullptr || x == nullptr)
+    return fail(IE_EINVAL, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  const long N = ctx->full->ncell();
+  IE_TRY(prepare_contrast(ctx, sigma6, IE_CONVENTIONAL, s));
+  double bn = 0;
+  IE_TRY(norms_host((const c128*)b, 3 * N, 1, &bn, ctx->kw, s));
+  const double r = bn / std::sqrt(3.0 * double(N));
+  double kr, ki;
+  k0h(ctx, &kr, &ki);
+  hipLaunchKernelGGL(k_features, dim3(grid1(N)), dim3(256), 0, s, ctx->M64.as<const double>(), N,
+                     (const c128*)b, N, ctx->med.sigma0, r > 0 ? 1.0 / r : 0.0, kr, ki, x);
+  IE_LAUNCH_CHECK();
+  IE_HIP(hipStreamSynchronize(s));
+  if (rms) *rms = r;
+  return IE_OK;
+}
+
+int ie_nn_target(ie_ctx* ctx, const void* b, const void* E, float* y, void* stream) {
+  if (ctx == nullptr || b == nullptr || E == nullptr || y == nullptr)
+    return fail(IE_EINVAL, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  const long N = ctx->full->ncell();
+  double bn = 0;
+  IE_TRY(norms_host((const c128*)b, 3 * N, 1, &bn, ctx->kw, s));
+  const double r = bn / std::sqrt(3.0 * double(N));
+  hipLaunchKernelGGL(k_target, dim3(grid1(N)), dim3(256), 0, s, (const c128*)b, (const c128*)E, N,
+                     r > 0 ? 1.0 / r : 0.0, y);
+  IE_LAUNCH_CHECK();
+  IE_HIP(hipStreamSynchronize(s));
+  return IE_OK;
+}
+
+int ie_nn_guess(ie_ctx* ctx, ie_nn* n, const double* sigma6, const void* b, void* x,
+                int32_t* accepted, void* stream) {
   if (ctx == nullptr || n == nullptr || sigma6 == nullptr || b == nullptr || x == nullptr)
     return fail(IE_EINVAL, "NULL argument");
-  if (n->in_ch != 14 || n->out_ch != 6)
-    return fail(IE_EINVAL, "the network must map 14 feature channels to 6 field channels");
   hipStream_t s = (hipStream_t)stream;
   Plan& F = *ctx->full;
+  IE_TRY(nn_check_shape(n, F.nz, F.ny, F.nx));
   IE_TRY(prepare_contrast(ctx, sigma6, IE_CONVENTIONAL, s));
-  OpDesc op;
-  op.form = IE_CONVENTIONAL;
-  op.M64 = ctx->M64.as<const double>();
-  op.M_cs = F.ncell();
-  op.M_bs = 6 * F.ncell();
   int acc = 0;
-  IE_TRY(nn_guess_blocks(n, ctx, F, sigma6, F.ncell(), 6 * F.ncell(), (const c128*)b, (c128*)x, 1,
-                         op, &acc, s));
+  IE_TRY(nn_guess_blocks(n, ctx, F, ctx->M64.as<const double>(), F.ncell(), 6 * F.ncell(),
+                         (const c128*)b, (c128*)x, 1, &acc, s));
   if (accepted) *accepted = acc;
   return IE_OK;
 }
+
+}  // extern "C"

@@ -5,6 +5,10 @@
 #include <algorithm>
 #include <complex>
 #include <string>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "ctx.hpp"
 #include "prof.hpp"
@@ -39,10 +43,24 @@ int fft_len(int n) {
     default: return fail(IE_EINVAL, "unsupported FFT length %d", L); \
   }
 
+// Calls F<T, L>::template go<V>(args...) for the plan's variant v (lengths below 16 have one).
+#define IE_VARIANTS(v, ...)                                              \
+  if constexpr (L < 16) {                                                \
+    return go<0>(__VA_ARGS__);                                           \
+  } else {                                                               \
+    switch (v) {                                                         \
+      case 1: return go<1>(__VA_ARGS__);                                 \
+      case 2: return go<2>(__VA_ARGS__);                                 \
+      case 3: return go<3>(__VA_ARGS__);                                 \
+      default: return go<0>(__VA_ARGS__);                                \
+    }                                                                    \
+  }
+
 template <typename T, int L>
 struct XfwdL {
-  static int run(const MvArgs<T>& a, int batch, hipStream_t s) {
-    using G = Geo<T, L>;
+  template <int V>
+  static int go(const MvArgs<T>& a, int batch, hipStream_t s) {
+    using G = Geo<T, L, V>;
     const long rows = long(a.nz) * a.ny;
     dim3 grid(ceil_div(rows, G::NL), 1, batch);
     const int z0 = std::max(a.src_z0, 0), z1 = std::min(a.src_z1, a.nz);
@@ -53,15 +71,19 @@ struct XfwdL {
     const double by = double(batch) * (double(zs) * a.ny * a.nx * (3 * cs + (a.M ? 6 * rs : 0)) +
                                        double(rows) * L * 3 * cs);
     ProfScope ps(s, "xfwd", shape_tag(int(cs), a.LX, a.LY, a.LZ, a.nz, batch).c_str(), by);
-    hipLaunchKernelGGL((k_xfwd<T, L>), grid, dim3(threads), 0, s, a);
+    hipLaunchKernelGGL((k_xfwd<T, L, V>), grid, dim3(threads), 0, s, a);
     IE_LAUNCH_CHECK();
     return IE_OK;
+  }
+  static int run(int v, const MvArgs<T>& a, int batch, hipStream_t s) {
+    IE_VARIANTS(v, a, batch, s);
   }
 };
 template <typename T, int L>
 struct XinvL {
-  static int run(const MvArgs<T>& a, int batch, hipStream_t s) {
-    using G = Geo<T, L>;
+  template <int V>
+  static int go(const MvArgs<T>& a, int batch, hipStream_t s) {
+    using G = Geo<T, L, V>;
     const long rows = long(a.out_z1 - a.out_z0) * a.ny;
     dim3 grid(ceil_div(rows, G::NL), 1, batch);
     const double cs = sizeof(cx<T>), rs = sizeof(T);
@@ -70,30 +92,39 @@ struct XinvL {
     const double per = 3 * cs + (ux ? 3 * cs : 0) + (um ? 6 * rs : 0) + (a.e ? 3 * cs : 0);
     const double by = double(batch) * (double(rows) * L * 3 * cs + double(rows) * a.nx * per);
     ProfScope ps(s, "xinv", shape_tag(int(cs), a.LX, a.LY, a.LZ, a.nz, batch).c_str(), by);
-    hipLaunchKernelGGL((k_xinv<T, L>), grid, dim3(G::NL * G::TLR), 0, s, a);
+    hipLaunchKernelGGL((k_xinv<T, L, V>), grid, dim3(G::NL * G::TLR), 0, s, a);
     IE_LAUNCH_CHECK();
     return IE_OK;
+  }
+  static int run(int v, const MvArgs<T>& a, int batch, hipStream_t s) {
+    IE_VARIANTS(v, a, batch, s);
   }
 };
 template <typename T, int L>
 struct ZconvL {
-  static int run(const MvArgs<T>& a, int batch, hipStream_t s) {
-    using G = Geo<T, L>;
-    dim3 grid(ceil_div(a.LX, G::W), a.LY, batch);
+  template <int V>
+  static int go(const MvArgs<T>& a, int batch, hipStream_t s) {
+    using G = GeoZ<T, L, V>;
+    dim3 grid(ceil_div(a.LX, G::W), G::PAIR ? a.LY / 2 + 1 : a.LY, batch);
     const double cs = sizeof(cx<T>);
+    // algorithmic bytes count the spectrum at its octant size (the unique values)
     const double oct = 6.0 * (a.LX / 2 + 1) * (a.LY / 2 + 1) * (L / 2 + 1);
     const double by = double(batch) * 3.0 * a.LY * a.LX * cs * (a.nz + (a.out_z1 - a.out_z0)) + oct * cs;
     ProfScope ps(s, "zconv", shape_tag(int(cs), a.LX, a.LY, a.LZ, a.nz, batch).c_str(), by);
-    hipLaunchKernelGGL((k_zconv<T, L>), grid, dim3(G::W * G::TL), 0, s, a);
+    hipLaunchKernelGGL((k_zconv<T, L, V>), grid, dim3(G::W * G::TL), 0, s, a);
     IE_LAUNCH_CHECK();
     return IE_OK;
+  }
+  static int run(int v, const MvArgs<T>& a, int batch, hipStream_t s) {
+    IE_VARIANTS(v, a, batch, s);
   }
 };
 template <typename T, int L>
 struct ColL {
-  static int run(const cx<T>* in, cx<T>* out, const ColArgs& c, int nplanes, int batch, bool inv,
-                 hipStream_t s, const cx<T>* tw) {
-    using G = Geo<T, L>;
+  template <int V>
+  static int go(const cx<T>* in, cx<T>* out, const ColArgs& c, int nplanes, int batch, bool inv,
+                hipStream_t s, const cx<T>* tw) {
+    using G = Geo<T, L, V>;
     dim3 grid(ceil_div(c.ncols, G::W), nplanes, batch);
     const double cs = sizeof(cx<T>);
     const double by = double(batch) * nplanes * double(c.ncols) * (c.rows_in + c.rows_out) * cs;
@@ -102,11 +133,16 @@ struct ColL {
              c.ncols, batch);
     ProfScope ps(s, inv ? "yinv" : "yfwd", tg, by);
     if (inv)
-      hipLaunchKernelGGL((k_colfft<T, L, true>), grid, dim3(G::W * G::TL), 0, s, in, out, c, tw);
+      hipLaunchKernelGGL((k_colfft<T, L, true, V>), grid, dim3(G::W * G::TL), 0, s, in, out, c, tw);
     else
-      hipLaunchKernelGGL((k_colfft<T, L, false>), grid, dim3(G::W * G::TL), 0, s, in, out, c, tw);
+      hipLaunchKernelGGL((k_colfft<T, L, false, V>), grid, dim3(G::W * G::TL), 0, s, in, out, c,
+                         tw);
     IE_LAUNCH_CHECK();
     return IE_OK;
+  }
+  static int run(int v, const cx<T>* in, cx<T>* out, const ColArgs& c, int nplanes, int batch,
+                 bool inv, hipStream_t s, const cx<T>* tw) {
+    IE_VARIANTS(v, in, out, c, nplanes, batch, inv, s, tw);
   }
 };
 
@@ -128,8 +164,12 @@ int Plan::work(int prec, int batch) {
 }
 
 template <typename T>
-int launch_matvec(Plan& p, MvArgs<T> a, int batch, hipStream_t s, const cx<T>* tw) {
+int launch_matvec(Plan& p, MvArgs<T> a, int batch, hipStream_t s, const cx<T>* tw, int only,
+                  int vover) {
   constexpr bool dbl = sizeof(T) == 8;
+  const int8_t* var = p.var[dbl ? 0 : 1];
+  auto vsel = [&](int pass) { return vover >= 0 ? vover : int(var[pass]); };
+  auto want = [&](int pass) { return only < 0 || only == pass; };
   IE_TRY(p.work(dbl ? IE_FP64 : IE_MIXED, batch));
   a.nx = p.nx;
   a.ny = p.ny;
@@ -150,8 +190,8 @@ int launch_matvec(Plan& p, MvArgs<T> a, int batch, hipStream_t s, const cx<T>* t
   if (batch < 1 || batch > 65535) return fail(IE_EINVAL, "bad batch %d", batch);
 
   // pass 1: contrast, pad, FFT along x
-  auto xf = [&]() -> int { IE_LEN_CASES(XfwdL, T, p.LX, a, batch, s); };
-  IE_TRY(xf());
+  auto xf = [&]() -> int { IE_LEN_CASES(XfwdL, T, p.LX, vsel(0), a, batch, s); };
+  if (want(0)) IE_TRY(xf());
   // pass 2: FFT along y (ny non-zero rows -> LY)
   ColArgs c{};
   c.ncols = p.LX;
@@ -170,12 +210,12 @@ int launch_matvec(Plan& p, MvArgs<T> a, int batch, hipStream_t s, const cx<T>* t
   c.active = a.active;
   c.active_bs = a.active_bs;
   auto col = [&](const cx<T>* in, cx<T>* out, const ColArgs& cc, int np, bool inv) -> int {
-    IE_LEN_CASES(ColL, T, p.LY, in, out, cc, np, batch, inv, s, tw);
+    IE_LEN_CASES(ColL, T, p.LY, vsel(inv ? 3 : 1), in, out, cc, np, batch, inv, s, tw);
   };
-  IE_TRY(col(a.T1, a.T2, c, 3 * p.nz, false));
+  if (want(1)) IE_TRY(col(a.T1, a.T2, c, 3 * p.nz, false));
   // pass 3: FFT along z, tensor multiply with G^, inverse FFT along z
-  auto zc = [&]() -> int { IE_LEN_CASES(ZconvL, T, p.LZ, a, batch, s); };
-  IE_TRY(zc());
+  auto zc = [&]() -> int { IE_LEN_CASES(ZconvL, T, p.LZ, vsel(2), a, batch, s); };
+  if (want(2)) IE_TRY(zc());
   // pass 4: inverse FFT along y on the kept planes (LY -> ny rows)
   const int nzo = a.out_z1 - a.out_z0;
   ColArgs d = c;
@@ -191,14 +231,121 @@ int launch_matvec(Plan& p, MvArgs<T> a, int batch, hipStream_t s, const cx<T>* t
   d.rows_out = p.ny;
   d.in_bs = a.T2_bs;
   d.out_bs = a.T1_bs;
-  IE_TRY(col(a.T2, a.T1, d, 3 * nzo, true));
+  if (want(3)) IE_TRY(col(a.T2, a.T1, d, 3 * nzo, true));
   // pass 5: inverse FFT along x, crop, combine
-  auto xi = [&]() -> int { IE_LEN_CASES(XinvL, T, p.LX, a, batch, s); };
-  return xi();
+  auto xi = [&]() -> int { IE_LEN_CASES(XinvL, T, p.LX, vsel(4), a, batch, s); };
+  if (want(4)) IE_TRY(xi());
+  return IE_OK;
 }
 
-template int launch_matvec<double>(Plan&, MvArgs<double>, int, hipStream_t, const c128*);
-template int launch_matvec<float>(Plan&, MvArgs<float>, int, hipStream_t, const c64*);
+template int launch_matvec<double>(Plan&, MvArgs<double>, int, hipStream_t, const c128*, int, int);
+template int launch_matvec<float>(Plan&, MvArgs<float>, int, hipStream_t, const c64*, int, int);
+
+// ---------------------------------------------------------------------------------------
+// Autotuner: every launch variant of every pass is timed (HIP events, one warm-up launch, then
+// the average of kReps launches) on the plan's own work buffers with zero inputs, and the
+// fastest is kept.  Results are cached per (device, precision, grid) for the process.
+// ---------------------------------------------------------------------------------------
+namespace {
+struct TuneEntry {
+  int8_t var[5];
+  float us[5][kVariants];
+};
+std::map<std::tuple<int, int, int, int, int>, TuneEntry> g_tune_cache;
+std::mutex g_tune_mu;
+constexpr int kReps = 5;
+}  // namespace
+
+template <typename T>
+static int tune_one(Plan& p, const cx<T>* tw, hipStream_t s, int8_t var[5], float us[5][kVariants]) {
+  constexpr bool dbl = sizeof(T) == 8;
+  IE_TRY(p.work(dbl ? IE_FP64 : IE_MIXED, 1));
+  const long N = p.ncell();
+  DevBuf x, y, M;
+  IE_TRY(x.ensure(sizeof(cx<T>) * 3 * N));
+  IE_TRY(y.ensure(sizeof(cx<T>) * 3 * N));
+  IE_TRY(M.ensure(sizeof(T) * 6 * N));
+  IE_HIP(hipMemsetAsync(x.p, 0, sizeof(cx<T>) * 3 * N, s));
+  IE_HIP(hipMemsetAsync(M.p, 0, sizeof(T) * 6 * N, s));
+  IE_HIP(hipMemsetAsync(dbl ? p.t1_64.p : p.t1_32.p, 0, sizeof(cx<T>) * p.t1_elems(), s));
+  IE_HIP(hipMemsetAsync(dbl ? p.t2_64.p : p.t2_32.p, 0, sizeof(cx<T>) * p.t2_elems(), s));
+  MvArgs<T> a{};  // the contraction-form operator: reads x and the contrast, writes y
+  a.x = x.as<const cx<T>>();
+  a.x_cs = N;
+  a.x_bs = 3 * N;
+  a.M = M.as<const T>();
+  a.M_cs = N;
+  a.M_bs = 6 * N;
+  a.src_z0 = 0;
+  a.src_z1 = p.nz;
+  a.hole_z0 = a.hole_z1 = -1;
+  a.out_z0 = 0;
+  a.out_z1 = p.nz;
+  a.y = y.as<cx<T>>();
+  a.y_cs = N;
+  a.y_bs = 3 * N;
+  a.a_x = 1;
+  a.a_m = 1;
+  a.a_s = -1;
+  hipEvent_t e0, e1;
+  IE_HIP(hipEventCreate(&e0));
+  IE_HIP(hipEventCreate(&e1));
+  int rc = IE_OK;
+  for (int pass = 0; pass < 5 && rc == IE_OK; ++pass) {
+    float best = 0;
+    var[pass] = 0;
+    for (int v = 0; v < kVariants && rc == IE_OK; ++v) {
+      rc = launch_matvec<T>(p, a, 1, s, tw, pass, v);
+      if (rc != IE_OK) break;
+      if (hipEventRecord(e0, s) != hipSuccess) rc = fail(IE_EDEVICE, "hipEventRecord failed");
+      for (int r = 0; r < kReps && rc == IE_OK; ++r) rc = launch_matvec<T>(p, a, 1, s, tw, pass, v);
+      if (rc != IE_OK) break;
+      float ms = 0;
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        rc = fail(IE_EDEVICE, "event timing failed");
+        break;
+      }
+      us[pass][v] = 1e3f * ms / kReps;
+      if (v == 0 || us[pass][v] < best) {
+        best = us[pass][v];
+        var[pass] = int8_t(v);
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
+int autotune(Plan& p, int prec_mask, const c128* tw64, const c64* tw32, hipStream_t s) {
+  int dev = 0;
+  IE_HIP(hipGetDevice(&dev));
+  for (int pi = 0; pi < 2; ++pi) {
+    const bool dbl = pi == 0;
+    if (!(prec_mask & (dbl ? IE_FP64 : IE_MIXED))) continue;
+    const auto key = std::make_tuple(dev, pi, p.nx, p.ny, p.nz);
+    {
+      std::lock_guard<std::mutex> g(g_tune_mu);
+      auto it = g_tune_cache.find(key);
+      if (it != g_tune_cache.end()) {
+        std::memcpy(p.var[pi], it->second.var, sizeof(p.var[pi]));
+        std::memcpy(p.tune_us[pi], it->second.us, sizeof(p.tune_us[pi]));
+        continue;
+      }
+    }
+    TuneEntry t{};
+    if (dbl)
+      IE_TRY(tune_one<double>(p, tw64, s, t.var, t.us));
+    else
+      IE_TRY(tune_one<float>(p, tw32, s, t.var, t.us));
+    std::memcpy(p.var[pi], t.var, sizeof(p.var[pi]));
+    std::memcpy(p.tune_us[pi], t.us, sizeof(p.tune_us[pi]));
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune_cache[key] = t;
+  }
+  return IE_OK;
+}
 
 // ---------------------------------------------------------------------------------------
 // Green setup
@@ -288,16 +435,17 @@ struct RowL {
   }
 };
 
-__global__ void k_octant(const c128* __restrict__ full, c128* __restrict__ o64, c64* __restrict__ o32,
-                         int LX, int LY, int LZ, double scale) {
-  const int hx = LX / 2 + 1, hy = LY / 2 + 1, hz = LZ / 2 + 1;
-  const long n = 6L * hx * hy * hz;
+// the stored part of the spectrum: all kx, ky <= LY/2, kz <= LZ/2 ([6][LZ/2+1][LY/2+1][LX])
+__global__ void k_halfspec(const c128* __restrict__ full, c128* __restrict__ o64,
+                           c64* __restrict__ o32, int LX, int LY, int LZ, double scale) {
+  const int hy = LY / 2 + 1, hz = LZ / 2 + 1;
+  const long n = 6L * LX * hy * hz;
   const long idx = long(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= n) return;
-  const int ox = int(idx % hx);
-  const int oy = int((idx / hx) % hy);
-  const int oz = int((idx / (long(hx) * hy)) % hz);
-  const int c = int(idx / (long(hx) * hy * hz));
+  const int ox = int(idx % LX);
+  const int oy = int((idx / LX) % hy);
+  const int oz = int((idx / (long(LX) * hy)) % hz);
+  const int c = int(idx / (long(LX) * hy * hz));
   const long Lt = long(LX) * LY * LZ;
   const c128 v = scale * full[c * Lt + (long(oz) * LY + oy) * LX + ox];
   if (o64) o64[idx] = v;
@@ -335,7 +483,7 @@ int build_green(Plan& p, double h, const Medium& m, int prec_mask, const c128* t
     ca.in_ls = ca.out_ls = p.LX;
     ca.rows_in = ca.rows_out = p.LY;
     {
-      auto f = [&]() -> int { IE_LEN_CASES(ColL, double, p.LY, b, b, ca, p.LZ, 1, false, s, tw64); };
+      auto f = [&]() -> int { IE_LEN_CASES(ColL, double, p.LY, 0, b, b, ca, p.LZ, 1, false, s, tw64); };
       IE_TRY(f());
     }
     // z axis: planes = y
@@ -344,11 +492,11 @@ int build_green(Plan& p, double h, const Medium& m, int prec_mask, const c128* t
     ca.in_ls = ca.out_ls = long(p.LY) * p.LX;
     ca.rows_in = ca.rows_out = p.LZ;
     {
-      auto f = [&]() -> int { IE_LEN_CASES(ColL, double, p.LZ, b, b, ca, p.LY, 1, false, s, tw64); };
+      auto f = [&]() -> int { IE_LEN_CASES(ColL, double, p.LZ, 0, b, b, ca, p.LY, 1, false, s, tw64); };
       IE_TRY(f());
     }
   }
-  const long no = p.oct_elems();
+  const long no = p.spec_elems();
   c128* o64 = nullptr;
   c64* o32 = nullptr;
   if (prec_mask & IE_FP64) {
@@ -359,7 +507,7 @@ int build_green(Plan& p, double h, const Medium& m, int prec_mask, const c128* t
     IE_TRY(p.ghat32.ensure(sizeof(c64) * no));
     o32 = p.ghat32.as<c64>();
   }
-  hipLaunchKernelGGL(k_octant, dim3(ceil_div(no, 256)), dim3(256), 0, s, full.as<c128>(), o64, o32,
+  hipLaunchKernelGGL(k_halfspec, dim3(ceil_div(no, 256)), dim3(256), 0, s, full.as<c128>(), o64, o32,
                      p.LX, p.LY, p.LZ, 1.0 / double(Lt));
   IE_LAUNCH_CHECK();
   IE_HIP(hipStreamSynchronize(s));  // `full` is released on return

@@ -4,7 +4,8 @@
 //          -> T1[3][nz][ny][LX]
 //   yfwd : FFT along y of the ny non-zero rows, padded to LY          -> T2[3][nz][LY][LX]
 //   zconv: per (kx, ky) column, FFT along z of the nz non-zero planes, S^_p = sum_q G^_pq J^_q
-//          with the six stored octant components of G^ (G_pq = G_qp, each even or odd per axis),
+//          with the six stored components of G^ (G_pq = G_qp, each even or odd per axis; the
+//          half kept for ky <= LY/2, kz <= LZ/2 serves the row pair ky, LY - ky of one block),
 //          inverse FFT along z, keep the output planes                  -> T2 (in place)
 //   yinv : inverse FFT along y, keep ny rows                             -> T1
 //   xinv : inverse FFT along x, keep nx cells, combine
@@ -40,7 +41,7 @@ struct MvArgs {
   cx<T>* T1;
   cx<T>* T2;
   long T1_bs, T2_bs;
-  const cx<T>* ghat;  // octant [6][LZ/2+1][LY/2+1][LX/2+1], scaled by 1/(LX LY LZ)
+  const cx<T>* ghat;  // [6][LZ/2+1][LY/2+1][LX], scaled by 1/(LX LY LZ)
   long ghat_bs;
   // output planes and combination
   int out_z0, out_z1;
@@ -62,23 +63,31 @@ __device__ __forceinline__ bool retired(const MvArgs<T>& a, int b) {
 }
 
 // ---------------------------------------------------------------------------------------
-// launch geometry per (precision, length)
+// launch geometry per (precision, length, variant)
+// Variant V (chosen per plan by the autotuner): bit 0 halves the values per thread (twice the
+// threads per line, more waves in flight, one more LDS exchange); bit 1 doubles the columns per
+// block of the column passes (256-byte row segments) and the rows per block of the row passes.
 // ---------------------------------------------------------------------------------------
-template <typename T, int L>
+constexpr int kVariants = 4;
+
+template <typename T, int L, int V = 0>
 struct Geo {
   // column passes (y, z): E values per thread per line, W adjacent columns per block so that a
-  // row segment is one 128-byte line; at least 64 threads per block; LDS budget 64 KB
+  // row segment is one (V & 2: two) 128-byte line(s); at least 64 threads per block; LDS <= 64 KB
   static constexpr int Edef = sizeof(T) == 8 ? 8 : 16;
-  static constexpr int E = L < Edef ? L : Edef;
+  static constexpr int E1 = L < Edef ? L : Edef;
+  static constexpr int E = ((V & 1) && E1 >= 4) ? E1 / 2 : E1;
   static constexpr int TL = L / E;
-  static constexpr int Wc = 128 / int(sizeof(cx<T>));
+  static constexpr int Wc = (128 / int(sizeof(cx<T>))) * ((V & 2) ? 2 : 1);
   static constexpr int Wm = (64 / TL) > Wc ? (64 / TL) : Wc;
   static constexpr int Wl = (65536 / int(L * sizeof(cx<T>))) < 1 ? 1 : (65536 / int(L * sizeof(cx<T>)));
   static constexpr int W = Wm < Wl ? Wm : Wl;
-  // row passes (x): ER values per thread, TLR threads per line, NL rows per block (~128 threads)
-  static constexpr int ER = L < 4 ? L : 4;
+  // row passes (x): ER values per thread, TLR threads per line, NL rows per block (~128 threads,
+  // V & 2: ~256)
+  static constexpr int ER1 = L < 4 ? L : 4;
+  static constexpr int ER = ((V & 1) && ER1 >= 4) ? ER1 / 2 : ER1;
   static constexpr int TLR = L / ER;
-  static constexpr int NL0 = 128 / TLR;
+  static constexpr int NL0 = ((V & 2) ? 256 : 128) / TLR;
   static constexpr int NL = NL0 < 1 ? 1 : NL0;
   static constexpr int LP = LdsPadded::padded_len(L);
 };
@@ -97,10 +106,10 @@ __device__ __forceinline__ void tensor_apply(const T m[6], const cx<T> v[3], cx<
 // ---------------------------------------------------------------------------------------
 // xfwd: contrast, pad, FFT along x.  Block: NL rows x TL threads; thread (row, t).
 // ---------------------------------------------------------------------------------------
-template <typename T, int LX>
-__global__ void __launch_bounds__((Geo<T, LX>::NL * Geo<T, LX>::TLR))
+template <typename T, int LX, int V>
+__global__ void __launch_bounds__((Geo<T, LX, V>::NL * Geo<T, LX, V>::TLR))
     k_xfwd(const MvArgs<T> a) {
-  using G = Geo<T, LX>;
+  using G = Geo<T, LX, V>;
   constexpr int E = G::ER, TL = G::TLR, NL = G::NL;
   __shared__ cx<T> lds[NL * G::LP];
   const int b = blockIdx.z;
@@ -165,11 +174,11 @@ struct ColArgs {
   int active_bs;
 };
 
-template <typename T, int L, bool INV>
-__global__ void __launch_bounds__((Geo<T, L>::W * Geo<T, L>::TL))
+template <typename T, int L, bool INV, int V>
+__global__ void __launch_bounds__((Geo<T, L, V>::W * Geo<T, L, V>::TL))
     k_colfft(const cx<T>* in, cx<T>* out, const ColArgs a,
              const cx<T>* __restrict__ tw) {
-  using G = Geo<T, L>;
+  using G = Geo<T, L, V>;
   constexpr int E = G::E, TL = G::TL, W = G::W;
   __shared__ cx<T> lds[W * L];
   const int b = blockIdx.z;
@@ -200,71 +209,114 @@ __global__ void __launch_bounds__((Geo<T, L>::W * Geo<T, L>::TL))
 }
 
 // ---------------------------------------------------------------------------------------
-// zconv: FFT along z, tensor multiply with the octant G^, inverse FFT along z (in place in T2).
-// Block: W kx-columns x TL threads at one ky (blockIdx.y).
+// zconv: FFT along z, tensor multiply with G^, inverse FFT along z (in place in T2).
+// A block takes W kx-columns of one row ky, or (pair form) of the rows ky and LY - ky, so that
+// both use each spectrum value fetched once.  G^ is stored for all kx, ky <= LY/2 and
+// kz <= LZ/2 ([6][LZ/2+1][LY/2+1][LX]); mirrored ky and kz follow from the parity of each
+// component (xy odd in y, xz odd in z, yz odd in y and z).
 // ---------------------------------------------------------------------------------------
-template <typename T, int LZ>
-__global__ void __launch_bounds__((Geo<T, LZ>::W * Geo<T, LZ>::TL))
+// Variants: V & 2 selects the row pair form (else one row per block).  Values per thread:
+// V0 8 (complex64) / 4 (complex128), V1 twice that, V2 half of V0 (pair), V3 as V0 (pair).
+// Columns per block fill a 128-byte row segment within 1024 (pair: 512) threads per block.
+template <typename T, int L, int V = 0>
+struct GeoZ {
+  static constexpr bool PAIR = (V & 2) != 0;
+  static constexpr int Esm = sizeof(T) == 8 ? 4 : 8;
+  static constexpr int Edef = V == 1 ? 2 * Esm : (V == 2 ? Esm / 2 : Esm);
+  static constexpr int E = L < Edef ? L : Edef;
+  static constexpr int TL = L / E;
+  static constexpr int Wc = 128 / int(sizeof(cx<T>));
+  static constexpr int Wm = (64 / TL) > Wc ? (64 / TL) : Wc;
+  static constexpr int Wl = (65536 / int(L * sizeof(cx<T>))) < 1 ? 1 : (65536 / int(L * sizeof(cx<T>)));
+  static constexpr int Tmax = PAIR ? 512 : 1024;  // the pair form needs more registers
+  static constexpr int Wt = (Tmax / TL) < 1 ? 1 : (Tmax / TL);
+  static constexpr int W1 = Wm < Wl ? Wm : Wl;
+  static constexpr int W = W1 < Wt ? W1 : Wt;
+  static constexpr int ROWS = PAIR ? 2 : 1;
+};
+
+template <typename T, int LZ, int V>
+__global__ void __launch_bounds__((GeoZ<T, LZ, V>::W * GeoZ<T, LZ, V>::TL))
     k_zconv(const MvArgs<T> a) {
-  using G = Geo<T, LZ>;
-  constexpr int E = G::E, TL = G::TL, W = G::W;
+  using G = GeoZ<T, LZ, V>;
+  constexpr int E = G::E, TL = G::TL, W = G::W, R = G::ROWS;
   __shared__ cx<T> lds[W * LZ];
   const int b = blockIdx.z;
   if (retired(a, b)) return;
   const int w = threadIdx.x % W;
   const int t = threadIdx.x / W;
   const int kx = blockIdx.x * W + w;
+  // pair form: rows ky and LY - ky (one row when ky is 0 or LY/2); single form: row ky
   const int ky = blockIdx.y;
+  const int hy = a.LY / 2;
+  const bool two = G::PAIR && ky != 0 && ky != hy;  // block-uniform
+  const int nr = two ? 2 : 1;
+  const int oy = ky > hy ? a.LY - ky : ky;            // stored row of G^
+  const T sy0 = ky > hy ? T(-1) : T(1);                // parity of the first row
   const bool live = kx < a.LX;
   const long ls = long(a.LY) * a.LX;  // z stride
   const long cs = long(a.nz) * ls;
-  cx<T>* buf = a.T2 + b * a.T2_bs + long(ky) * a.LX + kx;
-  cx<T> v[3][E];
+  cx<T>* row[R];
+  row[0] = a.T2 + b * a.T2_bs + long(ky) * a.LX + kx;
+  if constexpr (R == 2) row[1] = a.T2 + b * a.T2_bs + long(two ? a.LY - ky : ky) * a.LX + kx;
+  cx<T> v[R][3][E];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
+  for (int r = 0; r < R; ++r)
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const int z = t + m * TL;
-      v[c][m] = (live && z < a.nz) ? buf[c * cs + z * ls] : cx<T>{0, 0};
-    }
-  }
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int z = t + m * TL;
+        v[r][c][m] = (r < nr && live && z < a.nz) ? row[r][c * cs + z * ls] : cx<T>{0, 0};
+      }
   const LdsInterleaved addr{W, w};
 #pragma unroll
-  for (int c = 0; c < 3; ++c) fft_line<T, LZ, E, false>(v[c], lds, addr, t, a.tw);
-  // octant coordinates and parity signs
-  const int hx = a.LX / 2, hy = a.LY / 2, hz = LZ / 2;
-  const int ox = (live && kx > hx) ? a.LX - kx : (live ? kx : 0);
-  const int oy = ky > hy ? a.LY - ky : ky;
-  const T sx = (live && kx > hx) ? T(-1) : T(1);
-  const T sy = ky > hy ? T(-1) : T(1);
-  const long gps = long(hy + 1) * (hx + 1);
-  const long gcs = long(hz + 1) * gps;
-  const cx<T>* gh = a.ghat + b * a.ghat_bs + long(oy) * (hx + 1) + ox;
+  for (int r = 0; r < R; ++r) {
+    if (r >= nr) break;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) fft_line<T, LZ, E, false>(v[r][c], lds, addr, t, a.tw);
+  }
+  const int hz = LZ / 2;
+  const long gzs = long(hy + 1) * a.LX;  // per kz
+  const long gcs = long(hz + 1) * gzs;   // per component
+  const cx<T>* gh = a.ghat + b * a.ghat_bs + long(oy) * a.LX + (live ? kx : 0);
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int kz = t + m * TL;
     const int oz = kz > hz ? LZ - kz : kz;
     const T sz = kz > hz ? T(-1) : T(1);
-    const cx<T>* g = gh + oz * gps;
-    cx<T> gxx = g[0], gyy = g[gcs], gzz = g[2 * gcs];
-    cx<T> gxy = (sx * sy) * g[3 * gcs];
-    cx<T> gxz = (sx * sz) * g[4 * gcs];
-    cx<T> gyz = (sy * sz) * g[5 * gcs];
-    const cx<T> j0 = v[0][m], j1 = v[1][m], j2 = v[2][m];
-    v[0][m] = gxx * j0 + gxy * j1 + gxz * j2;
-    v[1][m] = gxy * j0 + gyy * j1 + gyz * j2;
-    v[2][m] = gxz * j0 + gyz * j1 + gzz * j2;
+    const cx<T>* g = gh + oz * gzs;
+    const cx<T> gxx = g[0], gyy = g[gcs], gzz = g[2 * gcs];
+    const cx<T> gxy = g[3 * gcs];
+    const cx<T> gxz = sz * g[4 * gcs];
+    const cx<T> gyz = sz * g[5 * gcs];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const T sy = r == 0 ? sy0 : T(-1);  // the mirrored row flips the y-odd components
+      const cx<T> hxy = sy * gxy, hyz = sy * gyz;
+      const cx<T> j0 = v[r][0][m], j1 = v[r][1][m], j2 = v[r][2][m];
+      v[r][0][m] = gxx * j0 + hxy * j1 + gxz * j2;
+      v[r][1][m] = hxy * j0 + gyy * j1 + hyz * j2;
+      v[r][2][m] = gxz * j0 + hyz * j1 + gzz * j2;
+    }
   }
 #pragma unroll
-  for (int c = 0; c < 3; ++c) fft_line<T, LZ, E, true>(v[c], lds, addr, t, a.tw);
+  for (int r = 0; r < R; ++r) {
+    if (r >= nr) break;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) fft_line<T, LZ, E, true>(v[r][c], lds, addr, t, a.tw);
+  }
   if (live) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    for (int r = 0; r < R; ++r) {
+      if (r >= nr) break;
 #pragma unroll
-      for (int m = 0; m < E; ++m) {
-        const int z = t + m * TL;
-        if (z >= a.out_z0 && z < a.out_z1) buf[c * cs + z * ls] = v[c][m];
-      }
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+          const int z = t + m * TL;
+          if (z >= a.out_z0 && z < a.out_z1) row[r][c * cs + z * ls] = v[r][c][m];
+        }
     }
   }
 }
@@ -272,10 +324,10 @@ __global__ void __launch_bounds__((Geo<T, LZ>::W * Geo<T, LZ>::TL))
 // ---------------------------------------------------------------------------------------
 // xinv: inverse FFT along x, crop, combine.  Rows (z, y) for z in [out_z0, out_z1).
 // ---------------------------------------------------------------------------------------
-template <typename T, int LX>
-__global__ void __launch_bounds__((Geo<T, LX>::NL * Geo<T, LX>::TLR))
+template <typename T, int LX, int V>
+__global__ void __launch_bounds__((Geo<T, LX, V>::NL * Geo<T, LX, V>::TLR))
     k_xinv(const MvArgs<T> a) {
-  using G = Geo<T, LX>;
+  using G = Geo<T, LX, V>;
   constexpr int E = G::ER, TL = G::TLR, NL = G::NL;
   __shared__ cx<T> lds[NL * G::LP];
   const int b = blockIdx.z;

@@ -17,10 +17,10 @@ IE_OK, IE_ENOCONV, IE_EINVAL, IE_ENOMEM, IE_EDEVICE, IE_ESTATE = 0, 1, -1, -2, -
 IE_FP64, IE_MIXED = 1, 2
 IE_CONVENTIONAL, IE_CIE, IE_GREEN_ONLY, IE_SCATTER = 0, 1, 2, 3
 IE_GS, IE_JACOBI = 0, 1
-IE_INIT_BACKGROUND, IE_INIT_USER, IE_INIT_LEARNED = 0, 1, 2
+IE_INIT_BACKGROUND, IE_INIT_USER, IE_INIT_LEARNED, IE_INIT_ZERO = 0, 1, 2, 3
 IE_MAG_DIPOLE, IE_ELEC_DIPOLE = 0, 1
 IE_MAX_SWEEPS, IE_MAX_BLOCKS = 128, 16
-IE_OPT_GRAPHS = 1
+IE_OPT_GRAPHS, IE_OPT_AUTOTUNE = 1, 2
 
 
 class ie_grid(C.Structure):
@@ -117,11 +117,15 @@ def lib():
                                        C.POINTER(C.c_float), vp]
         L.ie_nn_gemm.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, i32, vp]
         L.ie_nn_guess.argtypes = [vp, vp, vp, vp, vp, C.POINTER(i32), vp]
+        L.ie_ctx_tuning.argtypes = [vp, C.c_char_p, i32]
+        L.ie_nn_features.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_double), vp]
+        L.ie_nn_target.argtypes = [vp, vp, vp, vp, vp]
         for f in ("ie_green_setup", "ie_ctx_destroy", "ie_background_field", "ie_matvec",
                   "ie_gmres", "ie_dd_solve", "ie_profile_begin", "ie_profile_end",
                   "ie_nn_create", "ie_nn_destroy", "ie_nn_num_params", "ie_nn_get_params",
                   "ie_nn_set_params", "ie_nn_forward", "ie_nn_backward", "ie_nn_train_step",
-                  "ie_nn_gemm", "ie_nn_guess"):
+                  "ie_nn_gemm", "ie_nn_guess", "ie_nn_features", "ie_nn_target",
+                  "ie_ctx_tuning"):
             getattr(L, f).restype = C.c_int
         L.ie_last_error.restype = C.c_char_p
         L.ie_version.restype = C.c_char_p
@@ -258,6 +262,14 @@ def ie_profile_end(cap=256):
     return out
 
 
+def ie_ctx_tuning(ctx):
+    """The autotuner's per-pass decisions for a context (list of dicts)."""
+    import json
+    buf = C.create_string_buffer(1 << 16)
+    _check(lib().ie_ctx_tuning(C.c_void_p(ctx), buf, len(buf)), "ie_ctx_tuning")
+    return json.loads(buf.value.decode())
+
+
 def ie_set_option(option, value):
     return _check(lib().ie_set_option(option, value), "ie_set_option")
 
@@ -324,8 +336,21 @@ def ie_nn_gemm(A, B, Cout, M, N, K, a_trans=0, b_trans=0, splits=1, stream=None)
                                    _stream(stream)), "ie_nn_gemm")
 
 
+def ie_nn_features(ctx, sigma6, b, x, stream=None):
+    """Features into x (bfloat16 [nz, ny, nx, 14]); returns rms(b)."""
+    r = C.c_double(0)
+    _check(lib().ie_nn_features(C.c_void_p(ctx), _ptr(sigma6), _ptr(b), _ptr(x), C.byref(r),
+                                _stream(stream)), "ie_nn_features")
+    return r.value
+
+
+def ie_nn_target(ctx, b, E, y, stream=None):
+    return _check(lib().ie_nn_target(C.c_void_p(ctx), _ptr(b), _ptr(E), _ptr(y), _stream(stream)),
+                  "ie_nn_target")
+
+
 def ie_nn_guess(ctx, nn, sigma6, b, x, stream=None):
-    """Learned guess on the full grid; returns 1 if it replaced the default guess held in x."""
+    """Learned guess on the full grid; returns 1 (learned), 0 (default kept) or 2 (zero)."""
     acc = C.c_int32(0)
     _check(lib().ie_nn_guess(C.c_void_p(ctx), C.c_void_p(nn), _ptr(sigma6), _ptr(b), _ptr(x),
                              C.byref(acc), _stream(stream)), "ie_nn_guess")
