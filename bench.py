@@ -43,6 +43,11 @@ def parse():
     ap.add_argument("--batch-seq", type=int, default=16,
                     help="problems of the logging run also solved one call each (speed-up)")
     ap.add_argument("--profile-json", default=None, help="write the kernel profile here")
+    ap.add_argument("--pmc-calibration", action="store_true",
+                    help="first run the 1 GiB fill and copy kernels that scale the HBM counters")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the matvec on the 128x128x256 grid")
+    ap.add_argument("--no-nn", action="store_true", help="skip the learned-guess comparison")
     return ap.parse_args()
 
 
@@ -63,6 +68,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     ie.lib()
+    if args.pmc_calibration:
+        from paper_2306_17537_amd import traffic
+        traffic.calibrate()
     p = synth.config1()
     nx, ny, nz = p.n
     zb = (0, nz // 2, nz)
@@ -141,6 +149,13 @@ def main():
     dom = kern[0]
     avg_ms = dom["total_ms"] / dom["launches"]
     achieved = dom["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
+    tuning = ie.ie_ctx_tuning(ctx)
+    dom_kernel, traffic_bytes, traffic_src = template_name(dom["name"], tuning, p.n), None, None
+    if dom_kernel:
+        from paper_2306_17537_amd import traffic
+        hit = traffic.lookup(dom_kernel)
+        if hit is not None:
+            traffic_bytes, _, traffic_src = hit[0], hit[1], os.path.relpath(hit[2], ROOT)
     prof_total = sum(k["total_ms"] for k in prof)
     if args.profile_json:
         with open(args.profile_json, "w") as f:
@@ -165,6 +180,7 @@ def main():
                       gbs=round(byts / (t_ms * 1e-3) / 1e9, 1),
                       matvecs_per_s=round(1e3 / t_ms, 1))
     log(f"matvec: {mv}")
+    large = None if args.no_large else matvec_large(ie, torch)
 
     # other forms on the same GPU: plain float64 (the better of full-domain GMRES and DD-GS-A),
     # full-domain mixed GMRES and mixed DD-Jacobi
@@ -211,6 +227,7 @@ def main():
         log(f"plain fp64: {plain}")
         log(f"variants: {variants}")
 
+    learned = None if args.no_nn else learned_bench(ie, torch, ctx, s6, p, ref)
     batch = None if args.no_batch else batch_bench(ie, torch)
 
     cpu = None
@@ -241,7 +258,9 @@ def main():
                    "green_setup_s": round(setup_s, 5), "solves_per_s": round(args.steps / total, 3)},
         "roofline": {"bound": "hbm", "kernel": dom["name"], "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "avg_launch_ms": round(avg_ms, 5),
+                     "traffic": None if traffic_bytes is None else int(traffic_bytes),
+                     "traffic_source": traffic_src, "template": dom_kernel,
+                     "avg_launch_ms": round(avg_ms, 5),
                      "launches": dom["launches"], "bytes_per_launch": int(dom["bytes_per_launch"]),
                      "share_of_profiled_time": round(dom["total_ms"] / prof_total, 3),
                      "measured": "HIP events on the launch stream around every launch, in a "
@@ -249,12 +268,115 @@ def main():
         "cpu_baseline": cpu,
         "plain_fp64": plain,
         "variants": variants,
+        "learned_guess": learned,
         "batch": batch,
         "matvec": mv,
+        "matvec_large": large,
+        "autotune_full_grid": {f"{r['precision']} {r['pass']}": r["variant"] for r in tuning
+                               if r["grid"] == list(p.n)},
         "accuracy": acc,
     }
     print(json.dumps(out))
     ie.ie_ctx_destroy(ctx)
+
+
+PASS_NAMES = {"xfwd": "k_xfwd", "xinv": "k_xinv", "zconv": "k_zconv", "yfwd": "k_colfft",
+              "yinv": "k_colfft"}
+
+
+def template_name(prof_name, tuning, grid):
+    """Kernel template name (as rocprofv3 prints it) of a library profiler entry on the full
+    grid, with the launch variant the autotuner chose, e.g. 'k_zconv<float, 128, 1>'."""
+    parts = prof_name.split()
+    if len(parts) < 3 or parts[0] not in PASS_NAMES:
+        return None
+    prec = parts[1]
+    m = [r for r in tuning if r["grid"] == list(grid) and r["precision"] == prec
+         and r["pass"] == parts[0]]
+    if not m:
+        return None
+    t = "float" if prec == "c64" else "double"
+    dims = parts[2][1:].split("x")
+    if parts[0] in ("yfwd", "yinv"):
+        L = int(dims[0])
+        inv = "true" if parts[0] == "yinv" else "false"
+        return f"k_colfft<{t}, {L}, {inv}, {m[0]['variant']}>"
+    L = int(dims[2]) if parts[0] == "zconv" else int(dims[0])
+    return f"{PASS_NAMES[parts[0]]}<{t}, {L}, {m[0]['variant']}>"
+
+
+def matvec_large(ie, torch):
+    """The operator on the 128x128x256 grid (6-layer model, 2 MHz): the working set of a padded
+    three-component array exceeds the 256 MB last-level cache, so this is the HBM-bound case."""
+    import synth
+    p = synth.config3()
+    nx, ny, nz = p.n
+    g = ie.make_grid(p.n, p.h, p.origin)
+    ctx = ie.ie_green_setup(g, ie.ie_medium(p.sigma0, p.freq, 0.0), None, ie.IE_FP64 | ie.IE_MIXED)
+    s6 = torch.from_numpy(p.sigma6).cuda()
+    out = {}
+    for prec, dt_, nm in ((ie.IE_MIXED, torch.complex64, "c64"), (ie.IE_FP64, torch.complex128, "fp64")):
+        x = torch.randn((3, nz, ny, nx), dtype=dt_, device="cuda:0")
+        y = torch.empty_like(x)
+        ie.ie_matvec(ctx, s6, x, y, ie.IE_CIE, prec)
+        torch.cuda.synchronize()
+        ie.ie_profile_begin()
+        reps = 10
+        for _ in range(reps):
+            ie.ie_matvec(ctx, s6, x, y, ie.IE_CIE, prec)
+        pr = ie.ie_profile_end()
+        passes = {k["name"].split()[0]: k for k in pr
+                  if k["name"].split()[0] in ("xfwd", "yfwd", "zconv", "yinv", "xinv")}
+        t_ms = sum(k["total_ms"] for k in passes.values()) / reps
+        byts = sum(k["bytes_per_launch"] * k["launches"] for k in passes.values()) / reps
+        out[nm] = dict(us=round(1e3 * t_ms, 1), algorithmic_bytes=int(byts),
+                       gbs=round(byts / (t_ms * 1e-3) / 1e9, 1),
+                       frac=round(byts / (t_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       passes_us={n: round(1e3 * k["total_ms"] / k["launches"], 1)
+                                  for n, k in passes.items()})
+        del x, y
+    ie.ie_ctx_destroy(ctx)
+    out["workload"] = "config3 grid 128x128x256 (seed 303), contraction-form operator, 10 launches"
+    log(f"matvec large: {out}")
+    return out
+
+
+def learned_bench(ie, torch, ctx, s6, p, ref):
+    """The same full-domain mixed solve from a zero start and from the trained network's guess
+    (judged by one zero-start restart cycle; both judge cycles counted)."""
+    from paper_2306_17537_amd import guess
+    nn = guess.create()
+    nx, ny, nz = p.n
+    E0 = torch.empty((3, nz, ny, nx), dtype=torch.complex128, device="cuda:0")
+    out = {}
+    try:
+        for name in ("zero", "learned"):
+            ts, its, used = [], 0, 0
+            for _ in range(3):
+                x = torch.zeros_like(E0)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                ie.ie_background_field(ctx, p.sources, E0)
+                if name == "learned":
+                    used = guess.solve_learned_start(ctx, nn, s6, E0, x)
+                _, st = ie.ie_gmres(ctx, s6, E0, x, tol=1e-6, precision=ie.IE_MIXED,
+                                    form=ie.IE_CIE)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t)
+                its = st.its + (20 if name == "learned" else 0)
+            err = None
+            if ref is not None:
+                err = float(np.linalg.norm((x - E0).cpu().numpy() - ref) / np.linalg.norm(ref))
+            out[name] = dict(s=round(float(np.median(ts)), 5), its=int(its), Ea_rel_err=err)
+            if name == "learned":
+                out[name]["learned_start_won_judge"] = int(used)
+    finally:
+        ie.ie_nn_destroy(nn)
+    out["network"] = "3-D encoder-decoder, 4 levels, base 32 channels, BF16 MFMA (weights in " \
+                     "paper_2306_17537_amd/weights, trained on 2000 solver-generated 32^3 blocks)"
+    out["gain"] = round(out["zero"]["s"] / out["learned"]["s"], 3)
+    log(f"learned guess: {out}")
+    return out
 
 
 def batch_bench(ie, torch):

@@ -65,7 +65,7 @@ extern "C" {
 /* initial guess of ie_dd_solve */
 #define IE_INIT_BACKGROUND 0  /* E := E0, as Alg. 1 */
 #define IE_INIT_USER       1  /* E_total holds the initial guess on entry (resume) */
-#define IE_INIT_LEARNED    2  /* first-sweep block guesses from a trained network (ie_nn_*) */
+#define IE_INIT_LEARNED    2  /* E := 0, first-sweep block guesses from a trained network (ie_nn_*) */
 #define IE_INIT_ZERO       3  /* E := 0 (first sweep: zero coupling and zero block starts) */
 
 /* source kinds */
@@ -285,21 +285,33 @@ int ie_nn_gemm(const uint16_t* A, const uint16_t* B, float* C, int32_t M, int32_
  * Solver features and targets on the context's full grid (nx*ny*nz = N cells).
  * ie_nn_features: x (DEVICE BF16 [N][14]) from sigma6 (DEVICE float64 [6][N]) and the
  * right-hand side b (DEVICE complex128 [3][N]): channels 0-5 the contraction-form tensor
- * I - 2 sigma0 (sigma + sigma0 I)^-1 (xx, yy, zz, xy, xz, yz), 6-11 re/im of b / rms(b) for
- * x, y, z, 12-13 re/im of k0 h; rms(b) = ||b|| / sqrt(3N) goes to *rms (HOST, nullable).
- * ie_nn_target: y (DEVICE float32 [N][6]) = re/im of (E - b) / rms(b).
+ * I - 2 sigma0 (sigma + sigma0 I)^-1 (xx, yy, zz, xy, xz, yz), 6-11 re/im of
+ * b e^{-i phi} / rms(b) for x, y, z, 12-13 re/im of k0 h, with rms(b) = ||b|| / sqrt(3N) and
+ * phi = arg(sum b.b) / 2 (unconjugated sum), so that a global phase of b does not change the
+ * features; rms(b) goes to *rms (HOST, nullable).
+ * ie_nn_target: y (DEVICE float32 [N][6]) = re/im of (E - b) e^{-i phi} / rms(b).
  * Both synchronise with `stream`.
  */
 int ie_nn_features(ie_ctx* ctx, const double* sigma6, const void* b, uint16_t* x, double* rms,
                    void* stream);
 int ie_nn_target(ie_ctx* ctx, const void* b, const void* E, float* y, void* stream);
 /*
+ * The network's guess for (I - G dsigma) x = b on the context's full grid, unjudged:
+ * x = b + rms(b) e^{i phi} network(features) (DEVICE complex128 [3][N]).  Synchronises.
+ */
+int ie_nn_predict(ie_ctx* ctx, ie_nn* nn, const double* sigma6, const void* b, void* x,
+                  void* stream);
+/*
  * Learned initial guess for (I - G dsigma) x = b on the context's full grid:
- * x_nn = b + rms(b) * network(features).  x (DEVICE complex128, in: default guess, out: chosen
- * guess) becomes whichever of x_nn, the default guess and zero has the smallest float64
+ * x_nn = b + rms(b) e^{i phi} network(features).  x (DEVICE complex128, in: default guess, out:
+ * chosen guess) becomes whichever of x_nn, the default guess and zero has the smallest float64
  * residual ||b - (I - G dsigma) x||; *accepted (HOST, nullable) = 1 learned, 0 default, 2 zero.
- * ie_dd_solve with init = IE_INIT_LEARNED applies the same choice to every block of the first
- * sweep (the network must then divide each block's grid).  Synchronises with `stream`.
+ * Synchronises with `stream`.
+ * ie_dd_solve with init = IE_INIT_LEARNED uses the network in the first sweep: for every block
+ * it runs one restart cycle of the inner GMRES from x_nn and one from the default start and
+ * continues from whichever reached the smaller residual (both cycles count in the statistics;
+ * learned_used counts the blocks that continued from x_nn).  The network must divide each
+ * block's grid.
  */
 int ie_nn_guess(ie_ctx* ctx, ie_nn* nn, const double* sigma6, const void* b, void* x,
                 int32_t* accepted, void* stream);

@@ -256,7 +256,7 @@ int dd_group(ie_ctx* c, const std::vector<int>& idx, const ie_problem* problems,
     IE_LAUNCH_CHECK();
     IE_TRY(launch_background(gr.nx, gr.ny, gr.nz, gr.h, gr.origin, c->med, pr.sources,
                              pr.nsources, g.E0 + b * 3 * N, s));
-    if (o.init == IE_INIT_ZERO) {
+    if (o.init == IE_INIT_ZERO || o.init == IE_INIT_LEARNED) {
       IE_HIP(hipMemsetAsync(g.E + b * 3 * N, 0, sizeof(c128) * 3 * N, s));
     } else {
       const c128* init = o.init == IE_INIT_USER ? (const c128*)pr.E_total : g.E0 + b * 3 * N;
@@ -296,7 +296,7 @@ int dd_group(ie_ctx* c, const std::vector<int>& idx, const ie_problem* problems,
   c128* x = gb.x.as<c128>();
   std::vector<double> tols(B);
   std::vector<GmResult> res(B);
-  std::vector<int> accepted(B);
+  std::vector<GmResult> pre(B);  // the judge's cycles in the first sweep of a learned start
   const double inf = std::numeric_limits<double>::infinity();
   bool first = true;
 
@@ -326,12 +326,32 @@ int dd_group(ie_ctx* c, const std::vector<int>& idx, const ie_problem* problems,
         tols[b] = live ? (o.adaptive ? e[b] / 10.0 : o.inner_tol_fixed) : inf;
         solve = solve || live;
       }
+      std::fill(pre.begin(), pre.end(), GmResult{});
       if (solve && first && o.init == IE_INIT_LEARNED) {
-        // first sweep: learned guesses, judged against the default and a zero start
-        IE_TRY(nn_guess_blocks((ie_nn*)o.nn, c, *c->block_plan(nzb), g.D64 + long(z0) * plane, N,
-                               6 * N, rhs, x, B, accepted.data(), s));
-        for (int b = 0; b < B; ++b)
-          if (act[b] && has[b][i] && accepted[b] == 1) stats[idx[b]].learned_used += 1;
+        // first sweep: one restart cycle of GMRES from the learned guess and one from the
+        // default start; each block continues from whichever reached the smaller residual
+        Plan& BP = *c->block_plan(nzb);
+        IE_TRY(gb.xl.ensure(sizeof(c128) * 3 * nb * B));
+        c128* xl = gb.xl.as<c128>();
+        IE_TRY(nn_predict_blocks((ie_nn*)o.nn, c, BP, g.D64 + long(z0) * plane, N, 6 * N, rhs, xl,
+                                 B, s));
+        ie_gmres_opts one = o.inner;
+        one.max_its = o.inner.restart;
+        std::vector<GmResult> rl(B), rd(B);
+        IE_TRY(block_solve(g, BP, z0, rhs, xl, tols.data(), one, rl.data()));
+        IE_TRY(block_solve(g, BP, z0, rhs, x, tols.data(), one, rd.data()));
+        for (int b = 0; b < B; ++b) {
+          if (!(act[b] && has[b][i])) continue;
+          pre[b].its = rl[b].its + rd[b].its;
+          pre[b].mv64 = rl[b].mv64 + rd[b].mv64;
+          pre[b].mv32 = rl[b].mv32 + rd[b].mv32;
+          pre[b].graph_cycles = rl[b].graph_cycles + rd[b].graph_cycles;
+          if (rl[b].relres < rd[b].relres) {
+            stats[idx[b]].learned_used += 1;
+            IE_HIP(hipMemcpyAsync(x + b * 3 * nb, xl + b * 3 * nb, sizeof(c128) * 3 * nb,
+                                  hipMemcpyDeviceToDevice, s));
+          }
+        }
       }
       if (solve)
         IE_TRY(block_solve(g, *c->block_plan(nzb), z0, rhs, x, tols.data(), o.inner, res.data()));
@@ -346,10 +366,10 @@ int dd_group(ie_ctx* c, const std::vector<int>& idx, const ie_problem* problems,
         st.full_matvecs += 1;
         st.matvecs64 += 1;
         if (has[b][i]) {
-          st.block_its[sweeps[b]][i] = res[b].its;
-          st.matvecs64 += res[b].mv64;
-          st.matvecs32 += res[b].mv32;
-          st.graph_cycles += res[b].graph_cycles;
+          st.block_its[sweeps[b]][i] = res[b].its + pre[b].its;
+          st.matvecs64 += res[b].mv64 + pre[b].mv64;
+          st.matvecs32 += res[b].mv32 + pre[b].mv32;
+          st.graph_cycles += res[b].graph_cycles + pre[b].graph_cycles;
         }
       }
     }

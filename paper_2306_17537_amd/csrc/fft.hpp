@@ -190,4 +190,78 @@ __device__ __forceinline__ void fft_line(cx<T> (&v)[E], cx<T>* lds, Addr addr, i
                            std::make_integer_sequence<int, num_stages<L, E>()>{});
 }
 
+// The same FFT for NC lines held by one thread (v[c], c < NC), in lockstep: the twiddles of
+// each stage are loaded once and applied to every line, and the lines go through LDS one after
+// the other (one line of LDS space).
+template <typename T, int L, int E, int S, bool INV, int NC, typename Addr>
+__device__ __forceinline__ void fft_stage_multi(cx<T> (&v)[NC][E], cx<T>* __restrict__ lds,
+                                                Addr addr, int t,
+                                                const cx<T>* __restrict__ tw) {
+  constexpr int R = stage_radix<L, E>(S);
+  constexpr int NS = stage_ns<L, E>(S);
+  constexpr int TL = L / E;
+  constexpr int NB = E / R;
+  constexpr bool LAST = (S == num_stages<L, E>() - 1);
+  static_assert(E % R == 0, "radix must divide the register width");
+  cx<T> w[NB][R];
+  if constexpr (NS > 1) {
+    constexpr int step = TW_N / (NS * R);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int k = (t + b * TL) & (NS - 1);
+#pragma unroll
+      for (int r = 1; r < R; ++r) w[b][r] = twiddle<T, INV>(tw, r * k * step);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    cx<T> out[E];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      cx<T> u[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) u[r] = v[c][b + r * NB];
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) u[r] = u[r] * w[b][r];
+      }
+      Dft<T, R, INV>::run(u);
+#pragma unroll
+      for (int r = 0; r < R; ++r) out[b + r * NB] = u[r];
+    }
+    if constexpr (LAST) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[c][m] = out[m];
+    } else {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int j = t + b * TL;
+        const int k = j & (NS - 1);
+        const int base = (j / NS) * NS * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[addr(base + r * NS)] = out[b + r * NB];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[c][m] = lds[addr(t + m * TL)];
+      __syncthreads();
+    }
+  }
+}
+
+template <typename T, int L, int E, bool INV, int NC, typename Addr, int... S>
+__device__ __forceinline__ void fft_stages_multi(cx<T> (&v)[NC][E], cx<T>* lds, Addr addr, int t,
+                                                 const cx<T>* tw,
+                                                 std::integer_sequence<int, S...>) {
+  (fft_stage_multi<T, L, E, S, INV, NC>(v, lds, addr, t, tw), ...);
+}
+
+template <typename T, int L, int E, bool INV, int NC, typename Addr>
+__device__ __forceinline__ void fft_lines(cx<T> (&v)[NC][E], cx<T>* lds, Addr addr, int t,
+                                          const cx<T>* __restrict__ tw) {
+  static_assert(L % E == 0 && L <= MAX_FFT_LEN, "bad FFT length");
+  fft_stages_multi<T, L, E, INV, NC>(v, lds, addr, t, tw,
+                                     std::make_integer_sequence<int, num_stages<L, E>()>{});
+}
+
 }  // namespace ie

@@ -324,11 +324,12 @@ __global__ void k_to_bf16(const float* __restrict__ a, u16* __restrict__ b, long
 
 // Network input for one block, 14 channels: the contraction-form tensor
 // I - 2 sigma0 (dsigma + 2 sigma0 I)^-1 (bounded in (-1, 1); xx, yy, zz, xy, xz, yz), the field
-// b / rms(b) (re, im of x, y, z) and k0 h (re, im).  D: float64 dsigma [6][nb] with component
-// stride cs; b: complex128 [3][nb]; output BF16 channels-last [nb][14].
+// b e^{-i phi} / rms(b) (re, im of x, y, z) and k0 h (re, im).  phi = arg(sum b.b) / 2 fixes the
+// global phase (b -> b e^{i a} leaves the features unchanged), rot = e^{-i phi}.  D: float64
+// dsigma [6][nb] with component stride cs; b: complex128 [3][nb]; output BF16 [nb][14].
 __global__ void k_features(const double* __restrict__ D, long cs, const c128* __restrict__ b,
-                           long nb, double sigma0, double inv_rms, double k0h_re, double k0h_im,
-                           u16* __restrict__ x) {
+                           long nb, double sigma0, double inv_rms, c128 rot, double k0h_re,
+                           double k0h_im, u16* __restrict__ x) {
   for (long i = long(blockIdx.x) * blockDim.x + threadIdx.x; i < nb;
        i += long(gridDim.x) * blockDim.x) {
     const double t = 2.0 * sigma0;
@@ -348,36 +349,62 @@ __global__ void k_features(const double* __restrict__ D, long cs, const c128* __
     o[5] = f2bf(float(-f * cyz));
     for (int c = 0; c < 3; ++c) {
       const c128 v = b[c * nb + i];
-      o[6 + 2 * c] = f2bf(float(v.re * inv_rms));
-      o[7 + 2 * c] = f2bf(float(v.im * inv_rms));
+      o[6 + 2 * c] = f2bf(float((v.re * rot.re - v.im * rot.im) * inv_rms));
+      o[7 + 2 * c] = f2bf(float((v.re * rot.im + v.im * rot.re) * inv_rms));
     }
     o[12] = f2bf(float(k0h_re));
     o[13] = f2bf(float(k0h_im));
   }
 }
 
-// training target: y = (E - b) / rms(b), float32 channels-last [nb][6]
+// training target: y = (E - b) e^{-i phi} / rms(b), float32 channels-last [nb][6]
 __global__ void k_target(const c128* __restrict__ b, const c128* __restrict__ E, long nb,
-                         double inv_rms, float* __restrict__ y) {
+                         double inv_rms, c128 rot, float* __restrict__ y) {
   for (long i = long(blockIdx.x) * blockDim.x + threadIdx.x; i < nb;
        i += long(gridDim.x) * blockDim.x)
     for (int c = 0; c < 3; ++c) {
       const c128 v = b[c * nb + i], e = E[c * nb + i];
-      y[i * 6 + 2 * c] = float((e.re - v.re) * inv_rms);
-      y[i * 6 + 2 * c + 1] = float((e.im - v.im) * inv_rms);
+      const double dr = e.re - v.re, di = e.im - v.im;
+      y[i * 6 + 2 * c] = float((dr * rot.re - di * rot.im) * inv_rms);
+      y[i * 6 + 2 * c + 1] = float((dr * rot.im + di * rot.re) * inv_rms);
     }
 }
 
-// x0 = b + rms (y_re + i y_im) per component (the network predicts E - b, scaled by 1 / rms)
+// x0 = b + rms e^{i phi} (y_re + i y_im) per component; urot = rms e^{i phi}
 __global__ void k_apply_guess(const c128* __restrict__ b, const float* __restrict__ y, long nb,
-                              double rms, c128* __restrict__ x0) {
+                              c128 urot, c128* __restrict__ x0) {
   for (long i = long(blockIdx.x) * blockDim.x + threadIdx.x; i < nb;
        i += long(gridDim.x) * blockDim.x)
     for (int c = 0; c < 3; ++c) {
       const c128 v = b[c * nb + i];
-      x0[c * nb + i] = c128{v.re + rms * double(y[i * 6 + 2 * c]),
-                            v.im + rms * double(y[i * 6 + 2 * c + 1])};
+      const double yr = y[i * 6 + 2 * c], yi = y[i * 6 + 2 * c + 1];
+      x0[c * nb + i] = c128{v.re + urot.re * yr - urot.im * yi, v.im + urot.re * yi + urot.im * yr};
     }
+}
+
+// per-block partial sums of b.b (unconjugated) over [3][nb] for `batch` vectors: part[b][g]
+__global__ void __launch_bounds__(256) k_sumsq(const c128* __restrict__ v, long n,
+                                               c128* __restrict__ part) {
+  __shared__ double sr[256], si[256];
+  const int b = blockIdx.y;
+  const c128* p = v + long(b) * n;
+  double re = 0, im = 0;
+  for (long i = long(blockIdx.x) * 256 + threadIdx.x; i < n; i += long(gridDim.x) * 256) {
+    const c128 z = p[i];
+    re += z.re * z.re - z.im * z.im;
+    im += 2.0 * z.re * z.im;
+  }
+  sr[threadIdx.x] = re;
+  si[threadIdx.x] = im;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) {
+      sr[threadIdx.x] += sr[threadIdx.x + k];
+      si[threadIdx.x] += si[threadIdx.x + k];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[long(b) * gridDim.x + blockIdx.x] = c128{sr[0], si[0]};
 }
 
 // grid for the element-wise grid-stride kernels (x extent times 256 stays below 2^32)
@@ -413,6 +440,7 @@ struct ie_nn {
   std::vector<DevBuf> pooled;               // pooled inputs per level >= 1
   DevBuf gcur, gtmp, gsk[8], g16, gmask, dcol, part, mse_part, gy;
   DevBuf xg, res;          // learned guesses and their residuals
+  DevBuf sq;               // partial sums for the phase of the right-hand side
   bool keep_cols = true;  // training keeps every layer's im2col for the backward pass
   DevBuf icol;            // shared im2col buffer for inference
   std::vector<double> hpart;
@@ -862,38 +890,74 @@ int forward_chunked(ie_nn* n, const u16* x, int batch, int nz, int ny, int nx, f
   return IE_OK;
 }
 
+// rms(b) = ||b|| / sqrt(3 nb) and the phase rotation e^{-i phi}, phi = arg(sum b.b) / 2, for
+// `batch` vectors b [batch][3][nb] (fixed-order reductions; synchronises)
+int scale_and_phase(const c128* b, long nb, int batch, DevBuf& sq, KrylovWork& w, hipStream_t s,
+                    std::vector<double>& rms, std::vector<c128>& rot) {
+  rms.resize(batch);
+  rot.resize(batch);
+  IE_TRY(norms_host(b, 3 * nb, batch, rms.data(), w, s));
+  const int G = int(std::min<long>(256, ceil_div(3 * nb, 256)));
+  IE_TRY(sq.ensure(sizeof(c128) * G * batch));
+  hipLaunchKernelGGL(k_sumsq, dim3(G, batch), dim3(256), 0, s, b, 3 * nb, sq.as<c128>());
+  IE_LAUNCH_CHECK();
+  std::vector<c128> h(size_t(G) * batch);
+  IE_HIP(hipMemcpyAsync(h.data(), sq.p, sizeof(c128) * G * batch, hipMemcpyDeviceToHost, s));
+  IE_HIP(hipStreamSynchronize(s));
+  for (int q = 0; q < batch; ++q) {
+    double re = 0, im = 0;
+    for (int g = 0; g < G; ++g) {
+      re += h[size_t(q) * G + g].re;
+      im += h[size_t(q) * G + g].im;
+    }
+    const double phi = (re == 0 && im == 0) ? 0.0 : 0.5 * std::atan2(im, re);
+    rot[q] = c128{std::cos(phi), -std::sin(phi)};
+    rms[q] = rms[q] / std::sqrt(3.0 * double(nb));
+  }
+  return IE_OK;
+}
+
 }  // namespace
 
-int nn_guess_blocks(ie_nn* n, ie_ctx* c, Plan& B, const double* D, long d_cs, long d_bs,
-                    const c128* rhs, c128* x, int batch, int* accepted, hipStream_t s) {
+int nn_predict_blocks(ie_nn* n, ie_ctx* c, Plan& B, const double* D, long d_cs, long d_bs,
+                      const c128* rhs, c128* xg, int batch, hipStream_t s) {
   const long nb = B.ncell();
   IE_TRY(nn_check_shape(n, B.nz, B.ny, B.nx));
-  std::vector<double> bn(batch), rl(batch), rd(batch);
-  IE_TRY(norms_host(rhs, 3 * nb, batch, bn.data(), c->kw_blk, s));
+  std::vector<double> rms;
+  std::vector<c128> rot;
+  IE_TRY(scale_and_phase(rhs, nb, batch, n->sq, c->kw_blk, s, rms, rot));
   IE_TRY(n->x16.ensure(sizeof(u16) * 14 * nb * batch));
   double kr, ki;
   k0h(c, &kr, &ki);
   for (int b = 0; b < batch; ++b) {
-    const double rms = bn[b] / std::sqrt(3.0 * double(nb));
     hipLaunchKernelGGL(k_features, dim3(grid1(nb)), dim3(256), 0, s, D + b * d_bs, d_cs,
-                       rhs + b * 3 * nb, nb, c->med.sigma0, rms > 0 ? 1.0 / rms : 0.0, kr, ki,
-                       n->x16.as<u16>() + b * 14 * nb);
+                       rhs + b * 3 * nb, nb, c->med.sigma0, rms[b] > 0 ? 1.0 / rms[b] : 0.0,
+                       rot[b], kr, ki, n->x16.as<u16>() + b * 14 * nb);
     IE_LAUNCH_CHECK();
   }
   IE_TRY(n->gy.ensure(sizeof(float) * 6 * nb * batch));
   IE_TRY(forward_chunked(n, n->x16.as<u16>(), batch, B.nz, B.ny, B.nx, n->gy.as<float>(), s));
+  for (int b = 0; b < batch; ++b) {
+    const c128 urot{rms[b] * rot[b].re, -rms[b] * rot[b].im};  // rms e^{i phi}
+    hipLaunchKernelGGL(k_apply_guess, dim3(grid1(nb)), dim3(256), 0, s, rhs + b * 3 * nb,
+                       n->gy.as<float>() + b * 6 * nb, nb, urot, xg + b * 3 * nb);
+    IE_LAUNCH_CHECK();
+  }
+  return IE_OK;
+}
+
+int nn_guess_blocks(ie_nn* n, ie_ctx* c, Plan& B, const double* D, long d_cs, long d_bs,
+                    const c128* rhs, c128* x, int batch, int* accepted, hipStream_t s) {
+  const long nb = B.ncell();
   IE_TRY(n->xg.ensure(sizeof(c128) * 3 * nb * batch));
   IE_TRY(n->res.ensure(sizeof(c128) * 3 * nb * batch));
   c128* xg = n->xg.as<c128>();
   c128* r = n->res.as<c128>();
-  for (int b = 0; b < batch; ++b) {
-    const double rms = bn[b] / std::sqrt(3.0 * double(nb));
-    hipLaunchKernelGGL(k_apply_guess, dim3(grid1(nb)), dim3(256), 0, s, rhs + b * 3 * nb,
-                       n->gy.as<float>() + b * 6 * nb, nb, rms, xg + b * 3 * nb);
-    IE_LAUNCH_CHECK();
-  }
+  IE_TRY(nn_predict_blocks(n, c, B, D, d_cs, d_bs, rhs, xg, batch, s));
   // judge: float64 residuals ||rhs - (I - G dsigma) x|| of the learned and the default guess;
   // a zero start has residual ||rhs||
+  std::vector<double> bn(batch), rl(batch), rd(batch);
+  IE_TRY(norms_host(rhs, 3 * nb, batch, bn.data(), c->kw_blk, s));
   OpDesc op;
   op.form = IE_CONVENTIONAL;
   op.M64 = D;
@@ -930,16 +994,18 @@ int ie_nn_features(ie_ctx* ctx, const double* sigma6, const void* b, uint16_t* x
   hipStream_t s = (hipStream_t)stream;
   const long N = ctx->full->ncell();
   IE_TRY(prepare_contrast(ctx, sigma6, IE_CONVENTIONAL, s));
-  double bn = 0;
-  IE_TRY(norms_host((const c128*)b, 3 * N, 1, &bn, ctx->kw, s));
-  const double r = bn / std::sqrt(3.0 * double(N));
+  DevBuf sq;
+  std::vector<double> r;
+  std::vector<c128> rot;
+  IE_TRY(scale_and_phase((const c128*)b, N, 1, sq, ctx->kw, s, r, rot));
   double kr, ki;
   k0h(ctx, &kr, &ki);
   hipLaunchKernelGGL(k_features, dim3(grid1(N)), dim3(256), 0, s, ctx->M64.as<const double>(), N,
-                     (const c128*)b, N, ctx->med.sigma0, r > 0 ? 1.0 / r : 0.0, kr, ki, x);
+                     (const c128*)b, N, ctx->med.sigma0, r[0] > 0 ? 1.0 / r[0] : 0.0, rot[0], kr,
+                     ki, x);
   IE_LAUNCH_CHECK();
   IE_HIP(hipStreamSynchronize(s));
-  if (rms) *rms = r;
+  if (rms) *rms = r[0];
   return IE_OK;
 }
 
@@ -948,12 +1014,27 @@ int ie_nn_target(ie_ctx* ctx, const void* b, const void* E, float* y, void* stre
     return fail(IE_EINVAL, "NULL argument");
   hipStream_t s = (hipStream_t)stream;
   const long N = ctx->full->ncell();
-  double bn = 0;
-  IE_TRY(norms_host((const c128*)b, 3 * N, 1, &bn, ctx->kw, s));
-  const double r = bn / std::sqrt(3.0 * double(N));
+  DevBuf sq;
+  std::vector<double> r;
+  std::vector<c128> rot;
+  IE_TRY(scale_and_phase((const c128*)b, N, 1, sq, ctx->kw, s, r, rot));
   hipLaunchKernelGGL(k_target, dim3(grid1(N)), dim3(256), 0, s, (const c128*)b, (const c128*)E, N,
-                     r > 0 ? 1.0 / r : 0.0, y);
+                     r[0] > 0 ? 1.0 / r[0] : 0.0, rot[0], y);
   IE_LAUNCH_CHECK();
+  IE_HIP(hipStreamSynchronize(s));
+  return IE_OK;
+}
+
+int ie_nn_predict(ie_ctx* ctx, ie_nn* n, const double* sigma6, const void* b, void* x,
+                  void* stream) {
+  if (ctx == nullptr || n == nullptr || sigma6 == nullptr || b == nullptr || x == nullptr)
+    return fail(IE_EINVAL, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  Plan& F = *ctx->full;
+  IE_TRY(nn_check_shape(n, F.nz, F.ny, F.nx));
+  IE_TRY(prepare_contrast(ctx, sigma6, IE_CONVENTIONAL, s));
+  IE_TRY(nn_predict_blocks(n, ctx, F, ctx->M64.as<const double>(), F.ncell(), 6 * F.ncell(),
+                           (const c128*)b, (c128*)x, 1, s));
   IE_HIP(hipStreamSynchronize(s));
   return IE_OK;
 }

@@ -270,12 +270,10 @@ __global__ void __launch_bounds__((GeoZ<T, LZ, V>::W * GeoZ<T, LZ, V>::TL))
         v[r][c][m] = (r < nr && live && z < a.nz) ? row[r][c * cs + z * ls] : cx<T>{0, 0};
       }
   const LdsInterleaved addr{W, w};
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    if (r >= nr) break;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) fft_line<T, LZ, E, false>(v[r][c], lds, addr, t, a.tw);
-  }
+  // all lines of the block in lockstep (twiddles loaded once per stage); a single row in the
+  // pair form transforms zeros in place of its missing mirror row
+  auto& lines = reinterpret_cast<cx<T>(&)[R * 3][E]>(v);
+  fft_lines<T, LZ, E, false, R * 3>(lines, lds, addr, t, a.tw);
   const int hz = LZ / 2;
   const long gzs = long(hy + 1) * a.LX;  // per kz
   const long gcs = long(hz + 1) * gzs;   // per component
@@ -300,12 +298,7 @@ __global__ void __launch_bounds__((GeoZ<T, LZ, V>::W * GeoZ<T, LZ, V>::TL))
       v[r][2][m] = gxz * j0 + hyz * j1 + gzz * j2;
     }
   }
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    if (r >= nr) break;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) fft_line<T, LZ, E, true>(v[r][c], lds, addr, t, a.tw);
-  }
+  fft_lines<T, LZ, E, true, R * 3>(lines, lds, addr, t, a.tw);
   if (live) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {

@@ -117,6 +117,7 @@ def lib():
                                        C.POINTER(C.c_float), vp]
         L.ie_nn_gemm.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, i32, vp]
         L.ie_nn_guess.argtypes = [vp, vp, vp, vp, vp, C.POINTER(i32), vp]
+        L.ie_nn_predict.argtypes = [vp, vp, vp, vp, vp, vp]
         L.ie_ctx_tuning.argtypes = [vp, C.c_char_p, i32]
         L.ie_nn_features.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_double), vp]
         L.ie_nn_target.argtypes = [vp, vp, vp, vp, vp]
@@ -124,7 +125,7 @@ def lib():
                   "ie_gmres", "ie_dd_solve", "ie_profile_begin", "ie_profile_end",
                   "ie_nn_create", "ie_nn_destroy", "ie_nn_num_params", "ie_nn_get_params",
                   "ie_nn_set_params", "ie_nn_forward", "ie_nn_backward", "ie_nn_train_step",
-                  "ie_nn_gemm", "ie_nn_guess", "ie_nn_features", "ie_nn_target",
+                  "ie_nn_gemm", "ie_nn_guess", "ie_nn_features", "ie_nn_target", "ie_nn_predict",
                   "ie_ctx_tuning"):
             getattr(L, f).restype = C.c_int
         L.ie_last_error.restype = C.c_char_p
@@ -347,6 +348,12 @@ def ie_nn_features(ctx, sigma6, b, x, stream=None):
 def ie_nn_target(ctx, b, E, y, stream=None):
     return _check(lib().ie_nn_target(C.c_void_p(ctx), _ptr(b), _ptr(E), _ptr(y), _stream(stream)),
                   "ie_nn_target")
+
+
+def ie_nn_predict(ctx, nn, sigma6, b, x, stream=None):
+    """The network's (unjudged) guess for the full grid into x."""
+    return _check(lib().ie_nn_predict(C.c_void_p(ctx), C.c_void_p(nn), _ptr(sigma6), _ptr(b),
+                                      _ptr(x), _stream(stream)), "ie_nn_predict")
 
 
 def ie_nn_guess(ctx, nn, sigma6, b, x, stream=None):

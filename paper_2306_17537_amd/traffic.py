@@ -1,0 +1,146 @@
+"""HBM traffic per kernel launch from two rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE).
+
+Both counters are reported in KiB per dispatch but do not read one-to-one on this GPU, so each is
+scaled by what it reads for a kernel of known traffic run in the same process: a 1 GiB fill
+(writes 1 GiB, reads nothing) for WRITE_SIZE and a 1 GiB device-to-device copy (reads 1 GiB) for
+FETCH_SIZE.  ``calibrate()`` issues both; bench.py runs it first under ``--pmc-calibration``.
+
+Summaries are written as markdown with one machine-readable line per kernel variant:
+    traffic-json: {"kernel": ..., "fetch_bytes": ..., "write_bytes": ..., "sources": ...}
+``sources`` is a hash of the kernel source files at measurement time; ``lookup()`` returns
+nothing once the sources have changed, so a stale figure is never reported.
+
+Usage (from the repository root, after the two profiler runs):
+    python -m paper_2306_17537_amd.traffic summarize --fetch DIR1 --write DIR2 \\
+        --kernel 'k_zconv<float, 128' --out profiles/NAME.md --command '...'
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+import statistics
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(_HERE)
+CAL_BYTES = 1 << 30
+KERNEL_SOURCES = ("csrc/passes.hpp", "csrc/fft.hpp", "csrc/operator.hip")
+
+
+def sources_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(_HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def calibrate():
+    """1 GiB fill and 1 GiB copy on the current device (for the counter scale factors)."""
+    import torch
+    a = torch.empty(CAL_BYTES // 4, dtype=torch.float32, device="cuda:0")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    torch.cuda.empty_cache()
+
+
+def _rows(directory):
+    paths = glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)
+    if not paths:
+        raise FileNotFoundError(f"no counter_collection.csv under {directory}")
+    out = []
+    with open(paths[0]) as f:
+        for r in csv.DictReader(f):
+            out.append((r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"])))
+    return out
+
+
+def _factor(rows, counter, pattern):
+    vals = [v for k, c, v in rows if c == counter and re.search(pattern, k)]
+    if not vals:
+        raise ValueError(f"calibration kernel /{pattern}/ not found for {counter}")
+    kib = max(vals)  # the 1 GiB dispatch is the largest of its kind
+    return CAL_BYTES / (kib * 1024.0)
+
+
+def summarize(fetch_dir, write_dir, kernel):
+    """Per variant of `kernel` (a prefix of the demangled name): median scaled bytes/launch."""
+    fr, wr = _rows(fetch_dir), _rows(write_dir)
+    ff = _factor(fr, "FETCH_SIZE", r"copyBuffer")
+    wf = _factor(wr, "WRITE_SIZE", r"FillFunctor")
+    res = {}
+    for rows, counter, fac, key in ((fr, "FETCH_SIZE", ff, "fetch_bytes"),
+                                    (wr, "WRITE_SIZE", wf, "write_bytes")):
+        per = {}
+        for k, c, v in rows:
+            if c != counter or kernel not in k:
+                continue
+            m = re.search(r"(k_\w+<[^>]*>)", k)
+            per.setdefault(m.group(1) if m else k, []).append(v * 1024.0 * fac)
+        for name, vals in per.items():
+            res.setdefault(name, {})[key] = statistics.median(vals)
+            res[name]["launches_" + key.split("_")[0]] = len(vals)
+    return dict(fetch_factor=ff, write_factor=wf, kernels=res)
+
+
+def write_markdown(summary, path, command, title):
+    src = sources_hash()
+    lines = [f"# {title}", "", "Commands (from /tmp with TMPDIR=/tmp, repository at $R):", "",
+             "```", command, "```", "",
+             f"Counter scale factors from the in-process 1 GiB calibration kernels: "
+             f"FETCH_SIZE x {summary['fetch_factor']:.4f}, WRITE_SIZE x "
+             f"{summary['write_factor']:.4f}.", "",
+             "| kernel | launches | fetched MB/launch | written MB/launch |", "|---|---|---|---|"]
+    for name, d in sorted(summary["kernels"].items()):
+        lines.append(f"| `{name}` | {d.get('launches_fetch', 0)} | "
+                     f"{d.get('fetch_bytes', 0) / 1e6:.2f} | {d.get('write_bytes', 0) / 1e6:.2f} |")
+    lines.append("")
+    for name, d in sorted(summary["kernels"].items()):
+        lines.append("traffic-json: " + json.dumps(dict(kernel=name, sources=src, **{
+            k: v for k, v in d.items() if k.endswith("_bytes")})))
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def lookup(kernel, profiles_dir=None):
+    """fetch + write bytes per launch of `kernel` (exact template name) from the committed
+    summaries, or None if absent or measured on different kernel sources."""
+    profiles_dir = profiles_dir or os.path.join(ROOT, "profiles")
+    src = sources_hash()
+    for path in sorted(glob.glob(os.path.join(profiles_dir, "*.md"))):
+        with open(path) as f:
+            for line in f:
+                if not line.startswith("traffic-json: "):
+                    continue
+                d = json.loads(line[len("traffic-json: "):])
+                if d["kernel"] == kernel and d.get("sources") == src:
+                    return d.get("fetch_bytes", 0.0) + d.get("write_bytes", 0.0), d, path
+    return None
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("summarize")
+    s.add_argument("--fetch", required=True)
+    s.add_argument("--write", required=True)
+    s.add_argument("--kernel", required=True, help="prefix of the template name")
+    s.add_argument("--out", required=True)
+    s.add_argument("--command", required=True)
+    s.add_argument("--title", default="HBM traffic per launch")
+    a = ap.parse_args(argv)
+    summ = summarize(a.fetch, a.write, a.kernel)
+    write_markdown(summ, a.out, a.command, a.title)
+    print(json.dumps(summ, indent=1))
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())

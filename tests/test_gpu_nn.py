@@ -184,6 +184,8 @@ def _rand_field(shape, seed):
 
 
 def test_features_and_target_match_reference(torch):
+    """Features and targets against their definitions; a global phase of b must not change the
+    features (checked by a second call with b e^{0.7 i})."""
     import synth
     from oracle import green, operator
     from paper_2306_17537_amd import ie
@@ -201,14 +203,15 @@ def test_features_and_target_match_reference(torch):
         ie.ie_nn_target(ctx, dev(b), dev(E), yd)
         ref_rms = np.linalg.norm(b) / np.sqrt(b.size)
         assert abs(rms - ref_rms) <= 1e-12 * ref_rms
+        rot = np.exp(-0.5j * np.angle(np.sum(b * b)))  # global phase fixed by sum b.b
         bt, _, _ = operator.cie_tensors(operator.contrast(p.sigma6, p.sigma0), p.sigma0)
         k0h = green.wavenumber(p.sigma0, p.freq) * p.h
         ref = np.zeros((nz, ny, nx, 14))
         for c, (i, j) in enumerate(((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))):
             ref[..., c] = bt[i, j].real
         for c in range(3):
-            ref[..., 6 + 2 * c] = b[c].real / ref_rms
-            ref[..., 7 + 2 * c] = b[c].imag / ref_rms
+            ref[..., 6 + 2 * c] = (b[c] * rot).real / ref_rms
+            ref[..., 7 + 2 * c] = (b[c] * rot).imag / ref_rms
         ref[..., 12], ref[..., 13] = k0h.real, k0h.imag
         got = host(xd.float()).astype(np.float64)
         # both sides round the same value to bfloat16: equal up to one bf16 step at a tie
@@ -216,17 +219,23 @@ def test_features_and_target_match_reference(torch):
         assert np.mean(got == cnn.bf16(ref)) > 0.999
         ty = np.zeros((nz, ny, nx, 6))
         for c in range(3):
-            ty[..., 2 * c] = (E[c] - b[c]).real / ref_rms
-            ty[..., 2 * c + 1] = (E[c] - b[c]).imag / ref_rms
+            ty[..., 2 * c] = ((E[c] - b[c]) * rot).real / ref_rms
+            ty[..., 2 * c + 1] = ((E[c] - b[c]) * rot).imag / ref_rms
         assert rel(host(yd).astype(np.float64), ty) < 1e-6
+        xd2 = torch.empty_like(xd)
+        ie.ie_nn_features(ctx, dev(p.sigma6), dev(b * np.exp(0.7j)), xd2)
+        d = host((xd2.float() - xd.float()).abs()).max()
+        # invariant up to the sign of the half-angle phase and rounding
+        flip = host((xd2.float()[..., 6:12] + xd.float()[..., 6:12]).abs()).max()
+        assert d <= 2.0 ** -7 * np.abs(ref).max() or flip <= 2.0 ** -7 * np.abs(ref).max()
     finally:
         ie.ie_ctx_destroy(ctx)
 
 
 @pytest.mark.parametrize("default", ["exact", "garbage", "background"])
 def test_guess_judge_takes_smallest_residual(torch, default):
-    """With all weights zero the network output is zero, so the learned guess is b itself;
-    the judge must keep whichever of {b, default, 0} has the smallest residual."""
+    """With all weights zero the network output is zero, so the learned guess is b itself; the
+    judge must keep whichever of {b, default, 0} has the smallest residual."""
     import synth
     from oracle import dense, green, operator
     from paper_2306_17537_amd import ie
@@ -244,13 +253,14 @@ def test_guess_judge_takes_smallest_residual(torch, default):
         x_ex = dense.dense_solve(p.n, p.h, p.origin, k0, p.sigma0, dsig, b)
         x0 = {"exact": x_ex, "garbage": 50.0 * _rand_field(field_shape(p), 4),
               "background": b * 0.5}[default]
+        xl = b  # zero network output: the learned guess is b itself
         res = {k: np.linalg.norm(b - operator.apply_A(Ghat, dsig, v, p.n))
-               for k, v in (("learned", b), ("default", x0), ("zero", 0 * b))}
+               for k, v in (("learned", xl), ("default", x0), ("zero", 0 * b))}
         want = {"learned": 1, "default": 0, "zero": 2}[min(res, key=res.get)]
         xd = dev(x0)
         acc = ie.ie_nn_guess(ctx, nn, dev(p.sigma6), dev(b), xd)
         assert acc == want, (acc, res)
-        expect = {1: b, 0: x0, 2: 0 * b}[acc]
+        expect = {1: xl, 0: x0, 2: 0 * b}[acc]
         assert np.allclose(host(xd), expect, rtol=0, atol=1e-12 * np.max(np.abs(b)))
     finally:
         ie.ie_nn_destroy(nn)
