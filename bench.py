@@ -3,9 +3,9 @@
 
 Workload (one "step"): one complete solve of the 64^3 three-layer dipping TI model (cell
 0.25 m, 2 MHz, z dipole at the centre) to full-domain relative residual 1e-6 (eq. 9) by the
-chosen form: background field, contrast preparation and restarted GMRES(10) on the contraction
-form in mixed precision (complex64 Krylov vectors and convolutions; float64 residual at every
-restart, Arnoldi scalars, Givens rotations and solution accumulation).  The Green's spectrum is
+chosen form: background field, contrast preparation and restarted GMRES(10) from a zero start
+on the contraction form in mixed precision (complex64 Krylov vectors and convolutions; float64
+residual at every restart, Arnoldi scalars, Givens rotations and solution accumulation).  The Green's spectrum is
 built once before the timed region (it depends on grid and medium only) and timed separately.
 The same solve by Alg. 1 (block Gauss-Seidel and Jacobi over two z slabs, float64 and mixed)
 and by plain float64 GMRES is timed in the same run and reported beside it.
@@ -102,7 +102,7 @@ def main():
     ie.ie_background_field(ctx, p.sources, E0)
 
     def solve_full(precision):
-        x = E0.clone()
+        x = torch.zeros_like(E0)
         torch.cuda.synchronize()
         t = time.perf_counter()
         _, gst = ie.ie_gmres(ctx, s6, E0, x, tol=1e-6, precision=precision, form=ie.IE_CIE)
@@ -110,11 +110,12 @@ def main():
         return time.perf_counter() - t, gst, (x - E0).cpu().numpy()
 
     def solve_chosen():
-        # background field + contrast + mixed-precision GMRES, all inside the timed step
+        # background field + contrast + mixed-precision GMRES from a zero start, all inside the
+        # timed step
         torch.cuda.synchronize()
         t = time.perf_counter()
         ie.ie_background_field(ctx, p.sources, E0)
-        x = E0.clone()
+        x = torch.zeros_like(E0)
         _, gst = ie.ie_gmres(ctx, s6, E0, x, tol=1e-6, precision=ie.IE_MIXED, form=ie.IE_CIE)
         torch.sub(x, E0, out=Ea)
         torch.cuda.synchronize()
@@ -250,8 +251,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "config1: 64^3 cells of 0.25 m, 3-layer TI dipping 30 deg "
                                "(seed 101), 2 MHz, z dipole; full-domain contraction-form "
-                               "GMRES(10), complex64 Krylov/convolutions + float64 restarts, "
-                               "tol 1e-6",
+                               "GMRES(10) from zero, complex64 Krylov/convolutions + float64 "
+                               "restarts, tol 1e-6",
                    "grid": list(p.n), "its": chosen_stats.its,
                    "refinements": chosen_stats.refinements, "matvecs32": chosen_stats.matvecs32,
                    "matvecs64": chosen_stats.matvecs64, "graph_cycles": chosen_stats.graph_cycles,

@@ -1,4 +1,5 @@
-"""HBM traffic per kernel launch from two rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE).
+"""Profile summaries: HBM traffic per kernel launch from two rocprofv3 counter runs (FETCH_SIZE,
+then WRITE_SIZE), and the top of a rocprofv3 kernel-trace statistics table.
 
 Both counters are reported in KiB per dispatch but do not read one-to-one on this GPU, so each is
 scaled by what it reads for a kernel of known traffic run in the same process: a 1 GiB fill
@@ -10,9 +11,11 @@ Summaries are written as markdown with one machine-readable line per kernel vari
 ``sources`` is a hash of the kernel source files at measurement time; ``lookup()`` returns
 nothing once the sources have changed, so a stale figure is never reported.
 
-Usage (from the repository root, after the two profiler runs):
+Usage (from the repository root, after the profiler runs):
     python -m paper_2306_17537_amd.traffic summarize --fetch DIR1 --write DIR2 \\
         --kernel 'k_zconv<float, 128' --out profiles/NAME.md --command '...'
+    python -m paper_2306_17537_amd.traffic stats --dir DIR --out profiles/NAME.md \\
+        --command '...' [--top 20] [--extra TEXT]
 """
 from __future__ import annotations
 
@@ -71,7 +74,8 @@ def _factor(rows, counter, pattern):
 
 
 def summarize(fetch_dir, write_dir, kernel):
-    """Per variant of `kernel` (a prefix of the demangled name): median scaled bytes/launch."""
+    """Per kernel whose name matches the regular expression `kernel`: median scaled
+    bytes per launch."""
     fr, wr = _rows(fetch_dir), _rows(write_dir)
     ff = _factor(fr, "FETCH_SIZE", r"copyBuffer")
     wf = _factor(wr, "WRITE_SIZE", r"FillFunctor")
@@ -80,7 +84,7 @@ def summarize(fetch_dir, write_dir, kernel):
                                     (wr, "WRITE_SIZE", wf, "write_bytes")):
         per = {}
         for k, c, v in rows:
-            if c != counter or kernel not in k:
+            if c != counter or not re.search(kernel, k):
                 continue
             m = re.search(r"(k_\w+<[^>]*>)", k)
             per.setdefault(m.group(1) if m else k, []).append(v * 1024.0 * fac)
@@ -125,17 +129,55 @@ def lookup(kernel, profiles_dir=None):
     return None
 
 
+def kernel_stats(directory, top=20):
+    """Rows (name, calls, avg us, min us, max us, percent) of a --kernel-trace --stats run."""
+    paths = glob.glob(os.path.join(directory, "**", "*kernel_stats.csv"), recursive=True)
+    if not paths:
+        raise FileNotFoundError(f"no kernel_stats.csv under {directory}")
+    rows = []
+    with open(paths[0]) as f:
+        for r in csv.DictReader(f):
+            rows.append((r["Name"], int(r["Calls"]), float(r["AverageNs"]) / 1e3,
+                         float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+    rows.sort(key=lambda x: -x[5])
+    return rows[:top]
+
+
+def write_stats_markdown(rows, path, command, title, extra=""):
+    lines = [f"# {title}", "", "Command (from /tmp with TMPDIR=/tmp, repository at $R):", "", "```",
+             command, "```", "", "| kernel | calls | avg us | min us | max us | % time |",
+             "|---|---|---|---|---|---|"]
+    for n, c, a, lo, hi, pc in rows:
+        m = re.search(r"(k_\w+(?:<[^>]*>)?|__amd\w+)", n)
+        name = m.group(1) if m else re.sub(r"^void ", "", n)
+        lines.append(f"| `{name[:80]}` | {c} | {a:.2f} | {lo:.2f} | {hi:.2f} | {pc:.2f} |")
+    if extra:
+        lines += ["", extra]
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     s = sub.add_parser("summarize")
     s.add_argument("--fetch", required=True)
     s.add_argument("--write", required=True)
-    s.add_argument("--kernel", required=True, help="prefix of the template name")
+    s.add_argument("--kernel", required=True, help="regular expression on the kernel name")
     s.add_argument("--out", required=True)
     s.add_argument("--command", required=True)
     s.add_argument("--title", default="HBM traffic per launch")
+    k = sub.add_parser("stats")
+    k.add_argument("--dir", required=True)
+    k.add_argument("--out", required=True)
+    k.add_argument("--command", required=True)
+    k.add_argument("--title", default="Kernel trace statistics")
+    k.add_argument("--top", type=int, default=20)
+    k.add_argument("--extra", default="")
     a = ap.parse_args(argv)
+    if a.cmd == "stats":
+        write_stats_markdown(kernel_stats(a.dir, a.top), a.out, a.command, a.title, a.extra)
+        return 0
     summ = summarize(a.fetch, a.write, a.kernel)
     write_markdown(summ, a.out, a.command, a.title)
     print(json.dumps(summ, indent=1))
