@@ -42,10 +42,10 @@ struct Slots {
   static constexpr int NS = 2 * CM;
 };
 
-// Block-wide sums of the needed slots (k < nd, and NS if nrm); thread k writes out[k].
+// Block-wide sums of the needed slots (k < nd, and NS if nrm); thread k writes out[k * os].
 template <int NV>
 __device__ __forceinline__ void block_sums(double (&v)[NV], int nd, bool nrm, double* sh,
-                                           double* out) {
+                                           double* out, long os = 1) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < NV; ++k)
@@ -59,63 +59,82 @@ __device__ __forceinline__ void block_sums(double (&v)[NV], int nd, bool nrm, do
       double r = 0;
 #pragma unroll
       for (int q = 0; q < NWV; ++q) r += sh[q * NV + k];
-      out[k] = r;
+      out[k * os] = r;
     }
   }
 }
 
-// Sum the G block partials of problem b (every thread a fixed subset of rows, then one block
-// reduction; deterministic) into fin[].  Called by a one-block kernel.
+// Sum the G block partials of problem b (stored slot-major, part[(b PWD + slot) G + block], so
+// that consecutive threads read consecutive blocks; every thread a fixed subset of blocks, then
+// one block reduction; deterministic) into fin[].  Called by a one-block kernel.
 template <int NV>
 __device__ void reduce_partials(const double* part, int b, int G, int nd, bool nrm, double* sh,
                                 double* fin) {
   double a[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) a[k] = 0;
+  const double* pb = part + long(b) * PWD * G;
   for (int q = threadIdx.x; q < G; q += RB) {
-    const double* row = part + (long(b) * G + q) * PWD;
+    double v[NV];  // all slot loads of this block index are issued before the sums
 #pragma unroll
     for (int k = 0; k < NV; ++k)
-      if (k < nd || (nrm && k == NV - 1)) a[k] += row[k];
+      v[k] = (k < nd || (nrm && k == NV - 1)) ? pb[long(k) * G + q] : 0.0;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) a[k] += v[k];
   }
   block_sums<NV>(a, nd, nrm, sh, fin);
   __syncthreads();
 }
 
-// Givens step for Hessenberg column j once h_{j+1,j}^2 = hn2 is known (thread 0).
+// Givens step for Hessenberg column j once h_{j+1,j}^2 = hn2 is known.  Called by all threads
+// of the block: the column, the previous rotations and g[j] are staged in shared memory by
+// parallel loads, thread 0 applies the rotations, and the column is written back in parallel.
 __device__ void givens_update(GmState& s, int j, double hn2, int* flags, int batch, int b) {
-  const double hn = sqrt(hn2);
-  c128* H = s.H[j];
-  for (int i = 0; i < j; ++i) {
-    const c128 t = cjmul(s.cs[i], H[i]) + cjmul(s.sn[i], H[i + 1]);
-    H[i + 1] = c128{0, 0} - s.sn[i] * H[i] + s.cs[i] * H[i + 1];
-    H[i] = t;
+  __shared__ c128 Hs[MAXM + 1], cs[MAXM], sn[MAXM];
+  const int t = threadIdx.x;
+  if (t <= j) Hs[t] = s.H[j][t];
+  if (t < j) {
+    cs[t] = s.cs[t];
+    sn[t] = s.sn[t];
   }
-  const double hjj = sqrt(H[j].re * H[j].re + H[j].im * H[j].im);
-  const double den = sqrt(hjj * hjj + hn * hn);
-  c128 c, sn;
-  if (den == 0.0) {
-    c = c128{1, 0};
-    sn = c128{0, 0};
-  } else {
-    c = c128{H[j].re / den, H[j].im / den};
-    sn = c128{hn / den, 0};
+  __syncthreads();
+  if (t == 0) {
+    const double hn = sqrt(hn2);
+    c128* H = Hs;
+    for (int i = 0; i < j; ++i) {
+      const c128 u = cjmul(cs[i], H[i]) + cjmul(sn[i], H[i + 1]);
+      H[i + 1] = c128{0, 0} - sn[i] * H[i] + cs[i] * H[i + 1];
+      H[i] = u;
+    }
+    const double hjj = sqrt(H[j].re * H[j].re + H[j].im * H[j].im);
+    const double den = sqrt(hjj * hjj + hn * hn);
+    c128 c, sg;
+    if (den == 0.0) {
+      c = c128{1, 0};
+      sg = c128{0, 0};
+    } else {
+      c = c128{H[j].re / den, H[j].im / den};
+      sg = c128{hn / den, 0};
+    }
+    s.cs[j] = c;
+    s.sn[j] = sg;
+    H[j] = c128{den, 0};
+    H[j + 1] = c128{0, 0};
+    const c128 gj = s.g[j];
+    const c128 g1 = c128{0, 0} - sg * gj;
+    s.g[j + 1] = g1;
+    s.g[j] = cjmul(c, gj);
+    s.est = sqrt(g1.re * g1.re + g1.im * g1.im);
+    s.k = j + 1;
+    s.its += 1;
+    const bool brk = (hn == 0.0) || (den == 0.0);
+    s.breakdown = brk ? 1 : 0;
+    s.nv[j + 1] = brk ? 0.0 : 1.0 / hn;
+    if (s.est <= s.target || s.its >= s.max_its || brk) s.active = 0;
+    flags[j * batch + b] = s.active;
   }
-  s.cs[j] = c;
-  s.sn[j] = sn;
-  H[j] = c128{den, 0};
-  H[j + 1] = c128{0, 0};
-  const c128 gj = s.g[j];
-  s.g[j + 1] = c128{0, 0} - sn * gj;
-  s.g[j] = cjmul(c, gj);
-  s.est = sqrt(s.g[j + 1].re * s.g[j + 1].re + s.g[j + 1].im * s.g[j + 1].im);
-  s.k = j + 1;
-  s.its += 1;
-  const bool brk = (hn == 0.0) || (den == 0.0);
-  s.breakdown = brk ? 1 : 0;
-  s.nv[j + 1] = brk ? 0.0 : 1.0 / hn;
-  if (s.est <= s.target || s.its >= s.max_its || brk) s.active = 0;
-  flags[j * batch + b] = s.active;
+  __syncthreads();
+  if (t <= j + 1) s.H[j][t] = Hs[t];
 }
 
 // Fused Gram-Schmidt pass over w (per problem b = blockIdx.z), with v_i = nv[i] V_i:
@@ -181,8 +200,10 @@ __global__ void __launch_bounds__(RB)
     if (NRM) acc[SL::NS] += wd.re * wd.re + wd.im * wd.im;
   }
   const int nd = DOTS ? 2 * count : 0;
-  double* pb = part + (long(b) * gridDim.x + blockIdx.x) * PWD;
-  block_sums<NV>(acc, nd, NRM, sh, pb);
+  // slot-major partials: slot k of this block at part[(b PWD + k) G + blockIdx.x] (the
+  // finalisation kernel launched after this one uses the same register bucket CM)
+  double* pb = part + long(b) * PWD * gridDim.x + blockIdx.x;
+  block_sums<NV>(acc, nd, NRM, sh, pb, long(gridDim.x));
 }
 
 // Finalisation of a reduction (one block per problem):
@@ -209,17 +230,22 @@ __global__ void __launch_bounds__(RB)
   __shared__ double fin[NV];
   const int nd = FIN == FIN_H ? 2 * count : 0;
   reduce_partials<NV>(part, b, G, nd, FIN != FIN_H, sh, fin);
-  if (threadIdx.x != 0) return;
   if (FIN == FIN_H) {
-    for (int i = 0; i < count; ++i) {
+    const int i = threadIdx.x;  // one coefficient per thread
+    if (i < count) {
       const double nvi = S.nv[i];
       const c128 hv = c128{nvi * fin[2 * i], nvi * fin[2 * i + 1]};
       S.hc[i] = hv;
       S.H[j][i] = first ? hv : S.H[j][i] + hv;
     }
-  } else if (FIN == FIN_GIVENS) {
+    return;
+  }
+  if (FIN == FIN_GIVENS) {
     givens_update(S, j, fin[SL::NS], flags, batch, b);
-  } else if (FIN == FIN_CYCLE) {
+    return;
+  }
+  if (threadIdx.x != 0) return;
+  if (FIN == FIN_CYCLE) {
     const double beta = sqrt(fin[SL::NS]);
     S.beta = beta;
     S.est = beta;
