@@ -135,6 +135,18 @@ def main():
     log(f"chosen form: {ms_per_step:.2f} ms/solve, its={st.its} refinements={st.refinements} "
         f"mv32={st.matvecs32} mv64={st.matvecs64} graph_cycles={st.graph_cycles}")
 
+    # the paper's observable: H at receivers 7, 15 and 30 m above the transmitter (eqs. 4, 6)
+    rx = [[0.0, 0.0, 7.0], [0.0, 0.0, 15.0], [0.0, 0.0, 30.0]]
+    Et = Ea + E0
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    H, Ha = ie.ie_receivers(ctx, s6, p.sources, Et, rx)
+    t_rx = time.perf_counter() - t
+    receivers_out = dict(spacings_m=[7, 15, 30], ms=round(1e3 * t_rx, 3),
+                         Hz_abs=[float(abs(H[q, 2])) for q in range(3)],
+                         Hz_background_abs=[float(abs(H[q, 2] - Ha[q, 2])) for q in range(3)])
+    log(f"receivers: {receivers_out}")
+
     # the same steps with direct kernel launches (no graph replay), then profiled
     ie.ie_set_option(ie.IE_OPT_GRAPHS, 0)
     t_eager = [solve_chosen()[0] for _ in range(args.steps)]
@@ -269,6 +281,7 @@ def main():
         "cpu_baseline": cpu,
         "plain_fp64": plain,
         "variants": variants,
+        "induction_log": receivers_out,
         "learned_guess": learned,
         "batch": batch,
         "matvec": mv,

@@ -317,6 +317,21 @@ int ie_nn_guess(ie_ctx* ctx, ie_nn* nn, const double* sigma6, const void* b, voi
                 int32_t* accepted, void* stream);
 
 /*
+ * Magnetic field at receiver points (eqs. 4 and 6): with eq. (5), G^H J = grad g(r - r') x J, so
+ *   H(r) = H0(r) + h^3 sum_c grad g(r - r_c) x (dsigma E)_c
+ * over the cells of the context's grid (collocation at cell centres as in eq. 8; a receiver at a
+ * cell centre gets nothing from that cell).  H0: sigma0 G^E m for a magnetic dipole,
+ * grad g x p for an electric dipole.  The induction-log response of a z transmitter is H_z.
+ *   sigma6 : DEVICE float64 [6][nz][ny][nx];  E : DEVICE complex128 [3][nz][ny][nx], the total field
+ *   src    : HOST [nsrc] transmitters (nsrc >= 0);  rx : HOST float64 [nrx][3] positions (m),
+ *            1 <= nrx <= 4096, none within 1e-9 h of a transmitter
+ *   H      : HOST complex128 [nrx][3] total field;  Ha : HOST complex128 [nrx][3] or NULL, H - H0
+ * Deterministic (fixed-order sums).  Synchronises with `stream`.
+ */
+int ie_receivers(ie_ctx* ctx, const double* sigma6, const ie_source* src, int32_t nsrc,
+                 const void* E, const double* rx, int32_t nrx, void* H, void* Ha, void* stream);
+
+/*
  * Library options (process-wide).
  *   IE_OPT_GRAPHS: 1 (default) replays each Krylov restart cycle as a captured hipGraph; 0 issues
  *                  every kernel launch directly (the launch profiler always uses direct launches).

@@ -119,6 +119,7 @@ def lib():
         L.ie_nn_guess.argtypes = [vp, vp, vp, vp, vp, C.POINTER(i32), vp]
         L.ie_nn_predict.argtypes = [vp, vp, vp, vp, vp, vp]
         L.ie_ctx_tuning.argtypes = [vp, C.c_char_p, i32]
+        L.ie_receivers.argtypes = [vp, vp, C.POINTER(ie_source), i32, vp, vp, i32, vp, vp, vp]
         L.ie_nn_features.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_double), vp]
         L.ie_nn_target.argtypes = [vp, vp, vp, vp, vp]
         for f in ("ie_green_setup", "ie_ctx_destroy", "ie_background_field", "ie_matvec",
@@ -126,7 +127,7 @@ def lib():
                   "ie_nn_create", "ie_nn_destroy", "ie_nn_num_params", "ie_nn_get_params",
                   "ie_nn_set_params", "ie_nn_forward", "ie_nn_backward", "ie_nn_train_step",
                   "ie_nn_gemm", "ie_nn_guess", "ie_nn_features", "ie_nn_target", "ie_nn_predict",
-                  "ie_ctx_tuning"):
+                  "ie_ctx_tuning", "ie_receivers"):
             getattr(L, f).restype = C.c_int
         L.ie_last_error.restype = C.c_char_p
         L.ie_version.restype = C.c_char_p
@@ -261,6 +262,19 @@ def ie_profile_end(cap=256):
         out.append(dict(name=k.name.decode(), launches=k.launches, total_ms=k.total_ms,
                         min_ms=k.min_ms, max_ms=k.max_ms, bytes_per_launch=k.bytes_per_launch))
     return out
+
+
+def ie_receivers(ctx, sigma6, sources, E, rx, stream=None):
+    """Magnetic field at receivers rx [(x, y, z), ...]; returns (H, Ha) as numpy [nrx, 3]."""
+    import numpy as np
+    src = make_sources(sources) if not isinstance(sources, C.Array) else sources
+    pts = np.ascontiguousarray(rx, dtype=np.float64).reshape(-1, 3)
+    H = np.empty((len(pts), 3), dtype=np.complex128)
+    Ha = np.empty_like(H)
+    _check(lib().ie_receivers(C.c_void_p(ctx), _ptr(sigma6), src, len(src), _ptr(E),
+                              pts.ctypes.data, len(pts), H.ctypes.data, Ha.ctypes.data,
+                              _stream(stream)), "ie_receivers")
+    return H, Ha
 
 
 def ie_ctx_tuning(ctx):
