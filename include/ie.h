@@ -339,10 +339,14 @@ int ie_receivers(ie_ctx* ctx, const double* sigma6, const ie_source* src, int32_
  *                  (values per thread, columns or rows per block) on every grid it builds and keep
  *                  the fastest (cached per device, precision and grid for the process); 0 uses
  *                  the default variant.  Affects contexts set up afterwards.
+ *   IE_OPT_FORCE_VARIANT: -1 (default) leaves the choice to the autotuner; 0 .. 7 puts every
+ *                  pass of contexts set up afterwards on that variant (passes with four variants
+ *                  take it modulo 4): for tests that cover every variant.
  * Returns IE_EINVAL for an unknown option or value.
  */
 #define IE_OPT_GRAPHS 1
 #define IE_OPT_AUTOTUNE 2
+#define IE_OPT_FORCE_VARIANT 3
 int ie_set_option(int32_t option, int32_t value);
 
 /*

@@ -127,6 +127,13 @@ using namespace ie;
 
 namespace {
 bool g_autotune = true;
+int g_force_variant = -1;
+
+// every pass of the plan on one variant (row passes have eight, the others four)
+void force_variant(Plan& p, int v) {
+  for (int pi = 0; pi < 2; ++pi)
+    for (int q = 0; q < 5; ++q) p.var[pi][q] = int8_t((q == 0 || q == 4) ? v : (v & 3));
+}
 }  // namespace
 
 extern "C" {
@@ -144,6 +151,11 @@ int ie_set_option(int32_t option, int32_t value) {
   if (option == IE_OPT_AUTOTUNE) {
     if (value != 0 && value != 1) return fail(IE_EINVAL, "IE_OPT_AUTOTUNE takes 0 or 1");
     g_autotune = value != 0;
+    return IE_OK;
+  }
+  if (option == IE_OPT_FORCE_VARIANT) {
+    if (value < -1 || value > 7) return fail(IE_EINVAL, "IE_OPT_FORCE_VARIANT takes -1 .. 7");
+    g_force_variant = value;
     return IE_OK;
   }
   return fail(IE_EINVAL, "unknown option %d", option);
@@ -205,7 +217,9 @@ int ie_green_setup(const ie_grid* grid, const ie_medium* medium, const ie_partit
   }
   c->full = make_plan(grid->nx, grid->ny, grid->nz);
   IE_TRY(build_green(*c->full, grid->h, m, precision_mask, tw64(c.get()), tw32(c.get()), s));
-  if (g_autotune)
+  if (g_force_variant >= 0)
+    force_variant(*c->full, g_force_variant);
+  else if (g_autotune)
     IE_TRY(autotune(*c->full, precision_mask, tw64(c.get()), tw32(c.get()), s));
   if (partition != nullptr) {
     for (size_t i = 0; i + 1 < c->zb.size(); ++i) {
@@ -213,7 +227,10 @@ int ie_green_setup(const ie_grid* grid, const ie_medium* medium, const ie_partit
       if (c->blocks.count(nzb)) continue;
       auto p = make_plan(grid->nx, grid->ny, nzb);
       IE_TRY(build_green(*p, grid->h, m, precision_mask, tw64(c.get()), tw32(c.get()), s));
-      if (g_autotune) IE_TRY(autotune(*p, precision_mask, tw64(c.get()), tw32(c.get()), s));
+      if (g_force_variant >= 0)
+        force_variant(*p, g_force_variant);
+      else if (g_autotune)
+        IE_TRY(autotune(*p, precision_mask, tw64(c.get()), tw32(c.get()), s));
       c->blocks[nzb] = std::move(p);
     }
   }
@@ -229,13 +246,13 @@ int ie_ctx_tuning(const ie_ctx* ctx, char* buf, int32_t len) {
     for (int pi = 0; pi < 2; ++pi) {
       if (!(ctx->prec_mask & (pi == 0 ? IE_FP64 : IE_MIXED))) continue;
       for (int q = 0; q < 5; ++q) {
-        char t[256];
+        char t[384];
+        const float* u = p.tune_us[pi][q];
         snprintf(t, sizeof(t),
                  "%s{\"grid\": [%d, %d, %d], \"precision\": \"%s\", \"pass\": \"%s\", "
-                 "\"variant\": %d, \"us\": [%.2f, %.2f, %.2f, %.2f]}",
+                 "\"variant\": %d, \"us\": [%.2f, %.2f, %.2f, %.2f, %.2f, %.2f, %.2f, %.2f]}",
                  o.size() > 1 ? ", " : "", p.nx, p.ny, p.nz, pi == 0 ? "c128" : "c64",
-                 pass_names[q], p.var[pi][q], p.tune_us[pi][q][0], p.tune_us[pi][q][1],
-                 p.tune_us[pi][q][2], p.tune_us[pi][q][3]);
+                 pass_names[q], p.var[pi][q], u[0], u[1], u[2], u[3], u[4], u[5], u[6], u[7]);
         o += t;
       }
     }

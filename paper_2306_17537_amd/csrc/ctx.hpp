@@ -53,7 +53,7 @@ struct Plan {
   // launch variant per [precision: 0 float64, 1 complex64][pass: xfwd, yfwd, zconv, yinv, xinv],
   // set by the autotuner (0 when tuning is off)
   int8_t var[2][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
-  float tune_us[2][5][4] = {};  // measured average duration per variant (0: not measured)
+  float tune_us[2][5][8] = {};  // measured average duration per variant (0: not measured)
   long ncell() const { return long(nx) * ny * nz; }
   long t1_elems() const { return 3L * nz * ny * LX; }
   long t2_elems() const { return 3L * nz * LY * LX; }

@@ -128,6 +128,13 @@ struct LdsPadded {  // line-major, one pad slot every 16 positions (conflict-fre
   __device__ __forceinline__ int operator()(int p) const { return base + p + (p >> 4); }
   static constexpr __host__ __device__ int padded_len(int L) { return L + L / 16; }
 };
+// line-major, one pad slot every 4 positions (stride-4 writes of a radix-4 first stage land on
+// distinct banks), lines offset by half a bank row more
+struct LdsPadded4 {
+  int base;
+  __device__ __forceinline__ int operator()(int p) const { return base + p + (p >> 2); }
+  static constexpr __host__ __device__ int padded_len(int L) { return L + L / 4 + 16; }
+};
 
 template <typename T, int L, int E, int S, bool INV, typename Addr>
 __device__ __forceinline__ void fft_stage(cx<T> (&v)[E], cx<T>* __restrict__ lds, Addr addr,

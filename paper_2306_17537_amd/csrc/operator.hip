@@ -56,6 +56,23 @@ int fft_len(int n) {
     }                                                                    \
   }
 
+// The same for the row passes, which have eight variants.
+#define IE_ROW_VARIANTS(v, ...)                                          \
+  if constexpr (L < 16) {                                                \
+    return go<0>(__VA_ARGS__);                                           \
+  } else {                                                               \
+    switch (v) {                                                         \
+      case 1: return go<1>(__VA_ARGS__);                                 \
+      case 2: return go<2>(__VA_ARGS__);                                 \
+      case 3: return go<3>(__VA_ARGS__);                                 \
+      case 4: return go<4>(__VA_ARGS__);                                 \
+      case 5: return go<5>(__VA_ARGS__);                                 \
+      case 6: return go<6>(__VA_ARGS__);                                 \
+      case 7: return go<7>(__VA_ARGS__);                                 \
+      default: return go<0>(__VA_ARGS__);                                \
+    }                                                                    \
+  }
+
 template <typename T, int L>
 struct XfwdL {
   template <int V>
@@ -76,7 +93,7 @@ struct XfwdL {
     return IE_OK;
   }
   static int run(int v, const MvArgs<T>& a, int batch, hipStream_t s) {
-    IE_VARIANTS(v, a, batch, s);
+    IE_ROW_VARIANTS(v, a, batch, s);
   }
 };
 template <typename T, int L>
@@ -97,7 +114,7 @@ struct XinvL {
     return IE_OK;
   }
   static int run(int v, const MvArgs<T>& a, int batch, hipStream_t s) {
-    IE_VARIANTS(v, a, batch, s);
+    IE_ROW_VARIANTS(v, a, batch, s);
   }
 };
 template <typename T, int L>
@@ -249,7 +266,7 @@ template int launch_matvec<float>(Plan&, MvArgs<float>, int, hipStream_t, const 
 namespace {
 struct TuneEntry {
   int8_t var[5];
-  float us[5][kVariants];
+  float us[5][kRowVariants];
 };
 std::map<std::tuple<int, int, int, int, int>, TuneEntry> g_tune_cache;
 std::mutex g_tune_mu;
@@ -257,7 +274,8 @@ constexpr int kReps = 5;
 }  // namespace
 
 template <typename T>
-static int tune_one(Plan& p, const cx<T>* tw, hipStream_t s, int8_t var[5], float us[5][kVariants]) {
+static int tune_one(Plan& p, const cx<T>* tw, hipStream_t s, int8_t var[5],
+                    float us[5][kRowVariants]) {
   constexpr bool dbl = sizeof(T) == 8;
   IE_TRY(p.work(dbl ? IE_FP64 : IE_MIXED, 1));
   const long N = p.ncell();
@@ -294,7 +312,8 @@ static int tune_one(Plan& p, const cx<T>* tw, hipStream_t s, int8_t var[5], floa
   for (int pass = 0; pass < 5 && rc == IE_OK; ++pass) {
     float best = 0;
     var[pass] = 0;
-    for (int v = 0; v < kVariants && rc == IE_OK; ++v) {
+    const int nv = (pass == 0 || pass == 4) ? kRowVariants : kVariants;
+    for (int v = 0; v < nv && rc == IE_OK; ++v) {
       rc = launch_matvec<T>(p, a, 1, s, tw, pass, v);
       if (rc != IE_OK) break;
       if (hipEventRecord(e0, s) != hipSuccess) rc = fail(IE_EDEVICE, "hipEventRecord failed");

@@ -17,6 +17,8 @@
 // advance by their batch stride.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "fft.hpp"
 
@@ -67,8 +69,10 @@ __device__ __forceinline__ bool retired(const MvArgs<T>& a, int b) {
 // Variant V (chosen per plan by the autotuner): bit 0 halves the values per thread (twice the
 // threads per line, more waves in flight, one more LDS exchange); bit 1 doubles the columns per
 // block of the column passes (256-byte row segments) and the rows per block of the row passes.
+// Row passes (x) have four more: V + 4 uses the LDS layout padded every 4 positions.
 // ---------------------------------------------------------------------------------------
 constexpr int kVariants = 4;
+constexpr int kRowVariants = 8;
 
 template <typename T, int L, int V = 0>
 struct Geo {
@@ -89,7 +93,10 @@ struct Geo {
   static constexpr int TLR = L / ER;
   static constexpr int NL0 = ((V & 2) ? 256 : 128) / TLR;
   static constexpr int NL = NL0 < 1 ? 1 : NL0;
-  static constexpr int LP = LdsPadded::padded_len(L);
+  // row-pass LDS layout: V & 4 pads every 4 positions instead of every 16
+  static constexpr bool PAD4 = (V & 4) != 0;
+  static constexpr int LP = PAD4 ? LdsPadded4::padded_len(L) : LdsPadded::padded_len(L);
+  using RowLds = typename std::conditional<PAD4, LdsPadded4, LdsPadded>::type;
 };
 
 // 3x3 symmetric tensor (6 comps) times a complex 3-vector
@@ -147,7 +154,7 @@ __global__ void __launch_bounds__((Geo<T, LX, V>::NL * Geo<T, LX, V>::TLR))
       for (int c = 0; c < 3; ++c) v[c][m] = xv[c];
     }
   }
-  const LdsPadded addr{line * G::LP};
+  const typename G::RowLds addr{line * G::LP};
   cx<T>* out = a.T1 + b * a.T1_bs + (long(z) * a.ny + yy) * LX;
   const long cs = long(a.nz) * a.ny * LX;
 #pragma unroll
@@ -335,7 +342,7 @@ __global__ void __launch_bounds__((Geo<T, LX, V>::NL * Geo<T, LX, V>::TLR))
   const cx<T>* in = a.T1 + b * a.T1_bs + (long(z) * a.ny + yy) * LX;
   const long cs = long(a.nz) * a.ny * LX;
   cx<T> v[3][E];
-  const LdsPadded addr{line * G::LP};
+  const typename G::RowLds addr{line * G::LP};
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
 #pragma unroll

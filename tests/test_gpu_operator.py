@@ -147,3 +147,38 @@ def test_invalid_tensor_is_rejected(torch):
             ie.ie_matvec(ctx, dev(s), x, y, ie.IE_CONVENTIONAL, ie.IE_FP64)
     finally:
         ie.ie_ctx_destroy(ctx)
+
+
+@pytest.mark.parametrize("variant", range(8))
+@pytest.mark.parametrize("n", [(33, 20, 17), (64, 48, 40), (100, 30, 12)])
+def test_every_launch_variant_matches_oracle(torch, variant, n):
+    """Every launch variant the autotuner can pick, forced on all passes (row passes have eight,
+    the others four), on shapes whose FFT lengths span 32..256."""
+    from paper_2306_17537_amd import ie
+    banner(f"matvec variant={variant} n={n}")
+    p = synth.random_problem(n, seed=sum(n) + variant, freq=2.0e6, contrast=3.0)
+    ie.ie_set_option(ie.IE_OPT_FORCE_VARIANT, variant)
+    try:
+        ctx, _ = context(p)
+    finally:
+        ie.ie_set_option(ie.IE_OPT_FORCE_VARIANT, -1)
+    try:
+        k0 = green.wavenumber(p.sigma0, p.freq)
+        Ghat = green.kernel_spectrum(p.n, p.h, k0, p.sigma0)
+        dsig = operator.contrast(p.sigma6, p.sigma0)
+        b, _, _ = operator.cie_tensors(dsig, p.sigma0)
+        x = _rand(field_shape(p), 11)
+        want = operator.apply_C(Ghat, b, x, p.sigma0, p.n)
+        s6 = dev(p.sigma6)
+        yd = torch.zeros(field_shape(p), dtype=torch.complex128, device="cuda:0")
+        ie.ie_matvec(ctx, s6, dev(x), yd, ie.IE_CIE, ie.IE_FP64)
+        y32 = torch.zeros(field_shape(p), dtype=torch.complex64, device="cuda:0")
+        ie.ie_matvec(ctx, s6, dev(x.astype(np.complex64)), y32, ie.IE_CIE, ie.IE_MIXED)
+        torch.cuda.synchronize()
+        assert rel(host(yd), want) < 1e-12
+        assert rel(host(y32).astype(np.complex128), want) < 2e-6
+        tun = ie.ie_ctx_tuning(ctx)
+        assert all(r["variant"] == (variant if r["pass"] in ("xfwd", "xinv") else variant & 3)
+                   for r in tun)
+    finally:
+        ie.ie_ctx_destroy(ctx)
