@@ -15,6 +15,7 @@ from .models import (  # noqa: F401
     config3,
     config4_train,
     config4_eval,
+    example1,
     random_problem,
     tensor6_to_3x3,
     default_origin,

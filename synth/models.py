@@ -257,6 +257,30 @@ def config4_eval(start=50000, count=16):
         yield config1(seed=s)
 
 
+def example1(n=128, h=0.25):
+    """Two isolated isotropic 0.01 S/m anomalies of 30 x 30 x 7.5 m in the 0.1 S/m background,
+    10 m apart along z (about one background skin depth at 24 kHz), symmetric about a
+    transmitter at the origin oriented along x (the isolated sub-domains example, sec. 3.1; its
+    figure is not reproduced, so the anomalies are placed symmetrically about the transmitter).
+    The partition separates the two anomalies and the three zero-contrast slabs."""
+    nn = (n, n, n)
+    origin = default_origin(nn, h)
+    sig = np.zeros((6, n, n, n))
+    sig[:3] = SIGMA0_DEFAULT
+    ext = int(round(30.0 / h))     # 120 cells at 0.25 m
+    thick = int(round(7.5 / h))    # 30 cells
+    gap = int(round(10.0 / h))     # 40 cells
+    x0 = (n - ext) // 2
+    z_a0 = (n - gap) // 2 - thick
+    z_b0 = (n + gap) // 2
+    for z0 in (z_a0, z_b0):
+        sig[:3, z0:z0 + thick, x0:x0 + ext, x0:x0 + ext] = 0.01
+    src = [((0.0, 0.0, 0.0), (1.0, 0.0, 0.0), "magnetic")]
+    zb = (0, z_a0, z_a0 + thick, z_b0, z_b0 + thick, n)
+    return Problem(f"example1_{n}cubed_two_isolated_anomalies", nn, h, origin, SIGMA0_DEFAULT,
+                   2.4e4, sig, src, zb)
+
+
 def random_problem(n, h=0.25, seed=0, freq=1.0e5, sigma0=SIGMA0_DEFAULT, contrast=1.0,
                    z_bounds=None, src_offset=(0.3, -0.2, -1.1)):
     """Small random anisotropic model: each cell a random SPD tensor around
