@@ -61,6 +61,13 @@ extern "C" {
 /* outer schemes (section 2.3) */
 #define IE_GS      0   /* block Gauss-Seidel, eqs. (19)-(22) */
 #define IE_JACOBI  1   /* block Jacobi, eqs. (23)-(24) */
+/* Krylov outer iteration in place of the stationary sweeps (the improvement the conclusions
+ * propose): flexible GMRES(inner.restart) on the full-domain eq. (8) in float64, right-
+ * preconditioned by one sweep of the scheme from zero with block solves to inner_tol_fixed
+ * (adaptive is ignored).  Statistics: sweeps = outer steps (one preconditioner application
+ * each), total_its = inner iterations, relres[k] = residual estimate after step k. */
+#define IE_FGMRES_GS     2
+#define IE_FGMRES_JACOBI 3
 
 /* initial guess of ie_dd_solve */
 #define IE_INIT_BACKGROUND 0  /* E := E0, as Alg. 1 */

@@ -89,3 +89,51 @@ def dd_solve(st: Setup, z_bounds, scheme="gs", adaptive=True, tol=1e-6, inner_to
         info["relres"].append(e)
     info["converged"] = e <= tol
     return E, info
+
+
+def dd_sweep_from_zero(st: Setup, z_bounds, v, scheme="gs", inner_tol=1e-2, form="conventional",
+                       restart=10, inner_max_its=5000, ghat_cache=None):
+    """One sweep of Alg. 1 applied to A z = v from z = 0: the block Gauss-Seidel (eqs. 19-22) or
+    Jacobi (eqs. 23-24) preconditioner.  Returns (z, inner iterations)."""
+    nx, ny, nz = st.n
+    zb = list(z_bounds)
+    cache = {} if ghat_cache is None else ghat_cache
+    z = np.zeros_like(np.asarray(v, dtype=np.complex128))
+    its = 0
+    for (z0, z1) in zip(zb[:-1], zb[1:]):
+        rhs = v[:, z0:z1] + (coupling(st, z, z0, z1) if scheme == "gs" else 0.0)
+        dsig_i = st.dsig[:, :, z0:z1]
+        if not np.any(dsig_i):
+            z[:, z0:z1] = rhs
+            continue
+        nzb = z1 - z0
+        if nzb not in cache:
+            cache[nzb] = green.kernel_spectrum((nx, ny, nzb), st.h, st.k0, st.sigma0)
+        zi, inf = solve_system(cache[nzb], dsig_i, rhs, (nx, ny, nzb), st.sigma0, form,
+                               x0=None, tol=inner_tol, restart=restart, max_its=inner_max_its)
+        z[:, z0:z1] = zi
+        its += inf["its"]
+    return z, its
+
+
+def fgmres_dd(st: Setup, z_bounds, scheme="gs", tol=1e-6, inner_tol=1e-2, form="conventional",
+              restart=10, max_its=200, inner_max_its=5000):
+    """The Krylov outer iteration in place of the stationary sweeps (the improvement proposed in
+    the conclusions): flexible GMRES on the full-domain eq. (8) from E = 0, right-preconditioned
+    by one sweep of Alg. 1 with inner solves to `inner_tol`.  Returns (E, info) with the outer
+    GMRES info plus the total inner iterations."""
+    from .gmres import fgmres
+    cache = {}
+    inner = [0]
+
+    def precond(v):
+        z, its = dd_sweep_from_zero(st, z_bounds, v, scheme, inner_tol, form, restart,
+                                    inner_max_its, cache)
+        inner[0] += its
+        return z
+
+    E, info = fgmres(lambda x: operator.apply_A(st.Ghat, st.dsig, x, st.n), precond, st.E0,
+                     None, tol, restart, max_its)
+    info["inner_its"] = inner[0]
+    info["relres"] = operator.relres(st.Ghat, st.dsig, E, st.E0, st.n)
+    return E, info

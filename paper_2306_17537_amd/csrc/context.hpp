@@ -12,6 +12,7 @@ namespace ie {
 struct DdBufs {
   DevBuf D64, M64, M32, A64, Ai64, E0, E, Eold, rhs, x, active, flags, bad;
   DevBuf xl;  // learned first-sweep guesses
+  DevBuf fv, fz, fw, fpart;  // Krylov outer iteration: basis, preconditioned vectors, work
 };
 }  // namespace ie
 

@@ -89,8 +89,9 @@ struct Group {
   int* active;   // per problem: still sweeping
 };
 
-// rhs_p = E0_p on block [z0, z1) + G (dsigma_p src_p) with block planes removed from the source
-int coupling_rhs(Group& g, const c128* src, int z0, int z1, c128* rhs) {
+// rhs_p = e_p on block [z0, z1) + G (dsigma_p src_p) with block planes removed from the source
+// (e = E0 for Alg. 1; the preconditioner input for the Krylov outer iteration)
+int coupling_rhs(Group& g, const c128* src, int z0, int z1, c128* rhs, const c128* e = nullptr) {
   Plan& F = *g.c->full;
   MvArgs<double> a{};
   a.x = src;
@@ -109,7 +110,7 @@ int coupling_rhs(Group& g, const c128* src, int z0, int z1, c128* rhs) {
   a.y_cs = long(z1 - z0) * g.plane;
   a.y_bs = 3 * a.y_cs;
   a.y_zoff = z0;
-  a.e = g.E0;
+  a.e = e ? e : g.E0;
   a.e_cs = g.N;
   a.e_bs = 3 * g.N;
   a.e_zoff = 0;
@@ -174,6 +175,231 @@ int block_solve(Group& g, Plan& B, int z0, c128* rhs, c128* x, const double* tol
     return IE_OK;
   }
   return gmres_solve(B, op, rhs, x, g.B, o, res, g.c->kw_blk, tw64(g.c), tw32(g.c), g.s);
+}
+
+// ---------------------------------------------------------------------------------------
+// Krylov outer iteration (the improvement the conclusions propose): flexible GMRES on the
+// full-domain eq. (8), right-preconditioned by one sweep of Alg. 1 from zero with inner solves to
+// a fixed tolerance.  Outer vectors and scalars in float64; the Hessenberg matrix, rotations and
+// back substitution on the host (one problem at a time, at most IE_MAX_SWEEPS outer steps).
+// ---------------------------------------------------------------------------------------
+constexpr int LCMAX = MAXM + 1;  // vectors in one linear combination
+struct Coefs {
+  c128 c[LCMAX];
+};
+
+// out = alpha out + sum_{i < count} c_i V_i  (V_i = V + i vs; none of them aliases out)
+__global__ void k_lincomb(c128* __restrict__ out, double alpha, const c128* __restrict__ V,
+                          long vs, int count, Coefs cf, long n) {
+  for (long e = long(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
+       e += long(gridDim.x) * blockDim.x) {
+    c128 acc = alpha == 0.0 ? c128{0, 0} : c128{alpha * out[e].re, alpha * out[e].im};
+    for (int i = 0; i < count; ++i) acc = acc + cf.c[i] * V[i * vs + e];
+    out[e] = acc;
+  }
+}
+
+// partials of <V_i, w> (conjugate-linear in V_i): part[(2 i + re/im) G + block], fixed order
+__global__ void __launch_bounds__(256) k_dots(const c128* __restrict__ V, long vs, int count,
+                                              const c128* __restrict__ w, long n,
+                                              double* __restrict__ part) {
+  __shared__ double sh[4][2 * LCMAX];
+  double acc[2 * LCMAX];
+  for (int k = 0; k < 2 * LCMAX; ++k) acc[k] = 0;
+  for (long e = long(blockIdx.x) * 256 + threadIdx.x; e < n; e += long(gridDim.x) * 256) {
+    const c128 x = w[e];
+    for (int i = 0; i < count; ++i) {
+      const c128 v = V[i * vs + e];
+      acc[2 * i] += v.re * x.re + v.im * x.im;
+      acc[2 * i + 1] += v.re * x.im - v.im * x.re;
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int k = 0; k < 2 * count; ++k) {
+    double v = acc[k];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) sh[wv][k] = v;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < 2 * count; k += 256)
+    part[long(k) * gridDim.x + blockIdx.x] = sh[0][k] + sh[1][k] + sh[2][k] + sh[3][k];
+}
+
+int lincomb(c128* out, double alpha, const c128* V, long vs, int count, const c128* c, long n,
+            hipStream_t s) {
+  if (count > LCMAX) return fail(IE_EINVAL, "too many vectors in a combination");
+  Coefs cf{};
+  for (int i = 0; i < count; ++i) cf.c[i] = c[i];
+  hipLaunchKernelGGL(k_lincomb, dim3(int(std::min<long>(4096, ceil_div(n, 256)))), dim3(256), 0, s,
+                     out, alpha, V, vs, count, cf, n);
+  IE_LAUNCH_CHECK();
+  return IE_OK;
+}
+
+int dots_host(const c128* V, long vs, int count, const c128* w, long n, DevBuf& part,
+              std::vector<c128>& out, hipStream_t s) {
+  const int G = int(std::min<long>(512, std::max<long>(1, n / 2048)));
+  IE_TRY(part.ensure(sizeof(double) * 2 * LCMAX * G));
+  hipLaunchKernelGGL(k_dots, dim3(G), dim3(256), 0, s, V, vs, count, w, n, part.as<double>());
+  IE_LAUNCH_CHECK();
+  std::vector<double> h(size_t(2) * count * G);
+  IE_HIP(hipMemcpyAsync(h.data(), part.p, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+  IE_HIP(hipStreamSynchronize(s));
+  out.assign(count, c128{0, 0});
+  for (int i = 0; i < count; ++i) {
+    double re = 0, im = 0;
+    for (int b = 0; b < G; ++b) {
+      re += h[size_t(2 * i) * G + b];
+      im += h[size_t(2 * i + 1) * G + b];
+    }
+    out[i] = c128{re, im};
+  }
+  return IE_OK;
+}
+
+// z = P^-1 v: one sweep of Alg. 1 on A z = v from z = 0 (GS: blocks in order, each coupled to
+// the blocks already updated; Jacobi: block diagonal).  One problem (g.B == 1).
+int dd_precondition(Group& g, const std::vector<int>& has, const c128* v, c128* z, bool gs,
+                    const ie_gmres_opts& inner, double itol, c128* rhs, c128* xb,
+                    int* block_its, int* inner_its, int* mv64, int* mv32, int* full_mv) {
+  ie_ctx* c = g.c;
+  const int M = int(c->zb.size()) - 1;
+  IE_HIP(hipMemsetAsync(z, 0, sizeof(c128) * 3 * g.N, g.s));
+  for (int i = 0; i < M; ++i) {
+    const int z0 = c->zb[i], z1 = c->zb[i + 1], nzb = z1 - z0;
+    const long nb = long(nzb) * g.plane;
+    if (gs && i > 0) {
+      IE_TRY(coupling_rhs(g, z, z0, z1, rhs, v));
+      *full_mv += 1;
+      *mv64 += 1;
+    } else {
+      IE_TRY(copy_blocks(v, rhs, 3 * g.N, g.N, g.plane, z0, nzb, true, 1, nullptr, g.s));
+    }
+    const c128* from = rhs;
+    if (has[i]) {
+      IE_HIP(hipMemsetAsync(xb, 0, sizeof(c128) * 3 * nb, g.s));
+      GmResult r{};
+      const double t = itol;
+      IE_TRY(block_solve(g, *c->block_plan(nzb), z0, rhs, xb, &t, inner, &r));
+      block_its[i] = r.its;
+      *inner_its += r.its;
+      *mv64 += r.mv64;
+      *mv32 += r.mv32;
+      from = xb;
+    } else {
+      block_its[i] = 0;
+    }
+    IE_TRY(copy_blocks(from, z, 3 * g.N, g.N, g.plane, z0, nzb, false, 1, nullptr, g.s));
+  }
+  return IE_OK;
+}
+
+// Flexible GMRES(m) for one problem of the group: x = g.E (initial guess in, solution out).
+int fgmres_one(Group& g, const std::vector<int>& has, const ie_dd_opts& o, double bnorm,
+               ie_dd_stats& st, double* e_out, c128* rhs, c128* xb, DdBufs& bufs) {
+  ie_ctx* c = g.c;
+  Plan& F = *c->full;
+  const int M = int(c->zb.size()) - 1;
+  const int m = o.inner.restart;
+  const long n = 3 * g.N;
+  const bool gs = o.scheme == IE_FGMRES_GS;
+  IE_TRY(bufs.fv.ensure(sizeof(c128) * n * (m + 1)));
+  IE_TRY(bufs.fz.ensure(sizeof(c128) * n * m));
+  IE_TRY(bufs.fw.ensure(sizeof(c128) * n));
+  c128* V = bufs.fv.as<c128>();
+  c128* Z = bufs.fz.as<c128>();
+  c128* w = bufs.fw.as<c128>();
+  OpDesc op;
+  op.form = IE_CONVENTIONAL;
+  op.M64 = g.D64;
+  op.M_cs = g.N;
+  op.M_bs = 6 * g.N;
+  const double itol = o.inner_tol_fixed;
+  int outer = 0;
+  double e = 0;
+  auto sat = [](c128 a) { return std::sqrt(a.re * a.re + a.im * a.im); };
+  while (true) {
+    // true residual r = E0 - A x, beta = ||r||
+    IE_TRY(apply_op<double>(F, op, g.E, w, g.E0, true, 1, nullptr, 0, g.s, tw64(c)));
+    double beta = 0;
+    IE_TRY(norms_host(w, n, 1, &beta, c->kw, g.s));
+    st.full_matvecs += 1;
+    st.matvecs64 += 1;
+    e = bnorm > 0 ? beta / bnorm : 0.0;
+    if (outer == 0) st.relres[0] = e;
+    if (e <= o.tol || outer >= o.max_sweeps || beta == 0) break;
+    const c128 ib{1.0 / beta, 0};
+    IE_TRY(lincomb(V, 0.0, w, 0, 1, &ib, n, g.s));
+    std::vector<std::vector<c128>> H(m + 1, std::vector<c128>(m, c128{0, 0}));
+    std::vector<c128> cs(m), sn(m), gv(m + 1, c128{0, 0});
+    gv[0] = c128{beta, 0};
+    int k = 0;
+    for (int j = 0; j < m && outer < o.max_sweeps; ++j) {
+      c128* vj = V + j * n;
+      c128* zj = Z + j * n;
+      int inner_its = 0;
+      IE_TRY(dd_precondition(g, has, vj, zj, gs, o.inner, itol, rhs, xb, st.block_its[outer],
+                             &inner_its, &st.matvecs64, &st.matvecs32, &st.full_matvecs));
+      st.total_its += inner_its;
+      IE_TRY(apply_op<double>(F, op, zj, w, nullptr, false, 1, nullptr, 0, g.s, tw64(c)));
+      st.full_matvecs += 1;
+      st.matvecs64 += 1;
+      // classical Gram-Schmidt, two passes
+      std::vector<c128> h(j + 1, c128{0, 0}), hp;
+      for (int pass = 0; pass < 2; ++pass) {
+        IE_TRY(dots_host(V, n, j + 1, w, n, bufs.fpart, hp, g.s));
+        std::vector<c128> neg(j + 1);
+        for (int i = 0; i <= j; ++i) {
+          h[i] = h[i] + hp[i];
+          neg[i] = c128{-hp[i].re, -hp[i].im};
+        }
+        IE_TRY(lincomb(w, 1.0, V, n, j + 1, neg.data(), n, g.s));
+      }
+      double hn = 0;
+      IE_TRY(norms_host(w, n, 1, &hn, c->kw, g.s));
+      for (int i = 0; i <= j; ++i) H[i][j] = h[i];
+      H[j + 1][j] = c128{hn, 0};
+      for (int i = 0; i < j; ++i) {  // previous rotations, Q = [[conj c, conj s], [-s, c]]
+        const c128 t = cjmul(cs[i], H[i][j]) + cjmul(sn[i], H[i + 1][j]);
+        H[i + 1][j] = c128{0, 0} - sn[i] * H[i][j] + cs[i] * H[i + 1][j];
+        H[i][j] = t;
+      }
+      const double hjj = sat(H[j][j]);
+      const double den = std::sqrt(hjj * hjj + hn * hn);
+      if (den == 0.0) {
+        cs[j] = c128{1, 0};
+        sn[j] = c128{0, 0};
+      } else {
+        cs[j] = c128{H[j][j].re / den, H[j][j].im / den};
+        sn[j] = c128{hn / den, 0};
+      }
+      H[j][j] = c128{den, 0};
+      gv[j + 1] = c128{0, 0} - sn[j] * gv[j];
+      gv[j] = cjmul(cs[j], gv[j]);
+      k = j + 1;
+      outer += 1;
+      st.sweeps = outer;
+      const double est = bnorm > 0 ? sat(gv[j + 1]) / bnorm : 0.0;
+      st.relres[outer] = est;
+      if (est <= o.tol || den == 0.0 || hn == 0.0) break;
+      const c128 ih{1.0 / hn, 0};
+      IE_TRY(lincomb(V + (j + 1) * n, 0.0, w, 0, 1, &ih, n, g.s));
+    }
+    // y = R^-1 g, x += Z y
+    std::vector<c128> y(k);
+    for (int i = k - 1; i >= 0; --i) {
+      c128 acc = gv[i];
+      for (int l = i + 1; l < k; ++l) acc = acc - H[i][l] * y[l];
+      const c128 d = H[i][i];
+      const double dd = d.re * d.re + d.im * d.im;
+      y[i] = dd > 0 ? c128{(acc.re * d.re + acc.im * d.im) / dd, (acc.im * d.re - acc.re * d.im) / dd}
+                    : c128{0, 0};
+    }
+    if (k > 0) IE_TRY(lincomb(g.E, 1.0, Z, n, k, y.data(), n, g.s));
+  }
+  st.relres[std::min(outer, IE_MAX_SWEEPS)] = e;
+  *e_out = e;
+  return IE_OK;
 }
 
 int check_problem(ie_ctx* c, const ie_problem& pr) {
@@ -294,99 +520,118 @@ int dd_group(ie_ctx* c, const std::vector<int>& idx, const ie_problem* problems,
   IE_TRY(gb.x.ensure(sizeof(c128) * 3 * maxb * B));
   c128* rhs = gb.rhs.as<c128>();
   c128* x = gb.x.as<c128>();
-  std::vector<double> tols(B);
-  std::vector<GmResult> res(B);
-  std::vector<GmResult> pre(B);  // the judge's cycles in the first sweep of a learned start
-  const double inf = std::numeric_limits<double>::infinity();
-  bool first = true;
-
-  while (true) {
-    bool any = false;
+  if (o.scheme == IE_FGMRES_GS || o.scheme == IE_FGMRES_JACOBI) {
+    // Krylov outer iteration, one problem at a time (its vectors and Hessenberg are per problem)
     for (int b = 0; b < B; ++b) {
-      if (act[b] && sweeps[b] >= o.max_sweeps) act[b] = 0;  // out of sweeps: reported below
-      any = any || act[b];
+      if (!act[b]) continue;
+      Group g1 = g;
+      g1.B = 1;
+      g1.D64 = g.D64 + b * 6 * N;
+      g1.M64 = g.M64 + b * 6 * N;
+      g1.M32 = g.M32 + b * 6 * N;
+      g1.A64 = g.A64 + b * 6 * N;
+      g1.Ai64 = g.Ai64 + b * 6 * N;
+      g1.E0 = g.E0 + b * 3 * N;
+      g1.E = g.E + b * 3 * N;
+      g1.active = g.active + b;
+      IE_HIP(hipMemcpyAsync(g1.active, &act[b], sizeof(int), hipMemcpyHostToDevice, s));
+      IE_TRY(fgmres_one(g1, has[b], o, e0norm[b], stats[idx[b]], &e[b], rhs, x, gb));
     }
-    if (!any) break;
-    IE_HIP(hipMemcpyAsync(g.active, act.data(), sizeof(int) * B, hipMemcpyHostToDevice, s));
-    const c128* src = g.E;
-    if (o.scheme == IE_JACOBI) {
-      IE_HIP(hipMemcpyAsync(g.Eold, g.E, sizeof(c128) * 3 * N * B, hipMemcpyDeviceToDevice, s));
-      src = g.Eold;
-    }
-    for (int i = 0; i < M; ++i) {
-      const int z0 = c->zb[i], z1 = c->zb[i + 1], nzb = z1 - z0;
-      const long nb = long(nzb) * plane;
-      IE_TRY(coupling_rhs(g, src, z0, z1, rhs));
-      // warm start from the previous sweep (for Jacobi src = E at sweep k; for GS block i of E
-      // has not been updated yet in this sweep either)
-      IE_TRY(copy_blocks(src, x, 3 * N, N, plane, z0, nzb, true, B, g.active, s));
-      bool solve = false;
+  } else {
+    std::vector<double> tols(B);
+    std::vector<GmResult> res(B);
+    std::vector<GmResult> pre(B);  // the judge's cycles in the first sweep of a learned start
+    const double inf = std::numeric_limits<double>::infinity();
+    bool first = true;
+
+    while (true) {
+      bool any = false;
       for (int b = 0; b < B; ++b) {
-        const bool live = act[b] && has[b][i];
-        tols[b] = live ? (o.adaptive ? e[b] / 10.0 : o.inner_tol_fixed) : inf;
-        solve = solve || live;
+        if (act[b] && sweeps[b] >= o.max_sweeps) act[b] = 0;  // out of sweeps: reported below
+        any = any || act[b];
       }
-      std::fill(pre.begin(), pre.end(), GmResult{});
-      if (solve && first && o.init == IE_INIT_LEARNED) {
-        // first sweep: one restart cycle of GMRES from the learned guess and one from the
-        // default start; each block continues from whichever reached the smaller residual
-        Plan& BP = *c->block_plan(nzb);
-        IE_TRY(gb.xl.ensure(sizeof(c128) * 3 * nb * B));
-        c128* xl = gb.xl.as<c128>();
-        IE_TRY(nn_predict_blocks((ie_nn*)o.nn, c, BP, g.D64 + long(z0) * plane, N, 6 * N, rhs, xl,
-                                 B, s));
-        ie_gmres_opts one = o.inner;
-        one.max_its = o.inner.restart;
-        std::vector<GmResult> rl(B), rd(B);
-        IE_TRY(block_solve(g, BP, z0, rhs, xl, tols.data(), one, rl.data()));
-        IE_TRY(block_solve(g, BP, z0, rhs, x, tols.data(), one, rd.data()));
+      if (!any) break;
+      IE_HIP(hipMemcpyAsync(g.active, act.data(), sizeof(int) * B, hipMemcpyHostToDevice, s));
+      const c128* src = g.E;
+      if (o.scheme == IE_JACOBI) {
+        IE_HIP(hipMemcpyAsync(g.Eold, g.E, sizeof(c128) * 3 * N * B, hipMemcpyDeviceToDevice, s));
+        src = g.Eold;
+      }
+      for (int i = 0; i < M; ++i) {
+        const int z0 = c->zb[i], z1 = c->zb[i + 1], nzb = z1 - z0;
+        const long nb = long(nzb) * plane;
+        IE_TRY(coupling_rhs(g, src, z0, z1, rhs));
+        // warm start from the previous sweep (for Jacobi src = E at sweep k; for GS block i of E
+        // has not been updated yet in this sweep either)
+        IE_TRY(copy_blocks(src, x, 3 * N, N, plane, z0, nzb, true, B, g.active, s));
+        bool solve = false;
         for (int b = 0; b < B; ++b) {
-          if (!(act[b] && has[b][i])) continue;
-          pre[b].its = rl[b].its + rd[b].its;
-          pre[b].mv64 = rl[b].mv64 + rd[b].mv64;
-          pre[b].mv32 = rl[b].mv32 + rd[b].mv32;
-          pre[b].graph_cycles = rl[b].graph_cycles + rd[b].graph_cycles;
-          if (rl[b].relres < rd[b].relres) {
-            stats[idx[b]].learned_used += 1;
-            IE_HIP(hipMemcpyAsync(x + b * 3 * nb, xl + b * 3 * nb, sizeof(c128) * 3 * nb,
-                                  hipMemcpyDeviceToDevice, s));
+          const bool live = act[b] && has[b][i];
+          tols[b] = live ? (o.adaptive ? e[b] / 10.0 : o.inner_tol_fixed) : inf;
+          solve = solve || live;
+        }
+        std::fill(pre.begin(), pre.end(), GmResult{});
+        if (solve && first && o.init == IE_INIT_LEARNED) {
+          // first sweep: one restart cycle of GMRES from the learned guess and one from the
+          // default start; each block continues from whichever reached the smaller residual
+          Plan& BP = *c->block_plan(nzb);
+          IE_TRY(gb.xl.ensure(sizeof(c128) * 3 * nb * B));
+          c128* xl = gb.xl.as<c128>();
+          IE_TRY(nn_predict_blocks((ie_nn*)o.nn, c, BP, g.D64 + long(z0) * plane, N, 6 * N, rhs, xl,
+                                   B, s));
+          ie_gmres_opts one = o.inner;
+          one.max_its = o.inner.restart;
+          std::vector<GmResult> rl(B), rd(B);
+          IE_TRY(block_solve(g, BP, z0, rhs, xl, tols.data(), one, rl.data()));
+          IE_TRY(block_solve(g, BP, z0, rhs, x, tols.data(), one, rd.data()));
+          for (int b = 0; b < B; ++b) {
+            if (!(act[b] && has[b][i])) continue;
+            pre[b].its = rl[b].its + rd[b].its;
+            pre[b].mv64 = rl[b].mv64 + rd[b].mv64;
+            pre[b].mv32 = rl[b].mv32 + rd[b].mv32;
+            pre[b].graph_cycles = rl[b].graph_cycles + rd[b].graph_cycles;
+            if (rl[b].relres < rd[b].relres) {
+              stats[idx[b]].learned_used += 1;
+              IE_HIP(hipMemcpyAsync(x + b * 3 * nb, xl + b * 3 * nb, sizeof(c128) * 3 * nb,
+                                    hipMemcpyDeviceToDevice, s));
+            }
+          }
+        }
+        if (solve)
+          IE_TRY(block_solve(g, *c->block_plan(nzb), z0, rhs, x, tols.data(), o.inner, res.data()));
+        for (int b = 0; b < B; ++b) {
+          if (!act[b]) continue;
+          // blocks without contrast have A_ii = I: E(i) = b_i
+          const c128* from = has[b][i] ? x + b * 3 * nb : rhs + b * 3 * nb;
+          for (int cc = 0; cc < 3; ++cc)
+            IE_HIP(hipMemcpyAsync(g.E + b * 3 * N + cc * N + z0 * plane, from + cc * nb,
+                                  sizeof(c128) * nb, hipMemcpyDeviceToDevice, s));
+          ie_dd_stats& st = stats[idx[b]];
+          st.full_matvecs += 1;
+          st.matvecs64 += 1;
+          if (has[b][i]) {
+            st.block_its[sweeps[b]][i] = res[b].its + pre[b].its;
+            st.matvecs64 += res[b].mv64 + pre[b].mv64;
+            st.matvecs32 += res[b].mv32 + pre[b].mv32;
+            st.graph_cycles += res[b].graph_cycles + pre[b].graph_cycles;
           }
         }
       }
-      if (solve)
-        IE_TRY(block_solve(g, *c->block_plan(nzb), z0, rhs, x, tols.data(), o.inner, res.data()));
+      first = false;
+      IE_TRY(full_relres(g, e0norm.data(), e.data()));
       for (int b = 0; b < B; ++b) {
         if (!act[b]) continue;
-        // blocks without contrast have A_ii = I: E(i) = b_i
-        const c128* from = has[b][i] ? x + b * 3 * nb : rhs + b * 3 * nb;
-        for (int cc = 0; cc < 3; ++cc)
-          IE_HIP(hipMemcpyAsync(g.E + b * 3 * N + cc * N + z0 * plane, from + cc * nb,
-                                sizeof(c128) * nb, hipMemcpyDeviceToDevice, s));
         ie_dd_stats& st = stats[idx[b]];
+        for (int i = 0; i < M; ++i) st.total_its += st.block_its[sweeps[b]][i];
+        sweeps[b] += 1;
+        st.sweeps = sweeps[b];
+        st.relres[sweeps[b]] = e[b];
         st.full_matvecs += 1;
         st.matvecs64 += 1;
-        if (has[b][i]) {
-          st.block_its[sweeps[b]][i] = res[b].its + pre[b].its;
-          st.matvecs64 += res[b].mv64 + pre[b].mv64;
-          st.matvecs32 += res[b].mv32 + pre[b].mv32;
-          st.graph_cycles += res[b].graph_cycles + pre[b].graph_cycles;
-        }
+        if (e[b] <= o.tol) act[b] = 0;
       }
     }
-    first = false;
-    IE_TRY(full_relres(g, e0norm.data(), e.data()));
-    for (int b = 0; b < B; ++b) {
-      if (!act[b]) continue;
-      ie_dd_stats& st = stats[idx[b]];
-      for (int i = 0; i < M; ++i) st.total_its += st.block_its[sweeps[b]][i];
-      sweeps[b] += 1;
-      st.sweeps = sweeps[b];
-      st.relres[sweeps[b]] = e[b];
-      st.full_matvecs += 1;
-      st.matvecs64 += 1;
-      if (e[b] <= o.tol) act[b] = 0;
-    }
-  }
+  }  // stationary sweeps
   // outputs
   for (int b = 0; b < B; ++b) {
     const ie_problem& pr = problems[idx[b]];
@@ -415,7 +660,14 @@ extern "C" int ie_dd_solve(ie_ctx* const* ctxs, int32_t nproblems, const ie_prob
     return fail(IE_EINVAL, "NULL argument or no problems");
   const ie_dd_opts& o = *opts;
   if (!(o.tol >= 0)) return fail(IE_EINVAL, "bad tol");
-  if (o.scheme != IE_GS && o.scheme != IE_JACOBI) return fail(IE_EINVAL, "bad scheme");
+  if (o.scheme != IE_GS && o.scheme != IE_JACOBI && o.scheme != IE_FGMRES_GS &&
+      o.scheme != IE_FGMRES_JACOBI)
+    return fail(IE_EINVAL, "bad scheme");
+  const bool krylov = o.scheme == IE_FGMRES_GS || o.scheme == IE_FGMRES_JACOBI;
+  if (krylov && o.init == IE_INIT_LEARNED)
+    return fail(IE_EINVAL, "the learned start applies to the stationary sweeps only");
+  if (krylov && !(o.inner_tol_fixed > 0))
+    return fail(IE_EINVAL, "the Krylov outer iteration needs inner_tol_fixed > 0");
   if (o.inner.form != IE_CONVENTIONAL && o.inner.form != IE_CIE)
     return fail(IE_EINVAL, "bad inner form");
   if (o.inner.precision != IE_FP64 && o.inner.precision != IE_MIXED)

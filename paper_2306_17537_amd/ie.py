@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libie_gfx950.so")
 IE_OK, IE_ENOCONV, IE_EINVAL, IE_ENOMEM, IE_EDEVICE, IE_ESTATE = 0, 1, -1, -2, -3, -4
 IE_FP64, IE_MIXED = 1, 2
 IE_CONVENTIONAL, IE_CIE, IE_GREEN_ONLY, IE_SCATTER = 0, 1, 2, 3
-IE_GS, IE_JACOBI = 0, 1
+IE_GS, IE_JACOBI, IE_FGMRES_GS, IE_FGMRES_JACOBI = 0, 1, 2, 3
 IE_INIT_BACKGROUND, IE_INIT_USER, IE_INIT_LEARNED, IE_INIT_ZERO = 0, 1, 2, 3
 IE_MAG_DIPOLE, IE_ELEC_DIPOLE = 0, 1
 IE_MAX_SWEEPS, IE_MAX_BLOCKS = 128, 16
