@@ -3,7 +3,7 @@
 
 Workload (one "step"): one complete solve of the 64^3 three-layer dipping TI model (cell
 0.25 m, 2 MHz, z dipole at the centre) to full-domain relative residual 1e-6 (eq. 9) by the
-chosen form: background field, contrast preparation and restarted GMRES(10) from a zero start
+chosen form: background field, contrast preparation and restarted GMRES(12) from a zero start
 on the contraction form in mixed precision (complex64 Krylov vectors and convolutions; float64
 residual at every restart, Arnoldi scalars, Givens rotations and solution accumulation).  The Green's spectrum is
 built once before the timed region (it depends on grid and medium only) and timed separately.
@@ -14,7 +14,8 @@ Printed: one JSON line with the contract fields plus
   roofline     - dominant kernel of the timed region: algorithmic bytes / duration, HIP events
                  on the launch stream (library launch profiler), against 8 TB/s;
   cpu_baseline - the CPU oracle on this host, sampled and scaled to one solve;
-  plain_fp64   - the same solve in plain float64 (better of full-domain GMRES and DD-GS-A);
+  plain_fp64   - the same solve in plain float64 (best of full-domain GMRES(10), GMRES(12) and
+                 DD-GS-A);
   accuracy     - relative L2 error of the anomalous field against the stored oracle reference.
 """
 import argparse
@@ -30,6 +31,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "time-to-solve @ rel.resid 1e-6 + matvec HBM GB/s; plain FP64 vs mixed+NN"
 HBM_PEAK_GBS = 8000.0
+# Restart length of the chosen form.  The paper runs GMRES(10); in mixed precision 12 took 2-9 %
+# less time than 10 on this model and on four held-out seeds of it (fewer restarts, each a
+# float64 residual), 16 was no better on two of the five.  Plain float64 is timed at both.
+CHOSEN_RESTART = 12
 
 
 def parse():
@@ -103,11 +108,12 @@ def main():
     E0 = torch.zeros_like(E)
     ie.ie_background_field(ctx, p.sources, E0)
 
-    def solve_full(precision):
+    def solve_full(precision, restart=10):
         x = torch.zeros_like(E0)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        _, gst = ie.ie_gmres(ctx, s6, E0, x, tol=1e-6, precision=precision, form=ie.IE_CIE)
+        _, gst = ie.ie_gmres(ctx, s6, E0, x, tol=1e-6, precision=precision, form=ie.IE_CIE,
+                             restart=restart)
         torch.cuda.synchronize()
         return time.perf_counter() - t, gst, (x - E0).cpu().numpy()
 
@@ -118,7 +124,8 @@ def main():
         t = time.perf_counter()
         ie.ie_background_field(ctx, p.sources, E0)
         x = torch.zeros_like(E0)
-        _, gst = ie.ie_gmres(ctx, s6, E0, x, tol=1e-6, precision=ie.IE_MIXED, form=ie.IE_CIE)
+        _, gst = ie.ie_gmres(ctx, s6, E0, x, tol=1e-6, precision=ie.IE_MIXED, form=ie.IE_CIE,
+                             restart=CHOSEN_RESTART)
         torch.sub(x, E0, out=Ea)
         torch.cuda.synchronize()
         return time.perf_counter() - t, gst
@@ -217,6 +224,8 @@ def main():
         Ea_dd = Ea.cpu().numpy()
         solve_full(ie.IE_FP64)
         t_full, gst, Ea_full = solve_full(ie.IE_FP64)
+        solve_full(ie.IE_FP64, CHOSEN_RESTART)
+        t_full_r, gst_r, _ = solve_full(ie.IE_FP64, CHOSEN_RESTART)
         solve_dd(chosen)
         t_gm, st_gm = solve_dd(chosen)
         Ea_gm = Ea.cpu().numpy()
@@ -235,8 +244,10 @@ def main():
         Ea_fg = Ea.cpu().numpy()
         plain = dict(dd_gs_a_fp64_s=round(t_dd, 5), dd_sweeps=st_dd.sweeps, dd_its=st_dd.total_its,
                      full_gmres_fp64_s=round(t_full, 5), full_its=gst.its,
-                     best_s=round(min(t_dd, t_full), 5),
-                     speedup_chosen_vs_plain=round(min(t_dd, t_full) / (total / args.steps), 3))
+                     full_gmres12_fp64_s=round(t_full_r, 5), full12_its=gst_r.its,
+                     best_s=round(min(t_dd, t_full, t_full_r), 5),
+                     speedup_chosen_vs_plain=round(min(t_dd, t_full, t_full_r) /
+                                                   (total / args.steps), 3))
         variants = dict(dd_gs_a_mixed_s=round(t_gm, 5), gs_mixed_sweeps=st_gm.sweeps,
                         gs_mixed_its=st_gm.total_its,
                         dd_jacobi_a_mixed_s=round(t_j, 5), jacobi_sweeps=st_j.sweeps,
@@ -277,8 +288,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "config1: 64^3 cells of 0.25 m, 3-layer TI dipping 30 deg "
                                "(seed 101), 2 MHz, z dipole; full-domain contraction-form "
-                               "GMRES(10) from zero, complex64 Krylov/convolutions + float64 "
-                               "restarts, tol 1e-6",
+                               f"GMRES({CHOSEN_RESTART}) from zero, complex64 Krylov/"
+                               "convolutions + float64 restarts, tol 1e-6",
                    "grid": list(p.n), "its": chosen_stats.its,
                    "refinements": chosen_stats.refinements, "matvecs32": chosen_stats.matvecs32,
                    "matvecs64": chosen_stats.matvecs64, "graph_cycles": chosen_stats.graph_cycles,
@@ -511,7 +522,7 @@ def batch_bench(ie, torch):
 
 
 def cpu_baseline(p, gst):
-    """The oracle on this host: time restarted GMRES(10) iterations of its full-domain
+    """The oracle on this host: time restarted GMRES iterations of its full-domain
     contraction-form solve on a bounded sample, then scale to one solve with the iteration and
     restart counts of the GPU run."""
     import scipy.fft
@@ -528,14 +539,15 @@ def cpu_baseline(p, gst):
         its = 40
         t0 = time.perf_counter()
         _, info = gmres(lambda v: operator.apply_C(st.Ghat, b, v, p.sigma0, st.n), rhs, x0, 1e-14,
-                        10, its)
+                        CHOSEN_RESTART, its)
         t_sample = time.perf_counter() - t0
         # one iteration = one operator application; each restart adds one more (true residual)
         napp = info["its"] + info["restarts"] + 2
         t_app = t_sample / napp
     est = (gst.its + gst.restarts + 2) * t_app
     return {"value": round(est, 3), "unit": "s", "cores": cores, "kind": "oracle",
-            "sample": f"oracle FP64 full-domain contraction-form GMRES(10) on this host: "
+            "sample": f"oracle FP64 full-domain contraction-form GMRES({CHOSEN_RESTART}) on this "
+                      f"host: "
                       f"{info['its']} iterations ({napp} operator applications, "
                       f"{t_sample:.2f} s, {t_app:.3f} s each), scaled to the GPU solve's "
                       f"{gst.its} iterations and {gst.restarts + 1} restarts; oracle setup "

@@ -17,12 +17,17 @@ constexpr int RB = 256;             // threads per reduction block
 constexpr int NWV = RB / 64;        // wavefronts per block
 constexpr int PWD = 2 * MAXM + 1;  // doubles per block partial (at most 2 MAXM dots + norm)
 
-enum Fin { FIN_NONE = 0, FIN_H = 1, FIN_GIVENS = 2, FIN_CYCLE = 3, FIN_BNORM = 4 };
+enum Fin { FIN_NONE = 0, FIN_H = 1, FIN_GIVENS = 2, FIN_CYCLE = 3, FIN_BNORM = 4, FIN_HG = 5 };
 
+// Blocks of a reduction pass: about eight elements per thread, at most RED_MAX blocks (two per
+// CU).  Few blocks keep the per-block reduction tail small; the passes unroll their element
+// loop so that a wave still has many loads in flight.  The finalisation sums at most RED_MAX
+// partials per slot.
+constexpr int RED_MAX = 512;
 int red_grid(long n) {
   long g = (n + RB * 8 - 1) / (RB * 8);
   if (g < 1) g = 1;
-  if (g > 512) g = 512;
+  if (g > RED_MAX) g = RED_MAX;
   return int(g);
 }
 
@@ -42,20 +47,29 @@ struct Slots {
   static constexpr int NS = 2 * CM;
 };
 
-// Block-wide sums of the needed slots (k < nd, and NS if nrm); thread k writes out[k * os].
-template <int NV>
-__device__ __forceinline__ void block_sums(double (&v)[NV], int nd, bool nrm, double* sh,
-                                           double* out, long os = 1) {
+// Block-wide sums of the slots a pass produces: the dots (slots [0, NV - 1)) if DOTS and the
+// squared norm (slot NV - 1) if NRM.  The shuffle steps of all slots are interleaved, so a wave
+// waits for the shuffle latency once per step rather than once per slot and step.  Thread k
+// writes out[k * os] for the slots the caller needs (k < nd, and NV - 1 if NRM).
+template <int NV, bool DOTS, bool NRM>
+__device__ __forceinline__ void block_sums(double (&v)[NV], int nd, double* sh, double* out,
+                                           long os = 1) {
+  constexpr int ND = DOTS ? NV - 1 : 0;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int k = 0; k < NV; ++k)
-    if (k < nd || (nrm && k == NV - 1)) {
-      const double r = wave_sum(v[k]);
-      if (lane == 0) sh[wv * NV + k] = r;
-    }
+  for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+    for (int k = 0; k < ND; ++k) v[k] += __shfl_xor(v[k], off, 64);
+    if (NRM) v[NV - 1] += __shfl_xor(v[NV - 1], off, 64);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < ND; ++k) sh[wv * NV + k] = v[k];
+    if (NRM) sh[wv * NV + NV - 1] = v[NV - 1];
+  }
   __syncthreads();
   for (int k = threadIdx.x; k < NV; k += RB) {
-    if (k < nd || (nrm && k == NV - 1)) {
+    if (k < nd || (NRM && k == NV - 1)) {
       double r = 0;
 #pragma unroll
       for (int q = 0; q < NWV; ++q) r += sh[q * NV + k];
@@ -65,37 +79,73 @@ __device__ __forceinline__ void block_sums(double (&v)[NV], int nd, bool nrm, do
 }
 
 // Sum the G block partials of problem b (stored slot-major, part[(b PWD + slot) G + block], so
-// that consecutive threads read consecutive blocks; every thread a fixed subset of blocks, then
-// one block reduction; deterministic) into fin[].  Called by a one-block kernel.
-template <int NV>
-__device__ void reduce_partials(const double* part, int b, int G, int nd, bool nrm, double* sh,
-                                double* fin) {
+// that consecutive threads read consecutive blocks) into fin[]: the dot slots [0, NV - 1) if
+// DOTS, the norm slot NV - 1 if NRM.  Every slot index below NV lies inside the partial buffer
+// (NV <= PWD) and block indices past G are clamped to 0 and masked after loading, so all loads
+// of one chunk are unconditional and in flight together.  Fixed summation order: deterministic.
+// Called by a one-block kernel.
+template <int NV, bool DOTS, bool NRM>
+__device__ __forceinline__ void reduce_partials(const double* part, int b, int G, int nd,
+                                                double* sh, double* fin) {
+  constexpr int K0 = DOTS ? 0 : NV - 1, K1 = NRM ? NV : NV - 1;
   double a[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) a[k] = 0;
   const double* pb = part + long(b) * PWD * G;
-  for (int q = threadIdx.x; q < G; q += RB) {
-    double v[NV];  // all slot loads of this block index are issued before the sums
+  for (int q0 = 0; q0 < G; q0 += 2 * RB) {
+    const int q1 = q0 + threadIdx.x, q2 = q1 + RB;
+    const bool in1 = q1 < G, in2 = q2 < G;
+    const int c1 = in1 ? q1 : 0, c2 = in2 ? q2 : 0;
+    double v1[NV], v2[NV];
 #pragma unroll
-    for (int k = 0; k < NV; ++k)
-      v[k] = (k < nd || (nrm && k == NV - 1)) ? pb[long(k) * G + q] : 0.0;
+    for (int k = K0; k < K1; ++k) {
+      v1[k] = pb[long(k) * G + c1];
+      v2[k] = pb[long(k) * G + c2];
+    }
 #pragma unroll
-    for (int k = 0; k < NV; ++k) a[k] += v[k];
+    for (int k = K0; k < K1; ++k) a[k] += (in1 ? v1[k] : 0.0) + (in2 ? v2[k] : 0.0);
   }
-  block_sums<NV>(a, nd, nrm, sh, fin);
+  block_sums<NV, DOTS, NRM>(a, nd, sh, fin);
   __syncthreads();
 }
 
-// Givens step for Hessenberg column j once h_{j+1,j}^2 = hn2 is known.  Called by all threads
-// of the block: the column, the previous rotations and g[j] are staged in shared memory by
-// parallel loads, thread 0 applies the rotations, and the column is written back in parallel.
-__device__ void givens_update(GmState& s, int j, double hn2, int* flags, int batch, int b) {
+// State a Givens step reads, loaded by each thread at the start of the finalisation so that these
+// loads are in flight together with the partial sums: the column entry H[j][t] (t <= j), the
+// earlier rotations cs/sn[t] (t < j) and, in thread 0, g[j] and the counters.
+struct GivensPre {
+  c128 h, c, s, gj;
+  double target;
+  int its, max_its;
+};
+__device__ __forceinline__ GivensPre givens_prefetch(const GmState& S, int j, bool column) {
+  GivensPre p{};
+  const int t = threadIdx.x;
+  if (column && t <= j) p.h = S.H[j][t];
+  if (t < j) {
+    p.c = S.cs[t];
+    p.s = S.sn[t];
+  }
+  if (t == 0) {
+    p.gj = S.g[j];
+    p.target = S.target;
+    p.its = S.its;
+    p.max_its = S.max_its;
+  }
+  return p;
+}
+
+// Givens step for Hessenberg column j (entries pre.h of threads t <= j) once h_{j+1,j}^2 = hn2
+// is known.  Called by all threads of the block: the column and the previous rotations are
+// staged in shared memory, thread 0 applies the rotations, and the column is written back in
+// parallel.
+__device__ __forceinline__ void givens_update(GmState& s, int j, double hn2, int* flags,
+                                              int batch, int b, const GivensPre& pre) {
   __shared__ c128 Hs[MAXM + 1], cs[MAXM], sn[MAXM];
   const int t = threadIdx.x;
-  if (t <= j) Hs[t] = s.H[j][t];
+  if (t <= j) Hs[t] = pre.h;
   if (t < j) {
-    cs[t] = s.cs[t];
-    sn[t] = s.sn[t];
+    cs[t] = pre.c;
+    sn[t] = pre.s;
   }
   __syncthreads();
   if (t == 0) {
@@ -120,18 +170,21 @@ __device__ void givens_update(GmState& s, int j, double hn2, int* flags, int bat
     s.sn[j] = sg;
     H[j] = c128{den, 0};
     H[j + 1] = c128{0, 0};
-    const c128 gj = s.g[j];
+    const c128 gj = pre.gj;
     const c128 g1 = c128{0, 0} - sg * gj;
     s.g[j + 1] = g1;
     s.g[j] = cjmul(c, gj);
-    s.est = sqrt(g1.re * g1.re + g1.im * g1.im);
+    const double est = sqrt(g1.re * g1.re + g1.im * g1.im);
+    const int its = pre.its + 1;
+    s.est = est;
     s.k = j + 1;
-    s.its += 1;
+    s.its = its;
     const bool brk = (hn == 0.0) || (den == 0.0);
     s.breakdown = brk ? 1 : 0;
     s.nv[j + 1] = brk ? 0.0 : 1.0 / hn;
-    if (s.est <= s.target || s.its >= s.max_its || brk) s.active = 0;
-    flags[j * batch + b] = s.active;
+    const int active = (est <= pre.target || its >= pre.max_its || brk) ? 0 : 1;
+    s.active = active;
+    flags[j * batch + b] = active;
   }
   __syncthreads();
   if (t <= j + 1) s.H[j][t] = Hs[t];
@@ -140,9 +193,10 @@ __device__ void givens_update(GmState& s, int j, double hn2, int* flags, int bat
 // Fused Gram-Schmidt pass over w (per problem b = blockIdx.z), with v_i = nv[i] V_i:
 //   UPD : w <- w - sum_{i<count} hc[i] v_i
 //   DOTS: <v_i, w> for i < count;  NRM: ||w||^2
-// and a last-block finalisation FIN:
+// writing one partial per block and slot; k_fin, launched right after it, sums them and does:
 //   FIN_H      : hc[i] = <v_i, w>, H[j][i] = (first ? 0 : H[j][i]) + hc[i]
 //   FIN_GIVENS : h_{j+1,j} = ||w||, rotations, residual estimate, active flag, nv[j+1]
+//   FIN_HG     : FIN_H with first = 1, then FIN_GIVENS with h_{j+1,j}^2 = ||w||^2 - sum |hc_i|^2
 //   FIN_CYCLE  : beta = ||w||, g = beta e1, active unless converged (start of a restart cycle)
 //   FIN_BNORM  : ||b||, target = tol ||b||, counters reset (start of a solve)
 template <typename TA, typename TW, bool UPD, bool DOTS, bool NRM, int FIN, int CM>
@@ -153,7 +207,8 @@ __global__ void __launch_bounds__(RB)
   const int b = blockIdx.z;
   GmState& S = st[b];
   if (FIN != FIN_CYCLE && FIN != FIN_BNORM && S.active == 0) {
-    if (FIN == FIN_GIVENS && blockIdx.x == 0 && threadIdx.x == 0) flags[j * batch + b] = 0;
+    if ((FIN == FIN_GIVENS || FIN == FIN_HG) && blockIdx.x == 0 && threadIdx.x == 0)
+      flags[j * batch + b] = 0;
     return;
   }
   using SL = Slots<CM>;
@@ -172,43 +227,66 @@ __global__ void __launch_bounds__(RB)
   double acc[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k] = 0;
+  // U elements per thread and loop pass, all their loads issued before any is used, so that
+  // each wave keeps U (count + 1) loads in flight; indices past n are clamped to a valid
+  // element, their results masked and their stores skipped.
+  constexpr int U = (sizeof(TA) == 4 && sizeof(TW) == 4) ? 4 : 2;
   const long stride = long(gridDim.x) * RB;
-  for (long e = long(blockIdx.x) * RB + threadIdx.x; e < n; e += stride) {
-    cx<TA> vv[CM];
+  for (long e0 = long(blockIdx.x) * RB + threadIdx.x; e0 < n; e0 += U * stride) {
+    long ec[U];
+    bool in[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long e = e0 + u * stride;
+      in[u] = e < n;
+      ec[u] = in[u] ? e : e0;
+    }
+    cx<TA> vv[U][CM];
 #pragma unroll
     for (int i = 0; i < CM; ++i)
-      if ((UPD || DOTS) && i < count) vv[i] = Vb[i * vstride + e];
-    cx<TW> wv = wb[e];
-    if (UPD) {
-      c128 wd = up(wv);
+      if ((UPD || DOTS) && i < count) {
 #pragma unroll
-      for (int i = 0; i < CM; ++i)
-        if (i < count) wd = wd - h[i] * up(vv[i]);
-      wv = cx<TW>{TW(wd.re), TW(wd.im)};
-      wb[e] = wv;
-    }
-    const c128 wd = up(wv);
-    if (DOTS) {
+        for (int u = 0; u < U; ++u) vv[u][i] = Vb[i * vstride + ec[u]];
+      }
+    cx<TW> wv[U];
 #pragma unroll
-      for (int i = 0; i < CM; ++i)
-        if (i < count) {
-          const c128 d = cjmul(up(vv[i]), wd);
-          acc[2 * i] += d.re;
-          acc[2 * i + 1] += d.im;
-        }
+    for (int u = 0; u < U; ++u) wv[u] = wb[ec[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (UPD) {
+        c128 wd = up(wv[u]);
+#pragma unroll
+        for (int i = 0; i < CM; ++i)
+          if (i < count) wd = wd - h[i] * up(vv[u][i]);
+        wv[u] = cx<TW>{TW(wd.re), TW(wd.im)};
+        if (in[u]) wb[ec[u]] = wv[u];
+      }
+      const c128 wd = in[u] ? up(wv[u]) : c128{0, 0};
+      if (DOTS) {
+#pragma unroll
+        for (int i = 0; i < CM; ++i)
+          if (i < count) {
+            const c128 d = cjmul(up(vv[u][i]), wd);
+            acc[2 * i] += d.re;
+            acc[2 * i + 1] += d.im;
+          }
+      }
+      if (NRM) acc[SL::NS] += wd.re * wd.re + wd.im * wd.im;
     }
-    if (NRM) acc[SL::NS] += wd.re * wd.re + wd.im * wd.im;
   }
   const int nd = DOTS ? 2 * count : 0;
   // slot-major partials: slot k of this block at part[(b PWD + k) G + blockIdx.x] (the
   // finalisation kernel launched after this one uses the same register bucket CM)
   double* pb = part + long(b) * PWD * gridDim.x + blockIdx.x;
-  block_sums<NV>(acc, nd, NRM, sh, pb, long(gridDim.x));
+  if (DOTS || NRM) block_sums<NV, DOTS, NRM>(acc, nd, sh, pb, long(gridDim.x));
 }
 
 // Finalisation of a reduction (one block per problem):
 //   FIN_H      : hc[i] = <v_i, w>, H[j][i] = (first ? 0 : H[j][i]) + hc[i]
 //   FIN_GIVENS : h_{j+1,j} = ||w||, rotations, residual estimate, active flag, nv[j+1]
+//   FIN_HG     : both from one pass over w (dots and ||w||^2): hc[i], H[j][i] = hc[i] and
+//                h_{j+1,j}^2 = ||w||^2 - sum_i |hc_i|^2, the squared norm of w - sum hc_i v_i
+//                for orthonormal v_i (clamped at 0, where the Givens step reports breakdown)
 //   FIN_CYCLE  : beta = ||r||, g = beta e1, active unless converged (start of a restart cycle)
 //   FIN_BNORM  : ||b||, target = tol ||b||, counters reset (start of a solve)
 template <int FIN, int CM>
@@ -218,30 +296,51 @@ __global__ void __launch_bounds__(RB)
           const double* __restrict__ tols) {
   const int b = blockIdx.x;
   GmState& S = st[b];
-  if (FIN == FIN_H || FIN == FIN_GIVENS) {
-    if (S.active == 0) {
-      if (FIN == FIN_GIVENS && threadIdx.x == 0) flags[j * batch + b] = 0;
-      return;
-    }
-  }
   using SL = Slots<CM>;
   constexpr int NV = SL::NV;
   __shared__ double sh[NWV * NV];
   __shared__ double fin[NV];
-  const int nd = FIN == FIN_H ? 2 * count : 0;
-  reduce_partials<NV>(part, b, G, nd, FIN != FIN_H, sh, fin);
+  constexpr bool STEP = FIN == FIN_H || FIN == FIN_GIVENS || FIN == FIN_HG;
+  constexpr bool FD = FIN == FIN_H || FIN == FIN_HG, FN = FIN != FIN_H;
+  constexpr bool GV = FIN == FIN_GIVENS || FIN == FIN_HG;
+  const int t = threadIdx.x;
+  // every state load is issued before the partial sums; a retired problem (active == 0, the
+  // same for the whole block) leaves after them
+  const int act = STEP ? S.active : 1;
+  const double nvt = (FD && t < count) ? S.nv[t] : 0.0;
+  const c128 hprev = (FIN == FIN_H && !first && t < count) ? S.H[j][t] : c128{0, 0};
+  GivensPre pre{};
+  if (GV) pre = givens_prefetch(S, j, FIN == FIN_GIVENS);
+  const int nd = FD ? 2 * count : 0;
+  reduce_partials<NV, FD, FN>(part, b, G, nd, sh, fin);
+  if (STEP && act == 0) {
+    if (GV && t == 0) flags[j * batch + b] = 0;
+    return;
+  }
+  if (FIN == FIN_HG) {
+    __shared__ double sq[CM];
+    if (t < count) {  // one coefficient per thread
+      const c128 hv = c128{nvt * fin[2 * t], nvt * fin[2 * t + 1]};
+      S.hc[t] = hv;
+      pre.h = hv;
+      sq[t] = hv.re * hv.re + hv.im * hv.im;
+    }
+    __syncthreads();
+    double hn2 = fin[SL::NS];
+    for (int q = 0; q < count; ++q) hn2 -= sq[q];
+    givens_update(S, j, hn2 > 0.0 ? hn2 : 0.0, flags, batch, b, pre);
+    return;
+  }
   if (FIN == FIN_H) {
-    const int i = threadIdx.x;  // one coefficient per thread
-    if (i < count) {
-      const double nvi = S.nv[i];
-      const c128 hv = c128{nvi * fin[2 * i], nvi * fin[2 * i + 1]};
-      S.hc[i] = hv;
-      S.H[j][i] = first ? hv : S.H[j][i] + hv;
+    if (t < count) {  // one coefficient per thread
+      const c128 hv = c128{nvt * fin[2 * t], nvt * fin[2 * t + 1]};
+      S.hc[t] = hv;
+      S.H[j][t] = first ? hv : hprev + hv;
     }
     return;
   }
   if (FIN == FIN_GIVENS) {
-    givens_update(S, j, fin[SL::NS], flags, batch, b);
+    givens_update(S, j, fin[SL::NS], flags, batch, b, pre);
     return;
   }
   if (threadIdx.x != 0) return;
@@ -355,13 +454,35 @@ __global__ void __launch_bounds__(RB)
   for (int i = 0; i < MAXM; ++i) y[i] = i < k ? ys[i] : c128{0, 0};
   c128* xb = x + b * xbs;
   const cx<TA>* Vb = V + b * vbs;
+  // U elements per thread and pass with all loads issued first (as in k_orth)
+  constexpr int U = 2;
   const long stride = long(gridDim.x) * RB;
-  for (long e = long(blockIdx.x) * RB + threadIdx.x; e < n; e += stride) {
-    c128 acc = xb[e];
+  for (long e0 = long(blockIdx.x) * RB + threadIdx.x; e0 < n; e0 += U * stride) {
+    long ec[U];
+    bool in[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long e = e0 + u * stride;
+      in[u] = e < n;
+      ec[u] = in[u] ? e : e0;
+    }
+    cx<TA> vv[U][MAXM];
 #pragma unroll
     for (int i = 0; i < MAXM; ++i)
-      if (i < k) acc = acc + y[i] * up(Vb[i * vstride + e]);
-    xb[e] = acc;
+      if (i < k) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) vv[u][i] = Vb[i * vstride + ec[u]];
+      }
+    c128 acc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[u] = xb[ec[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int i = 0; i < MAXM; ++i)
+        if (i < k) acc[u] = acc[u] + y[i] * up(vv[u][i]);
+      if (in[u]) xb[ec[u]] = acc[u];
+    }
   }
 }
 
@@ -569,17 +690,28 @@ static int gmres_impl(Plan& p, const OpDesc& op, const c128* rhs, c128* x, int b
       a.active = act;
       a.active_bs = act_bs;
       IE_TRY(launch_matvec<TA>(p, a, batch, s, twa));
-      // Gram-Schmidt: h = V^H w (+ H column), w -= V h with ||w|| and the Givens update
-      IE_TRY((launch_orth<TA, TA, false, true, false, FIN_H>("orth_dots", tg, nb * sa * (j + 2),
-                                                             vgrid, s, V, n, vbs, w1, vbs, n, j + 1,
-                                                             j, 1, st, part, flags, batch, 0.0, 0)));
-      if (reorth)
+      if (!reorth) {
+        // classical Gram-Schmidt: h = V^H w and ||w||^2 in one pass, the H column, h_{j+1,j}
+        // (Pythagoras) and the Givens update; then w -= V h, a pass with no reduction
+        IE_TRY((launch_orth<TA, TA, false, true, true, FIN_HG>(
+            "orth_dots_norm", tg, nb * sa * (j + 2), vgrid, s, V, n, vbs, w1, vbs, n, j + 1, j, 1,
+            st, part, flags, batch, 0.0, 0)));
+        IE_TRY((launch_orth<TA, TA, true, false, false, FIN_NONE>(
+            "orth_upd", tg, nb * sa * (j + 3), vgrid, s, V, n, vbs, w1, vbs, n, j + 1, j, 0, st,
+            part, flags, batch, 0.0, 0)));
+      } else {
+        // CGS2: h = V^H w (+ H column); w -= V h with the second pass's dots added to the
+        // column; w -= V h' with ||w|| and the Givens update
+        IE_TRY((launch_orth<TA, TA, false, true, false, FIN_H>(
+            "orth_dots", tg, nb * sa * (j + 2), vgrid, s, V, n, vbs, w1, vbs, n, j + 1, j, 1, st,
+            part, flags, batch, 0.0, 0)));
         IE_TRY((launch_orth<TA, TA, true, true, false, FIN_H>(
             "orth_upd_dots", tg, nb * sa * (j + 3), vgrid, s, V, n, vbs, w1, vbs, n, j + 1, j, 0, st,
             part, flags, batch, 0.0, 0)));
-      IE_TRY((launch_orth<TA, TA, true, false, true, FIN_GIVENS>(
-          "orth_upd_norm", tg, nb * sa * (j + 3), vgrid, s, V, n, vbs, w1, vbs, n, j + 1, j, 0, st,
-          part, flags, batch, 0.0, 0)));
+        IE_TRY((launch_orth<TA, TA, true, false, true, FIN_GIVENS>(
+            "orth_upd_norm", tg, nb * sa * (j + 3), vgrid, s, V, n, vbs, w1, vbs, n, j + 1, j, 0, st,
+            part, flags, batch, 0.0, 0)));
+      }
       if (lagged) {
         prof_set_group(-1);
         IE_HIP(hipMemcpyAsync(w.hflags + j * batch, flags + j * batch, sizeof(int) * batch,

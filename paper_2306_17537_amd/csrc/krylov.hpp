@@ -4,8 +4,10 @@
 // norm, Hessenberg entry, Givens rotation and the solution accumulation are float64.  Each
 // restart cycle begins from the float64 true residual r = b - A x, so in IE_MIXED every cycle
 // is one step of iterative refinement whose correction comes from a complex64 Arnoldi cycle.
-// Orthogonalisation: classical Gram-Schmidt, optionally repeated once (CGS2), with fused
-// update-and-reduce passes.  All scalar work runs in single-block kernels; per-problem
+// Orthogonalisation: classical Gram-Schmidt with one reduction per Arnoldi step (the dots
+// <v_i, w> and ||w||^2 in one pass over w, h_{j+1,j}^2 = ||w||^2 - sum |h_ij|^2, then the update
+// pass), or CGS2 (repeated once, with fused update-and-reduce passes and the norm of the
+// updated vector).  All scalar work runs in single-block kernels; per-problem
 // `active` flags retire finished cycles inside the queued kernels, so the host synchronises
 // once per restart cycle.
 #pragma once
