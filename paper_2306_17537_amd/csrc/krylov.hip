@@ -31,12 +31,6 @@ int red_grid(long n) {
   return int(g);
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
 template <typename T>
 __device__ __forceinline__ c128 up(cx<T> v) { return c128{double(v.re), double(v.im)}; }
 
@@ -47,32 +41,53 @@ struct Slots {
   static constexpr int NS = 2 * CM;
 };
 
+// One row step of a 16-lane sum: v + v of the lane that the DPP pattern CTRL names (moved as two
+// 32-bit halves).  0xB1 and 0x4E swap lanes within quads (lane ^ 1, lane ^ 2), 0x141 mirrors each
+// half-row (lane i <- 7 - i), 0x140 each row (i <- 15 - i); after the four steps every lane of a
+// 16-lane row holds the row's sum.  These are VALU moves, no LDS traffic.
+template <int CTRL>
+__device__ __forceinline__ double dpp_add(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(u), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(u >> 32), CTRL, 0xF, 0xF, false);
+  return v + __longlong_as_double((static_cast<long long>(hi) << 32) |
+                                  static_cast<unsigned int>(lo));
+}
+
 // Block-wide sums of the slots a pass produces: the dots (slots [0, NV - 1)) if DOTS and the
-// squared norm (slot NV - 1) if NRM.  The shuffle steps of all slots are interleaved, so a wave
-// waits for the shuffle latency once per step rather than once per slot and step.  Thread k
-// writes out[k * os] for the slots the caller needs (k < nd, and NV - 1 if NRM).
+// squared norm (slot NV - 1) if NRM.  Each 16-lane row is summed in registers (four DPP steps,
+// all slots interleaved), the first lane of every row stores its row sums, and thread k adds the
+// 4 NWV row sums of slot k in a fixed order and writes out[k * os] for the slots the caller needs
+// (k < nd, and NV - 1 if NRM).
 template <int NV, bool DOTS, bool NRM>
 __device__ __forceinline__ void block_sums(double (&v)[NV], int nd, double* sh, double* out,
                                            long os = 1) {
   constexpr int ND = DOTS ? NV - 1 : 0;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  constexpr int NR = 4 * NWV;  // 16-lane rows per block
+  const int lane = threadIdx.x & 63, rowid = threadIdx.x >> 4;
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
+  for (int k = 0; k < ND; ++k) v[k] = dpp_add<0xB1>(v[k]);
+  if (NRM) v[NV - 1] = dpp_add<0xB1>(v[NV - 1]);
 #pragma unroll
-    for (int k = 0; k < ND; ++k) v[k] += __shfl_xor(v[k], off, 64);
-    if (NRM) v[NV - 1] += __shfl_xor(v[NV - 1], off, 64);
-  }
-  if (lane == 0) {
+  for (int k = 0; k < ND; ++k) v[k] = dpp_add<0x4E>(v[k]);
+  if (NRM) v[NV - 1] = dpp_add<0x4E>(v[NV - 1]);
 #pragma unroll
-    for (int k = 0; k < ND; ++k) sh[wv * NV + k] = v[k];
-    if (NRM) sh[wv * NV + NV - 1] = v[NV - 1];
+  for (int k = 0; k < ND; ++k) v[k] = dpp_add<0x141>(v[k]);
+  if (NRM) v[NV - 1] = dpp_add<0x141>(v[NV - 1]);
+#pragma unroll
+  for (int k = 0; k < ND; ++k) v[k] = dpp_add<0x140>(v[k]);
+  if (NRM) v[NV - 1] = dpp_add<0x140>(v[NV - 1]);
+  if ((lane & 15) == 0) {
+#pragma unroll
+    for (int k = 0; k < ND; ++k) sh[rowid * NV + k] = v[k];
+    if (NRM) sh[rowid * NV + NV - 1] = v[NV - 1];
   }
   __syncthreads();
   for (int k = threadIdx.x; k < NV; k += RB) {
     if (k < nd || (NRM && k == NV - 1)) {
       double r = 0;
 #pragma unroll
-      for (int q = 0; q < NWV; ++q) r += sh[q * NV + k];
+      for (int q = 0; q < NR; ++q) r += sh[q * NV + k];
       out[k * os] = r;
     }
   }
@@ -213,7 +228,7 @@ __global__ void __launch_bounds__(RB)
   }
   using SL = Slots<CM>;
   constexpr int NV = SL::NV;
-  __shared__ double sh[NWV * NV];
+  __shared__ double sh[4 * NWV * NV];
   __shared__ double fin[NV];
   const cx<TA>* Vb = V + b * vbs;
   cx<TW>* wb = w + b * wbs;
@@ -298,7 +313,7 @@ __global__ void __launch_bounds__(RB)
   GmState& S = st[b];
   using SL = Slots<CM>;
   constexpr int NV = SL::NV;
-  __shared__ double sh[NWV * NV];
+  __shared__ double sh[4 * NWV * NV];
   __shared__ double fin[NV];
   constexpr bool STEP = FIN == FIN_H || FIN == FIN_GIVENS || FIN == FIN_HG;
   constexpr bool FD = FIN == FIN_H || FIN == FIN_HG, FN = FIN != FIN_H;
