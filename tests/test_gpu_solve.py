@@ -240,3 +240,41 @@ def test_config1_full_size_matches_oracle_reference(torch, config1_ref, variant)
         assert err <= 1e-4
     finally:
         ie.ie_ctx_destroy(ctx)
+
+
+_ORACLE_ITS = {}  # oracle GMRES(restart) runs on config0, shared by the cases below
+
+
+@pytest.mark.parametrize("restart", [1, 4, 5, 9, 13, 16])
+@pytest.mark.parametrize("reorth", [0, 1])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_gmres_every_restart_bucket_and_orthogonalisation(torch, config0_ref, restart, reorth,
+                                                          prec):
+    """Every register bucket of the Gram-Schmidt passes (1, 4, 8, 12, 16 vectors) with the
+    one-reduction classical Gram-Schmidt (reorth 0) and CGS2 (reorth 1).  In float64 the Arnoldi
+    step count must match the oracle's (modified Gram-Schmidt, equal in exact arithmetic) to
+    within two steps; every run must reach the tolerance and the oracle's solution."""
+    from paper_2306_17537_amd import ie
+    p, st, Eref = config0_ref
+    banner(f"gmres config0 restart {restart} reorth {reorth} {prec}")
+    if restart not in _ORACLE_ITS:
+        _ORACLE_ITS[restart] = solve.solve_full(st, form="cie", tol=1e-8, restart=restart)[1]
+    oinfo = _ORACLE_ITS[restart]
+    ctx, _ = context(p)
+    try:
+        E0 = _gpu_e0(ctx, p, torch)
+        x = E0.clone()  # the oracle's start (the background field)
+        tol = 1e-8 if prec == "fp64" else 1e-6
+        rc, stats = ie.ie_gmres(ctx, dev(p.sigma6), E0, x, tol=tol, restart=restart,
+                                max_its=5000, reorth=reorth, form=ie.IE_CIE,
+                                precision=ie.IE_FP64 if prec == "fp64" else ie.IE_MIXED)
+        E = host(x)
+        err = rel(E - st.E0, Eref - st.E0)
+        banner(f"  its={stats.its} (oracle {oinfo['its']}) relres={stats.relres:.2e} err={err:.1e}")
+        assert stats.relres <= tol
+        assert operator.relres(st.Ghat, st.dsig, E, st.E0, p.n) <= 1.01 * tol
+        assert err <= (1e-6 if prec == "fp64" else 1e-4)
+        if prec == "fp64":
+            assert abs(stats.its - oinfo["its"]) <= 2
+    finally:
+        ie.ie_ctx_destroy(ctx)
