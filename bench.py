@@ -13,6 +13,8 @@ and by plain float64 GMRES is timed in the same run and reported beside it.
 Printed: one JSON line with the contract fields plus
   roofline     - dominant kernel of the timed region: algorithmic bytes / duration, HIP events
                  on the launch stream (library launch profiler), against 8 TB/s;
+  roofline_alu - the same kernel against the non-packed vector-ALU peak (model flops: 5 L log2 L
+                 per transform, 72 per point for the tensor multiply);
   cpu_baseline - the CPU oracle on this host, sampled and scaled to one solve;
   plain_fp64   - the same solve in plain float64 (best of full-domain GMRES(10), GMRES(16) and
                  DD-GS-A);
@@ -31,6 +33,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "time-to-solve @ rel.resid 1e-6 + matvec HBM GB/s; plain FP64 vs mixed+NN"
 HBM_PEAK_GBS = 8000.0
+# Non-packed vector peak (packed FP32 instructions are disabled in the build): 256 CUs x 4 SIMDs x
+# 16 lanes x 2 flop (FMA) x 2.4 GHz, the same for float32 and float64.
+VALU_PEAK_TFLOPS = 78.6
 # Restart length of the chosen form.  The paper runs GMRES(10).  In mixed precision, summed over
 # this model and four held-out seeds of it, restart 16 took 6 % less time than 10 and 2 % less
 # than 12 (fewer restarts, each a float64 residual; fewer Arnoldi steps).  Plain float64 is
@@ -305,6 +310,7 @@ def main():
                      "share_of_profiled_time": round(dom["total_ms"] / prof_total, 3),
                      "measured": "HIP events on the launch stream around every launch, in a "
                                  "profiled replay of the timed steps (direct launches)"},
+        "roofline_alu": zconv_alu(dom, avg_ms),
         "cpu_baseline": cpu,
         "plain_fp64": plain,
         "variants": variants,
@@ -320,6 +326,22 @@ def main():
     }
     print(json.dumps(out))
     ie.ie_ctx_destroy(ctx)
+
+
+def zconv_alu(dom, avg_ms):
+    """The dominant kernel (the z pass) against the vector-ALU peak: model flops per launch =
+    lines x (6 transforms x 5 L log2 L + 72 L) for L = LZ (three components, forward and
+    inverse, unpruned) plus the 3x3 complex tensor multiply (72 flop per padded point)."""
+    parts = dom["name"].split()
+    if len(parts) < 3 or parts[0] != "zconv" or not parts[2].startswith("L"):
+        return None
+    lx, ly, lz = (int(v) for v in parts[2][1:].split("x"))
+    batch = int(parts[-1][1:]) if parts[-1].startswith("b") else 1
+    flops = float(lx * ly * batch) * (6 * 5 * lz * float(np.log2(lz)) + 72 * lz)
+    tf = float(flops / (avg_ms * 1e-3) / 1e12)
+    return {"bound": "alu", "achieved": round(tf, 2), "peak": VALU_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(tf / VALU_PEAK_TFLOPS, 4),
+            "flops_per_launch": int(flops), "kernel": dom["name"]}
 
 
 PASS_NAMES = {"xfwd": "k_xfwd", "xinv": "k_xinv", "zconv": "k_zconv", "yfwd": "k_colfft",
