@@ -506,7 +506,7 @@ def batch_bench(ie, torch):
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     opts = ie.dd_opts(tol=1e-6, adaptive=False, inner_tol_fixed=5e-7, precision=ie.IE_MIXED,
-                      max_its=5000)
+                      max_its=5000, restart=CHOSEN_RESTART)
     data = []
     for p in probs:
         key = (p.n, p.freq)
@@ -533,7 +533,8 @@ def batch_bench(ie, torch):
     for c in ctxs.values():
         ie.ie_ctx_destroy(c)
     out = dict(workload="config2: 64 positions x {400 kHz, 2 MHz} = 128 solves, grids "
-                        "32^3 / 48x48x64 / 64x64x96 (seed 202), full-domain mixed GMRES(10), "
+                        "32^3 / 48x48x64 / 64x64x96 (seed 202), full-domain mixed "
+                        f"GMRES({CHOSEN_RESTART}), "
                         "tol 1e-6, one ie_dd_solve call",
                solves=len(probs), groups=len(ctxs), wall_s=round(t_all, 4),
                solves_per_s=round(len(probs) / t_all, 2), matvecs=mv,
