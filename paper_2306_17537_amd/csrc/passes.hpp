@@ -270,9 +270,13 @@ __global__ void __launch_bounds__((GeoZ<T, LZ, V>::W * GeoZ<T, LZ, V>::TL))
   const int w = threadIdx.x % W;
   const int t = threadIdx.x / W;
   const int kx = blockIdx.x * W + w;
-  // pair form: rows ky and LY - ky (one row when ky is 0 or LY/2); single form: row ky
-  const int ky = blockIdx.y;
+  // pair form: rows ky and LY - ky (one row when ky is 0 or LY/2); single form: row ky, in the
+  // launch order 0, LY/2, 1, LY-1, 2, LY-2, ... so that the two rows reading the same stored
+  // spectrum row run at the same time (their blocks are LX/W apart in launch order) and the
+  // second read finds the row in cache
   const int hy = a.LY / 2;
+  const int by = blockIdx.y;
+  const int ky = G::PAIR ? by : (by < 2 ? by * hy : ((by & 1) ? a.LY - (by >> 1) : (by >> 1)));
   const bool two = G::PAIR && ky != 0 && ky != hy;  // block-uniform
   const int nr = two ? 2 : 1;
   const int oy = ky > hy ? a.LY - ky : ky;            // stored row of G^
