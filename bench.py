@@ -204,8 +204,11 @@ def main():
         passes = [k for k in pr if k["name"].split()[0] in ("xfwd", "yfwd", "zconv", "yinv", "xinv")]
         t_ms = sum(k["total_ms"] for k in passes) / reps
         byts = sum(k["bytes_per_launch"] * k["launches"] for k in passes) / reps
+        tr = measured_traffic({k["name"]: k for k in passes}, tuning, p.n)
         mv[nm] = dict(ms=round(t_ms, 4), algorithmic_bytes=int(byts),
                       gbs=round(byts / (t_ms * 1e-3) / 1e9, 1),
+                      traffic_bytes=None if tr is None else int(tr),
+                      traffic_gbs=None if tr is None else round(tr / (t_ms * 1e-3) / 1e9, 1),
                       matvecs_per_s=round(1e3 / t_ms, 1))
     log(f"matvec: {mv}")
     large = None if args.no_large else matvec_large(ie, torch)
@@ -369,6 +372,21 @@ def template_name(prof_name, tuning, grid):
     return f"{PASS_NAMES[parts[0]]}<{t}, {L}, {m[0]['variant']}>"
 
 
+def measured_traffic(passes, tuning, grid):
+    """HBM bytes of one operator application from the committed counter summaries (FETCH_SIZE +
+    WRITE_SIZE per launch of each pass's chosen variant), or None if any pass has no entry for
+    the current kernel sources."""
+    from paper_2306_17537_amd import traffic
+    tot = 0.0
+    for k in passes.values():
+        tn = template_name(k["name"], tuning, grid)
+        hit = traffic.lookup(tn) if tn else None
+        if hit is None:
+            return None
+        tot += hit[0]
+    return tot
+
+
 def matvec_large(ie, torch):
     """The operator on the 128x128x256 grid (6-layer model, 2 MHz): the working set of a padded
     three-component array exceeds the 256 MB last-level cache, so this is the HBM-bound case."""
@@ -393,9 +411,12 @@ def matvec_large(ie, torch):
                   if k["name"].split()[0] in ("xfwd", "yfwd", "zconv", "yinv", "xinv")}
         t_ms = sum(k["total_ms"] for k in passes.values()) / reps
         byts = sum(k["bytes_per_launch"] * k["launches"] for k in passes.values()) / reps
+        tr = measured_traffic(passes, ie.ie_ctx_tuning(ctx), p.n)
         out[nm] = dict(us=round(1e3 * t_ms, 1), algorithmic_bytes=int(byts),
                        gbs=round(byts / (t_ms * 1e-3) / 1e9, 1),
                        frac=round(byts / (t_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       traffic_bytes=None if tr is None else int(tr),
+                       traffic_gbs=None if tr is None else round(tr / (t_ms * 1e-3) / 1e9, 1),
                        passes_us={n: round(1e3 * k["total_ms"] / k["launches"], 1)
                                   for n, k in passes.items()})
         del x, y
