@@ -1,7 +1,7 @@
 """GPU parity of the solvers through the C ABI: restarted GMRES on the full domain (section 2.2)
 and Alg. 1 (block Gauss-Seidel / Jacobi, section 2.3), in float64 and mixed precision, against
 the CPU oracle (dense LU on small grids, the oracle's own converged solve otherwise).
-Gate (the benchmark spec): relative L2 error of the anomalous field <= 1e-4 at relative residual 1e-6."""
+Accuracy gate: relative L2 error of the anomalous field <= 1e-4 at relative residual 1e-6."""
 import numpy as np
 import pytest
 

@@ -117,7 +117,7 @@ def test_gmres_on_known_spectra():
 
 
 def test_config0_solution_has_c4v_symmetry():
-    """configs[0] (VTI, horizontal interface, z dipole on the grid axis) is symmetric under
+    """config0 (VTI, horizontal interface, z dipole on the grid axis) is symmetric under
     90-degree rotations about z, E(R r) = R E(r), and under the vertical mirror x -> -x the
     field of an axial (magnetic) dipole flips, E(M r) = -M E(r)."""
     p = synth.config0()
