@@ -83,10 +83,12 @@ __device__ __forceinline__ bool retired(const MvArgs<T>& a, int b) {
 
 // ---------------------------------------------------------------------------------------
 // launch geometry per (precision, length, variant)
-// Variant V (chosen per plan by the autotuner): bit 0 halves the values per thread (twice the
-// threads per line, more waves in flight, one more LDS exchange); bit 1 doubles the columns per
-// block of the column passes (256-byte row segments) and the rows per block of the row passes.
-// Row passes (x) have four more: V + 4 uses the LDS layout padded every 4 positions.
+// Variant V (chosen per plan by the autotuner): bit 0 halves the values per thread of the column
+// passes (twice the threads per line, more waves in flight, one more LDS exchange) and doubles
+// those of the row passes (8 instead of 4: half the threads per line, one LDS exchange fewer,
+// 128-byte instead of 256-byte row segments per load); bit 1 doubles the columns per block of
+// the column passes (256-byte row segments) and the rows per block of the row passes.  Row
+// passes (x) have four more: V + 4 uses the LDS layout padded every 4 positions.
 // ---------------------------------------------------------------------------------------
 constexpr int kVariants = 4;
 constexpr int kRowVariants = 8;
@@ -106,7 +108,7 @@ struct Geo {
   // row passes (x): ER values per thread, TLR threads per line, NL rows per block (~128 threads,
   // V & 2: ~256)
   static constexpr int ER1 = L < 4 ? L : 4;
-  static constexpr int ER = ((V & 1) && ER1 >= 4) ? ER1 / 2 : ER1;
+  static constexpr int ER = ((V & 1) && L >= 16) ? 2 * ER1 : ER1;
   static constexpr int TLR = L / ER;
   static constexpr int NL0 = ((V & 2) ? 256 : 128) / TLR;
   static constexpr int NL = NL0 < 1 ? 1 : NL0;
