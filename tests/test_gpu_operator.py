@@ -91,6 +91,63 @@ def test_matvec_full_size_sampled_direct_sums(torch):
         ie.ie_ctx_destroy(ctx)
 
 
+def _direct_sum(xs, target, n, h, k0, sigma0, chunk=32):
+    """S_i = sum_j Gd(i - j) x_j over all source cells j for one target cell i, from the oracle's
+    kernel values (eq. 5 off the diagonal, the ball integral on it), in slabs of `chunk` planes."""
+    nx, ny, nz = n
+    iz, iy, ix = target
+    out = np.zeros(3, dtype=np.complex128)
+    dy = (iy - np.arange(ny))[None, :, None]
+    dx = (ix - np.arange(nx))[None, None, :]
+    for z0 in range(0, nz, chunk):
+        dz = (iz - np.arange(z0, min(nz, z0 + chunk)))[:, None, None]
+        DZ, DY, DX = np.broadcast_arrays(dz, dy, dx)
+        R = np.stack([DX, DY, DZ], axis=-1).astype(np.float64) * h
+        zero = (DX == 0) & (DY == 0) & (DZ == 0)
+        R[zero] = (h, 0.0, 0.0)  # placeholder, replaced by the self term below
+        G = green.green_tensor(R, k0, sigma0) * h ** 3
+        G[zero] = green.self_term(h, k0, sigma0) * np.eye(3)
+        out += np.einsum("zyxpq,qzyx->p", G, xs[:, z0:z0 + chunk])
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_matvec_largest_grid_sampled_direct_sums(torch, prec):
+    """128x128x256 (the largest workload grid; padded 256x256x512, so the z pass runs at length
+    512 in the launch order and variants the autotuner picks for this grid): sampled outputs of
+    G x for a dense random x against direct sums over all 4.2 M source cells (no FFT on the
+    oracle side), float64 and complex64."""
+    from paper_2306_17537_amd import ie
+    p = synth.config3()
+    nx, ny, nz = p.n
+    banner(f"matvec largest grid {p.n} {prec}")
+    fp64 = prec == "fp64"
+    ctx, _ = context(p, mask=ie.IE_FP64 if fp64 else ie.IE_MIXED)
+    try:
+        xd = torch.from_numpy(_rand(field_shape(p), 5)).to(
+            torch.complex128 if fp64 else torch.complex64).cuda()
+        yd = torch.zeros_like(xd)
+        ie.ie_matvec(ctx, dev(p.sigma6), xd, yd, ie.IE_GREEN_ONLY,
+                     ie.IE_FP64 if fp64 else ie.IE_MIXED)
+        torch.cuda.synchronize()
+        y = host(yd).astype(np.complex128)
+        xs = host(xd).astype(np.complex128)  # the input as the kernels saw it
+        rms = float(np.sqrt(np.mean(np.abs(y) ** 2)))
+        k0 = green.wavenumber(p.sigma0, p.freq)
+        rng = np.random.default_rng(21)
+        pts = [(0, 0, 0), (nz - 1, ny - 1, nx - 1), (nz // 2, ny // 2, nx // 2),
+               tuple(int(rng.integers(0, s)) for s in (nz, ny, nx))]
+        tol = 1e-10 if fp64 else 5e-5
+        for t in pts:
+            s = _direct_sum(xs, t, p.n, p.h, k0, p.sigma0)
+            err = float(np.abs(y[:, t[0], t[1], t[2]] - s).max())
+            scale = max(float(np.abs(s).max()), rms)
+            banner(f"  target {t}: |err| {err:.2e} scale {scale:.2e}")
+            assert err <= tol * scale, (t, err, scale)
+    finally:
+        ie.ie_ctx_destroy(ctx)
+
+
 @pytest.mark.parametrize("n", [(8, 8, 8), (7, 5, 6), (64, 64, 64)])
 def test_background_field_matches_oracle(torch, n):
     from paper_2306_17537_amd import ie
