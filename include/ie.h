@@ -349,11 +349,16 @@ int ie_receivers(ie_ctx* ctx, const double* sigma6, const ie_source* src, int32_
  *   IE_OPT_FORCE_VARIANT: -1 (default) leaves the choice to the autotuner; 0 .. 7 puts every
  *                  pass of contexts set up afterwards on that variant (passes with four variants
  *                  take it modulo 4): for tests that cover every variant.
+ *   IE_OPT_GROUP_THREADS: 1 (default) lets ie_dd_solve advance the problems of different
+ *                  contexts at the same time (one host thread and one stream per context, joined
+ *                  to the caller's stream); 0 solves the groups one after the other.  Results are
+ *                  the same either way.
  * Returns IE_EINVAL for an unknown option or value.
  */
 #define IE_OPT_GRAPHS 1
 #define IE_OPT_AUTOTUNE 2
 #define IE_OPT_FORCE_VARIANT 3
+#define IE_OPT_GROUP_THREADS 4
 int ie_set_option(int32_t option, int32_t value);
 
 /*

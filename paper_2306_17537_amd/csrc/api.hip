@@ -125,6 +125,10 @@ static std::unique_ptr<Plan> make_plan(int nx, int ny, int nz) {
 
 using namespace ie;
 
+namespace ie {
+bool g_group_threads = true;
+}  // namespace ie
+
 namespace {
 bool g_autotune = true;
 int g_force_variant = -1;
@@ -156,6 +160,11 @@ int ie_set_option(int32_t option, int32_t value) {
   if (option == IE_OPT_FORCE_VARIANT) {
     if (value < -1 || value > 7) return fail(IE_EINVAL, "IE_OPT_FORCE_VARIANT takes -1 .. 7");
     g_force_variant = value;
+    return IE_OK;
+  }
+  if (option == IE_OPT_GROUP_THREADS) {
+    if (value != 0 && value != 1) return fail(IE_EINVAL, "IE_OPT_GROUP_THREADS takes 0 or 1");
+    g_group_threads = value != 0;
     return IE_OK;
   }
   return fail(IE_EINVAL, "unknown option %d", option);

@@ -41,6 +41,10 @@ struct ie_ctx {
 
 namespace ie {
 
+// process-wide switch (ie_set_option IE_OPT_GROUP_THREADS): ie_dd_solve runs the groups of
+// different contexts concurrently
+extern bool g_group_threads;
+
 inline const c128* tw64(const ie_ctx* c) { return c->tw64.as<const c128>(); }
 inline const c64* tw32(const ie_ctx* c) { return c->tw32.as<const c64>(); }
 

@@ -20,10 +20,13 @@
 #include <cstring>
 #include <limits>
 #include <map>
+#include <string>
+#include <thread>
 #include <vector>
 
 #include "context.hpp"
 #include "nn.hpp"
+#include "prof.hpp"
 
 namespace ie {
 
@@ -709,7 +712,62 @@ extern "C" int ie_dd_solve(ie_ctx* const* ctxs, int32_t nproblems, const ie_prob
   }
   hipStream_t s = (hipStream_t)stream;
   int worst = IE_OK;
-  for (ie_ctx* c : order) IE_TRY(dd_group(c, groups[c], problems, o, stats, s, &worst));
+  // Groups of different contexts share no device buffers, so they may run at the same time: one
+  // host thread and one stream per group, ordered after and before the caller's stream by events
+  // (small groups then fill the GPU together).  Kept sequential for a single group, a shared
+  // network handle, an active launch profiler or IE_OPT_GROUP_THREADS = 0.
+  if (order.size() == 1 || o.init == IE_INIT_LEARNED || prof_enabled() || !g_group_threads) {
+    for (ie_ctx* c : order) IE_TRY(dd_group(c, groups[c], problems, o, stats, s, &worst));
+  } else {
+    struct Lane {
+      hipStream_t st = nullptr;
+      hipEvent_t done = nullptr;
+      int rc = IE_OK, worst = IE_OK;
+      std::string err;
+    };
+    std::vector<Lane> lanes(order.size());
+    hipEvent_t start = nullptr;
+    IE_HIP(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+    int rc = hipEventRecord(start, s) == hipSuccess ? IE_OK : IE_EDEVICE;
+    for (auto& l : lanes) {
+      if (rc == IE_OK && (hipStreamCreateWithFlags(&l.st, hipStreamNonBlocking) != hipSuccess ||
+                          hipEventCreateWithFlags(&l.done, hipEventDisableTiming) != hipSuccess ||
+                          hipStreamWaitEvent(l.st, start, 0) != hipSuccess))
+        rc = IE_EDEVICE;
+    }
+    if (rc == IE_OK) {
+      std::vector<std::thread> th;
+      for (size_t i = 0; i < order.size(); ++i)
+        th.emplace_back([&, i]() {
+          Lane& l = lanes[i];
+          if (hipSetDevice(order[i]->device) != hipSuccess) {
+            l.rc = IE_EDEVICE;
+            l.err = "hipSetDevice failed in a group thread";
+            return;
+          }
+          l.rc = dd_group(order[i], groups[order[i]], problems, o, stats, l.st, &l.worst);
+          if (l.rc < 0) l.err = ie_last_error();
+          if (hipEventRecord(l.done, l.st) != hipSuccess && l.rc >= 0) l.rc = IE_EDEVICE;
+        });
+      for (auto& t : th) t.join();
+      for (auto& l : lanes)
+        if (hipStreamWaitEvent(s, l.done, 0) != hipSuccess && rc == IE_OK) rc = IE_EDEVICE;
+    }
+    std::string err;
+    for (auto& l : lanes) {
+      if (l.rc < 0 && rc == IE_OK) {
+        rc = l.rc;
+        err = l.err;
+      }
+      if (l.worst == IE_ENOCONV) worst = IE_ENOCONV;
+    }
+    for (auto& l : lanes) {
+      if (l.done) (void)hipEventDestroy(l.done);
+      if (l.st) (void)hipStreamDestroy(l.st);
+    }
+    (void)hipEventDestroy(start);
+    if (rc < 0) return err.empty() ? fail(rc, "device error in a group") : fail(rc, "%s", err.c_str());
+  }
   if (worst == IE_ENOCONV) return fail(IE_ENOCONV, "at least one problem did not converge");
   return IE_OK;
 }

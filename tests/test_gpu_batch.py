@@ -123,3 +123,47 @@ def test_batch_with_converged_and_zero_contrast_members(torch):
             assert torch.equal(E1, outs[k])
     finally:
         ie.ie_ctx_destroy(ctx)
+
+
+def test_group_threads_equal_sequential_groups_and_report_errors(torch):
+    """Problems of different contexts run concurrently (one host thread and stream per context)
+    or one group after the other (IE_OPT_GROUP_THREADS = 0): identical fields and statistics.
+    An invalid member in one group comes back as that group's error through the caller."""
+    from paper_2306_17537_amd import ie
+    import dataclasses
+    probs = [dataclasses.replace(p, z_bounds=(0, p.n[2])) for p in synth.config2()[:6]]
+    ctxs, grids = _contexts(probs)
+    banner(f"group threads: {len(probs)} problems, {len(ctxs)} contexts")
+    opts = ie.dd_opts(tol=1e-6, adaptive=False, inner_tol_fixed=5e-7, precision=ie.IE_MIXED,
+                      max_its=5000, restart=16)
+
+    def run(sig=None):
+        outs, plist, clist = [], [], []
+        for k, p in enumerate(probs):
+            key = (p.n, p.freq, p.z_bounds)
+            E = torch.zeros(field_shape(p), dtype=torch.complex128, device="cuda:0")
+            s6 = dev(p.sigma6) if sig is None or k != sig else dev(np.full_like(p.sigma6, np.nan))
+            outs.append(E)
+            clist.append(ctxs[key])
+            plist.append(dict(grid=grids[key], sigma6=s6, sources=p.sources, E_total=E))
+        _, st = ie.ie_dd_solve(clist, plist, opts)
+        return outs, st
+
+    try:
+        assert len(ctxs) >= 2
+        ie.ie_set_option(ie.IE_OPT_GROUP_THREADS, 0)
+        seq, st_seq = run()
+        ie.ie_set_option(ie.IE_OPT_GROUP_THREADS, 1)
+        thr, st_thr = run()
+        for k in range(len(probs)):
+            assert torch.equal(seq[k], thr[k]), k
+            assert st_seq[k].total_its == st_thr[k].total_its, k
+            assert st_thr[k].relres[st_thr[k].sweeps] <= 1e-6
+        with pytest.raises(ie.IEError) as ei:
+            run(sig=len(probs) - 1)
+        assert ei.value.code == ie.IE_EINVAL
+        assert "non-finite" in str(ei.value)
+    finally:
+        ie.ie_set_option(ie.IE_OPT_GROUP_THREADS, 1)
+        for c in ctxs.values():
+            ie.ie_ctx_destroy(c)
