@@ -101,3 +101,14 @@ def test_entry_points_reject_null_arguments(L):
     assert lib.ie_dd_solve(None, 0, None, None, None, None) == L.IE_EINVAL
     assert lib.ie_background_field(None, None, 0, None, None) == L.IE_EINVAL
     assert lib.ie_ctx_destroy(None) == L.IE_OK
+
+
+def test_set_option_validates_on_host(L):
+    lib = L.lib()
+    for opt, bad in ((L.IE_OPT_GRAPHS, 2), (L.IE_OPT_AUTOTUNE, -1), (L.IE_OPT_FORCE_VARIANT, 8),
+                     (L.IE_OPT_GROUP_THREADS, 2), (99, 0)):
+        assert lib.ie_set_option(opt, bad) == L.IE_EINVAL, (opt, bad)
+    for opt, good, default in ((L.IE_OPT_GRAPHS, 0, 1), (L.IE_OPT_GROUP_THREADS, 0, 1),
+                               (L.IE_OPT_FORCE_VARIANT, 3, -1)):
+        assert lib.ie_set_option(opt, good) == L.IE_OK
+        assert lib.ie_set_option(opt, default) == L.IE_OK
