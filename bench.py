@@ -18,6 +18,7 @@ Printed: one JSON line with the contract fields plus
   cpu_baseline - the CPU oracle on this host, sampled and scaled to one solve;
   plain_fp64   - the same solve in plain float64 (best of full-domain GMRES(10), GMRES(16) and
                  DD-GS-A);
+  solve_large  - the chosen form, plain float64 and two DD forms on the 128x128x256 grid;
   accuracy     - relative L2 error of the anomalous field against the stored oracle reference.
 """
 import argparse
@@ -57,7 +58,7 @@ def parse():
     ap.add_argument("--pmc-calibration", action="store_true",
                     help="first run the 1 GiB fill and copy kernels that scale the HBM counters")
     ap.add_argument("--no-large", action="store_true",
-                    help="skip the matvec on the 128x128x256 grid")
+                    help="skip the operator and the solves on the 128x128x256 grid")
     ap.add_argument("--no-nn", action="store_true", help="skip the learned-guess comparison")
     ap.add_argument("--no-ex1", action="store_true",
                     help="skip the isolated sub-domains example (128^3, DD vs full domain)")
@@ -212,6 +213,7 @@ def main():
                       matvecs_per_s=round(1e3 / t_ms, 1))
     log(f"matvec: {mv}")
     large = None if args.no_large else matvec_large(ie, torch)
+    large_solve = None if args.no_large else solve_large(ie, torch)
 
     # other forms on the same GPU: plain float64 (the better of full-domain GMRES and DD-GS-A),
     # full-domain mixed GMRES and mixed DD-Jacobi
@@ -323,6 +325,7 @@ def main():
         "batch": batch,
         "matvec": mv,
         "matvec_large": large,
+        "solve_large": large_solve,
         "autotune_full_grid": {f"{r['precision']} {r['pass']}": r["variant"] for r in tuning
                                if r["grid"] == list(p.n)},
         "accuracy": acc,
@@ -385,6 +388,65 @@ def measured_traffic(passes, tuning, grid):
             return None
         tot += hit[0]
     return tot
+
+
+def solve_large(ie, torch):
+    """Time to e <= 1e-6 on the 128x128x256 grid (six layers dipping 20 deg, principal values in
+    [0.1, 10] S/m, 2 MHz, four z slabs of 64): full-domain contraction-form GMRES in mixed
+    precision (the chosen form) and in plain float64, the Krylov outer iteration over one block
+    GS sweep (mixed, blocks to 0.3), and stationary block GS with the adaptive inner tolerance
+    (Alg. 1, mixed), each from a zero start."""
+    import synth
+    p = synth.config3()
+    nx, ny, nz = p.n
+    g = ie.make_grid(p.n, p.h, p.origin)
+    ctx = ie.ie_green_setup(g, ie.ie_medium(p.sigma0, p.freq, 0.0), p.z_bounds)
+    s6 = torch.from_numpy(p.sigma6).cuda()
+    E0 = torch.zeros((3, nz, ny, nx), dtype=torch.complex128, device="cuda:0")
+    ie.ie_background_field(ctx, p.sources, E0)
+    out = {"workload": "config3 grid 128x128x256 (seed 303), 2 MHz, z slabs "
+                       f"{list(p.z_bounds)}, tol 1e-6, zero start"}
+
+    def timed(fn):
+        fn()  # warm-up: graphs, workspaces
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, r
+
+    for name, prec, m in (("full_mixed", ie.IE_MIXED, CHOSEN_RESTART),
+                          ("full_fp64", ie.IE_FP64, CHOSEN_RESTART),
+                          ("full_fp64_gmres10", ie.IE_FP64, 10)):
+        x = torch.zeros_like(E0)
+
+        def run(x=x, prec=prec, m=m):
+            x.zero_()
+            return ie.ie_gmres(ctx, s6, E0, x, tol=1e-6, restart=m, precision=prec,
+                               form=ie.IE_CIE, max_its=5000, allow_noconv=True)[1]
+        dt, st = timed(run)
+        out[name] = dict(s=round(dt, 4), its=st.its, relres=float(f"{st.relres:.3e}"))
+        del x
+    E = torch.zeros_like(E0)
+    for name, scheme, sweeps in (("fgmres_gs_mixed", ie.IE_FGMRES_GS, 60),
+                                 ("dd_gs_a_mixed", ie.IE_GS, 20)):
+        opts = ie.dd_opts(scheme=scheme, adaptive=scheme == ie.IE_GS, tol=1e-6,
+                          inner_tol_fixed=0.3, init=ie.IE_INIT_ZERO, precision=ie.IE_MIXED,
+                          form=ie.IE_CIE, restart=CHOSEN_RESTART, max_sweeps=sweeps, max_its=5000)
+
+        def run(opts=opts):
+            return ie.ie_dd_solve([ctx], [dict(grid=g, sigma6=s6, sources=p.sources, E_total=E)],
+                                  opts, allow_noconv=True)[1][0]
+        dt, st = timed(run)
+        out[name] = dict(s=round(dt, 4), sweeps=st.sweeps, inner_its=st.total_its,
+                         relres=float(f"{st.relres[st.sweeps]:.3e}"),
+                         converged=bool(st.relres[st.sweeps] <= 1e-6))
+    out["speedup_chosen_vs_plain"] = round(
+        min(out["full_fp64"]["s"], out["full_fp64_gmres10"]["s"]) / out["full_mixed"]["s"], 3)
+    del E, E0, s6
+    ie.ie_ctx_destroy(ctx)
+    log(f"solve large: {out}")
+    return out
 
 
 def matvec_large(ie, torch):

@@ -162,11 +162,10 @@ def config1(seed=101, n=(64, 64, 64), h=0.25):
                                 f"config1_{n[0]}x{n[1]}x{n[2]}_3layer_dip30_seed{seed}")
 
 
-def config3(seed=303):
+def config3(seed=303, n=(128, 128, 256), h=0.25):
     """128x128x256 cells of 0.25 m, six tilted-TI layers dipping 20 deg, principal values
-    in [0.1, 10] S/m, 2 MHz, z dipole at the centre, four z slabs of 64."""
-    n = (128, 128, 256)
-    h = 0.25
+    in [0.1, 10] S/m, 2 MHz, z dipole at the centre, four z slabs of 64.  Other n and h give
+    the same layers (interface offsets in metres) on another grid, in four equal z slabs."""
     rng = np.random.Generator(np.random.PCG64(seed))
     normal = axis_from_angles(math.radians(20.0), 0.0)
     d = _sorted_offsets(rng, 5, -24.0, 24.0, 3.0)
@@ -176,8 +175,9 @@ def config3(seed=303):
     origin = default_origin(n, h)
     sigma6 = _layered_sigma6(n, h, origin, normal, d, sig_h, sig_v)
     src = [((0.0, 0.0, 0.0), (0.0, 0.0, 1.0), "magnetic")]
-    return Problem(f"config3_128x128x256_6layer_dip20_seed{seed}", n, h, origin,
-                   SIGMA0_DEFAULT, 2.0e6, sigma6, src, (0, 64, 128, 192, 256))
+    nz = n[2]
+    return Problem(f"config3_{n[0]}x{n[1]}x{n[2]}_h{h}_6layer_dip20_seed{seed}", n, h, origin,
+                   SIGMA0_DEFAULT, 2.0e6, sigma6, src, (0, nz // 4, nz // 2, 3 * nz // 4, nz))
 
 
 CONFIG2_SHAPES = ((32, 32, 32), (48, 48, 64), (64, 64, 96))
