@@ -394,8 +394,8 @@ def solve_large(ie, torch):
     """Time to e <= 1e-6 on the 128x128x256 grid (six layers dipping 20 deg, principal values in
     [0.1, 10] S/m, 2 MHz, four z slabs of 64): full-domain contraction-form GMRES in mixed
     precision (the chosen form) and in plain float64, the Krylov outer iteration over one block
-    GS sweep (mixed, blocks to 0.3), and stationary block GS with the adaptive inner tolerance
-    (Alg. 1, mixed), each from a zero start."""
+    GS or block Jacobi sweep (mixed, blocks to 0.3), and stationary block GS with the adaptive
+    inner tolerance (Alg. 1, mixed, 20 sweeps), each from a zero start."""
     import synth
     p = synth.config3()
     nx, ny, nz = p.n
@@ -429,6 +429,7 @@ def solve_large(ie, torch):
         del x
     E = torch.zeros_like(E0)
     for name, scheme, sweeps in (("fgmres_gs_mixed", ie.IE_FGMRES_GS, 60),
+                                 ("fgmres_jacobi_mixed", ie.IE_FGMRES_JACOBI, 60),
                                  ("dd_gs_a_mixed", ie.IE_GS, 20)):
         opts = ie.dd_opts(scheme=scheme, adaptive=scheme == ie.IE_GS, tol=1e-6,
                           inner_tol_fixed=0.3, init=ie.IE_INIT_ZERO, precision=ie.IE_MIXED,
