@@ -207,6 +207,7 @@ def main():
         byts = sum(k["bytes_per_launch"] * k["launches"] for k in passes) / reps
         tr = measured_traffic({k["name"]: k for k in passes}, tuning, p.n)
         mv[nm] = dict(ms=round(t_ms, 4), algorithmic_bytes=int(byts),
+                      cache_resident=True,  # padded arrays far below the 256 MB last-level cache
                       gbs=round(byts / (t_ms * 1e-3) / 1e9, 1),
                       traffic_bytes=None if tr is None else int(tr),
                       traffic_gbs=None if tr is None else round(tr / (t_ms * 1e-3) / 1e9, 1),
@@ -476,6 +477,7 @@ def matvec_large(ie, torch):
         byts = sum(k["bytes_per_launch"] * k["launches"] for k in passes.values()) / reps
         tr = measured_traffic(passes, ie.ie_ctx_tuning(ctx), p.n)
         out[nm] = dict(us=round(1e3 * t_ms, 1), algorithmic_bytes=int(byts),
+                       cache_resident=False,
                        gbs=round(byts / (t_ms * 1e-3) / 1e9, 1),
                        frac=round(byts / (t_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                        traffic_bytes=None if tr is None else int(tr),
