@@ -73,7 +73,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the solver has no "
-                                   "multi-GPU path (see DESIGN.md: how the path would shard)",
+                                   "multi-GPU path",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
