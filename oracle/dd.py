@@ -50,7 +50,8 @@ def coupling(st: Setup, E, z0, z1):
 
 def dd_solve(st: Setup, z_bounds, scheme="gs", adaptive=True, tol=1e-6, inner_tol_fixed=1e-6,
              form="conventional", restart=10, max_sweeps=100, inner_max_its=5000, E_init=None):
-    """Alg. 1.  Returns (E, info) with per-sweep full residuals and per-block iteration counts."""
+    """Alg. 1.  Returns (E, info) with per-sweep full residuals, the inner tolerance each sweep
+    used and per-block iteration counts."""
     nx, ny, nz = st.n
     zb = list(z_bounds)
     blocks = list(zip(zb[:-1], zb[1:]))
@@ -63,11 +64,13 @@ def dd_solve(st: Setup, z_bounds, scheme="gs", adaptive=True, tol=1e-6, inner_to
 
     E = st.E0.copy() if E_init is None else np.array(E_init, dtype=np.complex128)
     e = operator.relres(st.Ghat, st.dsig, E, st.E0, st.n)
-    info = dict(relres=[e], block_its=[], sweeps=0, total_its=0, converged=e <= tol)
+    info = dict(relres=[e], block_its=[], inner_tol=[], sweeps=0, total_its=0,
+                converged=e <= tol)
     while e > tol and info["sweeps"] < max_sweeps:
         E_old = E.copy()
         its_sweep = []
         inner_tol = e / 10.0 if adaptive else inner_tol_fixed
+        info["inner_tol"].append(inner_tol)
         for (z0, z1) in blocks:
             src = E if scheme == "gs" else E_old
             rhs = st.E0[:, z0:z1] + coupling(st, src, z0, z1)

@@ -111,3 +111,45 @@ def test_cie_inner_solves_reach_same_fixed_point():
     E2, i2 = dd.dd_solve(st, (0, 3, 6), form="cie", tol=1e-9)
     assert i1["converged"] and i2["converged"]
     assert np.linalg.norm(E1 - E2) / np.linalg.norm(E1) < 1e-8
+
+
+def test_adaptive_inner_tolerance_is_a_tenth_of_the_last_residual():
+    """Alg. 1, adaptive scheme: sweep k solves every block to e/10, with e the full relative
+    residual (eq. 9) left by sweep k-1.  Replayed with dense block algebra: e from the dense
+    system, block right-hand sides from eqs. (19)-(22), and each block's GMRES iteration count from
+    a separate GMRES on the dense block matrix started where the oracle's was.  The counts equal
+    the oracle's at e/10 and differ from what e/100 or e would take, so a changed factor fails."""
+    from oracle.gmres import gmres
+    p = synth.random_problem((6, 6, 6), seed=27, contrast=3.0)
+    st = solve.setup(p)
+    zb = (0, 3, 6)
+    A, idx = _dense_blocks(p, st, zb)
+    b = st.E0.ravel()
+    E, info = dd.dd_solve(st, zb, scheme="gs", adaptive=True, tol=1e-9)
+    assert info["converged"] and info["sweeps"] >= 3
+    states = [st.E0.ravel().copy()]
+    for k in range(1, info["sweeps"] + 1):
+        Ek, _ = dd.dd_solve(st, zb, scheme="gs", adaptive=True, tol=0.0, max_sweeps=k)
+        states.append(Ek.ravel())
+    miss = {10: 0, 100: 0, 1: 0}
+    for k in range(info["sweeps"]):
+        x_old, x_new = states[k], states[k + 1]
+        e = np.linalg.norm(b - A @ x_old) / np.linalg.norm(b)
+        assert abs(e - info["relres"][k]) <= 1e-6 * e + 1e-15
+        assert info["inner_tol"][k] == info["relres"][k] / 10
+        for i, ii in enumerate(idx):
+            x = np.concatenate([x_new[jj] if j < i else x_old[jj] for j, jj in enumerate(idx)])
+            order = np.concatenate(idx)
+            xf = np.empty_like(x)
+            xf[order] = x
+            Aii = A[np.ix_(ii, ii)]
+            rhs = b[ii] - (A[ii] @ xf - Aii @ xf[ii])
+            for f in miss:
+                _, inf = gmres(lambda v: Aii @ v, rhs, x_old[ii], tol=e / f, restart=10,
+                               max_its=5000)
+                miss[f] += abs(inf["its"] - info["block_its"][k][i])
+    nblk = info["sweeps"] * len(idx)
+    print(f"sweeps {info['sweeps']}, blocks {len(idx)}, summed |count difference| "
+          f"at e/10, e/100, e: {miss[10]}, {miss[100]}, {miss[1]}")
+    assert miss[10] <= nblk // 4
+    assert miss[100] > nblk and miss[1] > nblk

@@ -156,3 +156,39 @@ def test_app_c_rotated_ti_tensor():
         assert np.allclose(s6, app_c, atol=1e-15)
     vti = synth.ti_tensor6(sh, sv, (0.0, 0.0, 1.0))
     assert np.allclose(vti, [sh, sh, sv, 0, 0, 0])
+
+
+def test_voxel_sphere_static_field_approaches_sphere_and_is_scale_free():
+    """Eq. (8) in the static limit with a uniform applied field: a sphere of conductivity sigma1 in
+    sigma0 carries the uniform interior field 3 sigma0 / (sigma1 + 2 sigma0) times the applied one
+    (textbook sphere in a uniform field).  A voxelised sphere approaches that value as the voxels
+    shrink, and since the static problem has no length scale the discrete solution must not change
+    when h does: both fail if the off-diagonal weight h^3, its sign or the kernel's static part
+    (the R^-3 dipole term of eq. 5) is wrong."""
+    sigma0, s1 = 0.1, 1.0
+    k0 = green.wavenumber(sigma0, 1e-2)
+    means = {}
+    fields = {}
+    for nn in (12, 16):
+        for h in (0.5, 2.0):
+            n = (nn, nn, nn)
+            X, Y, Z = synth.cell_centres(n, h, synth.default_origin(n, h))
+            inside = X ** 2 + Y ** 2 + Z ** 2 < ((nn / 2 - 1.5) * h) ** 2
+            Ghat = green.kernel_spectrum(n, h, k0, sigma0)
+            dsig = np.zeros((3, 3) + inside.shape)
+            for p in range(3):
+                dsig[p, p][inside] = s1 - sigma0
+            E0 = np.zeros((3,) + inside.shape, dtype=np.complex128)
+            E0[0] = 1.0
+            E, info = gmres(lambda v: operator.apply_A(Ghat, dsig, v, n), E0, E0.copy(), 1e-12,
+                            20, 2000)
+            assert info["converged"]
+            means[nn, h] = E[0][inside].real.mean()
+            fields[nn, h] = E
+    exact = 3 * sigma0 / (s1 + 2 * sigma0)
+    for nn in (12, 16):
+        # equal up to the O((k0 L)^2) dynamic correction, ~1e-6 at 10 mHz
+        assert np.linalg.norm(fields[nn, 0.5] - fields[nn, 2.0]) < 1e-5 * np.linalg.norm(
+            fields[nn, 0.5])
+    assert abs(means[16, 0.5] - exact) < 0.05 * exact
+    assert abs(means[16, 0.5] - exact) < abs(means[12, 0.5] - exact)

@@ -68,3 +68,39 @@ def test_zero_contrast_gives_background_and_cell_centre_receivers_skip_their_cel
     a = receivers.h_anomalous(p2.n, p2.h, p2.origin, d2, E2, c[None], k0)
     b = receivers.h_anomalous(p2.n, p2.h, p2.origin, d_hole, E2, c[None], k0)
     assert np.allclose(a, b, rtol=1e-14, atol=0)
+
+
+def test_scattered_magnetic_field_is_curl_of_scattered_electric_field():
+    """Eq. (1) away from the cells: the field of the discretised cell currents J = dsigma E obeys
+    curl E^a = i omega mu0 H^a.  E^a at an off-grid point is written here as a plain sum of the
+    electric kernel of eq. (5) with the operator's cell weight h^3 (checked first against the FFT
+    operator of eq. 10 at a cell centre, whose own cell is the self term); its finite-difference
+    curl must equal the oracle's H^a of eq. (4).  Fails if h^3, the current dsigma E, the kernel's
+    sign or the sum over cells is wrong in either."""
+    p = synth.random_problem((4, 3, 5), seed=3, freq=4e5, contrast=2.0)
+    k0 = green.wavenumber(p.sigma0, p.freq)
+    omega = 2 * np.pi * p.freq
+    dsig = operator.contrast(p.sigma6, p.sigma0)
+    rng = np.random.default_rng(4)
+    E = rng.normal(size=(3, 5, 3, 4)) + 1j * rng.normal(size=(3, 5, 3, 4))
+    J = operator.tensor_apply(dsig, E)
+    X, Y, Z = synth.cell_centres(p.n, p.h, p.origin)
+    centres = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=-1)
+    Jc = J.reshape(3, -1).T
+
+    def e_scat(r, skip=None):
+        out = np.zeros(3, dtype=np.complex128)
+        for c in range(len(centres)):
+            if c != skip:
+                out += green.green_tensor((r - centres[c])[None], k0, p.sigma0)[0] @ Jc[c] * p.h ** 3
+        return out
+
+    S = operator.apply_green(green.kernel_spectrum(p.n, p.h, k0, p.sigma0), J, p.n)
+    c = 2 * 12 + 1 * 4 + 2  # cell (2, 1, 2)
+    expect = S.reshape(3, -1)[:, c] - green.self_term(p.h, k0, p.sigma0) * Jc[c]
+    assert np.allclose(e_scat(centres[c], skip=c), expect, rtol=1e-12, atol=0)
+    pts = np.array([[0.05, 0.02, 0.1], [0.9, -0.6, 1.7], [-0.3, 0.4, -2.0]])
+    for r in pts:
+        H_fd = _curl(e_scat, r, d=1e-6) / (1j * omega * MU0)
+        H = receivers.h_anomalous(p.n, p.h, p.origin, dsig, E, r[None], k0)[0]
+        assert np.allclose(H, H_fd, rtol=1e-6, atol=1e-9 * np.abs(H).max())
