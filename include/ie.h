@@ -256,8 +256,9 @@ int ie_profile_end(ie_kernel_stat* out, int32_t cap, int32_t* count);
  * (uint16 bit patterns), outputs and targets float32; all DEVICE pointers.  nz, ny, nx must be
  * divisible by 2^(levels-1).  Parameters: per layer W[taps][c_in][c_out] then bias[c_out],
  * layers in forward order.  A network is used by one thread at a time.
- * For the solver the network maps 14 channels [ (sigma - sigma0 I)/sigma0 (xx,yy,zz,xy,xz,yz),
- * (re, im) of b / rms(b) for x, y, z, (re, im) of k0 h ] to 6 channels (re, im of (E - b) / rms(b)).
+ * For the solver the network maps the 14 feature channels that ie_nn_features writes (the
+ * contraction-form tensor, the phase-normalised right-hand side and k0 h; see there) to the 6
+ * channels of ie_nn_target (re, im of the phase-normalised (E - b) / rms(b)).
  */
 typedef struct ie_nn ie_nn;
 typedef struct {

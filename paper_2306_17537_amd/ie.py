@@ -2,6 +2,9 @@
 
 Functions carry the C names and only marshal arguments: device arrays are passed as raw
 pointers (``tensor.data_ptr()``), the stream as ``torch.cuda.current_stream().cuda_stream``.
+Before any call each array is checked against what the header states (a contiguous GPU tensor
+of the stated dtype, element count and, for arrays of a context, the context's device), since
+the library cannot check sizes behind a pointer; a mismatch raises ValueError.
 Every step of the computation runs in the HIP library; there is no host fallback.  A missing
 or unloadable library raises ``ImportError`` on first use.
 """
@@ -147,15 +150,79 @@ def _check(code, where, allow_noconv=False):
     return code
 
 
-def _ptr(t):
-    return None if t is None else C.c_void_p(t.data_ptr())
+# what the binding knows of each live handle, for the argument checks below:
+# context -> ((nx, ny, nz), device index); network -> (in_ch, out_ch)
+_CTX = {}
+_NN = {}
 
 
-def _stream(stream):
-    if stream is None:
-        import torch
-        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
-    return C.c_void_p(stream)
+def _dtype(name):
+    import torch
+    return getattr(torch, name)
+
+
+def _arg(t, what, dtypes, numel=None, optional=False):
+    """Check that `t` is a contiguous tensor of one of `dtypes` (torch dtype names) with `numel`
+    elements; returns (what, t), or None for an omitted optional array.  Raises ValueError (the
+    library cannot check sizes behind a raw pointer)."""
+    if t is None:
+        if optional:
+            return None
+        raise ValueError(f"{what}: a device tensor is required")
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{what}: expected a torch tensor, got {type(t).__name__}")
+    allowed = [_dtype(d) for d in dtypes]
+    if t.dtype not in allowed:
+        raise ValueError(f"{what}: dtype {t.dtype}, expected {' or '.join(map(str, allowed))}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{what}: {t.numel()} elements, expected {numel}")
+    return what, t
+
+
+def _ptrs(device, *args):
+    """Pointers of checked arrays (from _arg) after checking that each is a GPU tensor on
+    `device` (any device if None, then all on the first one's)."""
+    out = []
+    for a in args:
+        if a is None:
+            out.append(None)
+            continue
+        what, t = a
+        if t.device.type != "cuda":
+            raise ValueError(f"{what}: must be a GPU tensor, not on {t.device}")
+        if device is None:
+            device = t.device.index
+        if t.device.index != device:
+            raise ValueError(f"{what}: on cuda:{t.device.index}, expected cuda:{device}")
+        out.append(C.c_void_p(t.data_ptr()))
+    return out
+
+
+def _ctx_cells(ctx):
+    """(cell count, device) of a context made by this binding, else (None, None)."""
+    info = _CTX.get(ctx)
+    if info is None:
+        return None, None
+    (nx, ny, nz), device = info
+    return nx * ny * nz, device
+
+
+def _field(ctx, t, what, prec=IE_FP64, optional=False):
+    N = _ctx_cells(ctx)[0]
+    dt = ("complex128",) if prec == IE_FP64 else ("complex64",)
+    return _arg(t, what, dt, None if N is None else 3 * N, optional)
+
+
+def _tensor6(ctx, t, what="sigma6", optional=False):
+    N = _ctx_cells(ctx)[0]
+    return _arg(t, what, ("float64",), None if N is None else 6 * N, optional)
+
+
+def _dev_of(ctx):
+    return _ctx_cells(ctx)[1]
 
 
 def ie_last_error() -> str:
@@ -192,22 +259,32 @@ def ie_green_setup(grid: ie_grid, medium: ie_medium, z_bounds=None, precision_ma
                               C.byref(part) if part is not None else None,
                               precision_mask, _stream(stream), C.byref(out))
     _check(rc, "ie_green_setup")
+    import torch
+    _CTX[out.value] = ((grid.nx, grid.ny, grid.nz), torch.cuda.current_device())
     return out.value
 
 
 def ie_ctx_destroy(ctx):
+    _CTX.pop(ctx, None)
     return _check(lib().ie_ctx_destroy(C.c_void_p(ctx)), "ie_ctx_destroy")
 
 
 def ie_background_field(ctx, sources, E0, stream=None):
     src = make_sources(sources) if not isinstance(sources, C.Array) else sources
-    return _check(lib().ie_background_field(C.c_void_p(ctx), src, len(src), _ptr(E0),
+    (e0,) = _ptrs(_dev_of(ctx), _field(ctx, E0, "E0"))
+    return _check(lib().ie_background_field(C.c_void_p(ctx), src, len(src), e0,
                                             _stream(stream)), "ie_background_field")
 
 
+def _matvec_args(ctx, sigma6, x, y, form, precision):
+    return _ptrs(_dev_of(ctx), _tensor6(ctx, sigma6, optional=form == IE_GREEN_ONLY),
+                 _field(ctx, x, "x", precision), _field(ctx, y, "y", precision))
+
+
 def ie_matvec(ctx, sigma6, x, y, form=IE_CONVENTIONAL, precision=IE_FP64, stream=None):
-    return _check(lib().ie_matvec(C.c_void_p(ctx), _ptr(sigma6), _ptr(x), _ptr(y), form,
-                                  precision, _stream(stream)), "ie_matvec")
+    s6, xp, yp = _matvec_args(ctx, sigma6, x, y, form, precision)
+    return _check(lib().ie_matvec(C.c_void_p(ctx), s6, xp, yp, form, precision, _stream(stream)),
+                  "ie_matvec")
 
 
 def ie_gmres(ctx, sigma6, b, x, tol=1e-6, restart=10, max_its=2000, precision=IE_FP64,
@@ -215,8 +292,10 @@ def ie_gmres(ctx, sigma6, b, x, tol=1e-6, restart=10, max_its=2000, precision=IE
     """Solve in place (x holds the initial guess).  Returns (status, ie_gmres_stats)."""
     opts = ie_gmres_opts(tol, restart, max_its, precision, form, reorth)
     st = ie_gmres_stats()
-    rc = lib().ie_gmres(C.c_void_p(ctx), _ptr(sigma6), _ptr(b), _ptr(x), C.byref(opts),
-                        C.byref(st), _stream(stream))
+    s6, bp, xp = _ptrs(_dev_of(ctx), _tensor6(ctx, sigma6), _field(ctx, b, "b"),
+                       _field(ctx, x, "x"))
+    rc = lib().ie_gmres(C.c_void_p(ctx), s6, bp, xp, C.byref(opts), C.byref(st),
+                        _stream(stream))
     _check(rc, "ie_gmres", allow_noconv)
     return rc, st
 
@@ -236,12 +315,19 @@ def ie_dd_solve(ctxs, problems, opts: ie_dd_opts, stream=None, allow_noconv=Fals
     carr = (C.c_void_p * n)(*ctxs)
     parr = (ie_problem * n)()
     keep = []
+    checked = []
     for i, p in enumerate(problems):
         src = make_sources(p["sources"])
         g = p["grid"]
         keep += [src, g]
-        parr[i] = ie_problem(C.pointer(g), _ptr(p["sigma6"]), src, len(src),
-                             _ptr(p["E_total"]), _ptr(p.get("E_anom")))
+        N = g.nx * g.ny * g.nz
+        checked.append((i, _arg(p["sigma6"], f"problem {i} sigma6", ("float64",), 6 * N),
+                        _arg(p["E_total"], f"problem {i} E_total", ("complex128",), 3 * N),
+                        _arg(p.get("E_anom"), f"problem {i} E_anom", ("complex128",), 3 * N,
+                             optional=True), src, g))
+    for i, s6, et, ea, src, g in checked:
+        s6p, etp, eap = _ptrs(_dev_of(ctxs[i]), s6, et, ea)
+        parr[i] = ie_problem(C.pointer(g), s6p, src, len(src), etp, eap)
     stats = (ie_dd_stats * n)()
     rc = lib().ie_dd_solve(carr, n, parr, C.byref(opts), stats, _stream(stream))
     _check(rc, "ie_dd_solve", allow_noconv)
@@ -271,7 +357,8 @@ def ie_receivers(ctx, sigma6, sources, E, rx, stream=None):
     pts = np.ascontiguousarray(rx, dtype=np.float64).reshape(-1, 3)
     H = np.empty((len(pts), 3), dtype=np.complex128)
     Ha = np.empty_like(H)
-    _check(lib().ie_receivers(C.c_void_p(ctx), _ptr(sigma6), src, len(src), _ptr(E),
+    s6, ep = _ptrs(_dev_of(ctx), _tensor6(ctx, sigma6), _field(ctx, E, "E"))
+    _check(lib().ie_receivers(C.c_void_p(ctx), s6, src, len(src), ep,
                               pts.ctypes.data, len(pts), H.ctypes.data, Ha.ctypes.data,
                               _stream(stream)), "ie_receivers")
     return H, Ha
@@ -297,11 +384,26 @@ def ie_nn_create(in_ch=14, out_ch=6, base_ch=32, levels=4, seed=0, stream=None):
     cfg = ie_nn_config(in_ch, out_ch, base_ch, levels, seed)
     out = C.c_void_p()
     _check(lib().ie_nn_create(C.byref(cfg), _stream(stream), C.byref(out)), "ie_nn_create")
+    _NN[out.value] = (in_ch, out_ch)
     return out.value
 
 
 def ie_nn_destroy(nn):
+    _NN.pop(nn, None)
     return _check(lib().ie_nn_destroy(C.c_void_p(nn)), "ie_nn_destroy")
+
+
+def _nn_io(nn, x, y, ywhat="y", ydtype="float32"):
+    """Pointers of a network input x (bfloat16 [batch, nz, ny, nx, in_ch]) and an output-shaped
+    tensor y ([batch, nz, ny, nx, out_ch]), checked; returns (b, nz, ny, nx, xp, yp)."""
+    if x is None or x.dim() != 5:
+        raise ValueError("x: expected a [batch, nz, ny, nx, channels] tensor")
+    b, nz, ny, nx = (int(v) for v in x.shape[:4])
+    cin, cout = _NN.get(nn, (None, None))
+    cells = b * nz * ny * nx
+    xa = _arg(x, "x", ("bfloat16",), None if cin is None else cells * cin)
+    ya = _arg(y, ywhat, (ydtype,), None if cout is None else cells * cout)
+    return b, nz, ny, nx, xa, ya
 
 
 def ie_nn_num_params(nn):
@@ -325,54 +427,70 @@ def ie_nn_set_params(nn, params):
 
 
 def ie_nn_forward(nn, x, y, stream=None):
-    b, nz, ny, nx = x.shape[:4]
-    return _check(lib().ie_nn_forward(C.c_void_p(nn), _ptr(x), b, nz, ny, nx, _ptr(y),
-                                      _stream(stream)), "ie_nn_forward")
+    b, nz, ny, nx, xa, ya = _nn_io(nn, x, y)
+    xp, yp = _ptrs(None, xa, ya)
+    return _check(lib().ie_nn_forward(C.c_void_p(nn), xp, b, nz, ny, nx, yp, _stream(stream)),
+                  "ie_nn_forward")
 
 
 def ie_nn_backward(nn, x, dy, y, stream=None):
-    b, nz, ny, nx = x.shape[:4]
-    return _check(lib().ie_nn_backward(C.c_void_p(nn), _ptr(x), _ptr(dy), b, nz, ny, nx, _ptr(y),
+    b, nz, ny, nx, xa, ya = _nn_io(nn, x, y)
+    dya = _nn_io(nn, x, dy, "dy")[5]
+    xp, yp, dyp = _ptrs(None, xa, ya, dya)
+    return _check(lib().ie_nn_backward(C.c_void_p(nn), xp, dyp, b, nz, ny, nx, yp,
                                        _stream(stream)), "ie_nn_backward")
 
 
 def ie_nn_train_step(nn, x, target, lr, stream=None):
     """One Adam step on the mean squared error; returns the loss before the step."""
-    b, nz, ny, nx = x.shape[:4]
+    b, nz, ny, nx, xa, ta = _nn_io(nn, x, target, "target")
+    xp, tp = _ptrs(None, xa, ta)
     loss = C.c_float()
-    _check(lib().ie_nn_train_step(C.c_void_p(nn), _ptr(x), _ptr(target), b, nz, ny, nx,
-                                  C.c_float(lr), C.byref(loss), _stream(stream)),
-           "ie_nn_train_step")
+    _check(lib().ie_nn_train_step(C.c_void_p(nn), xp, tp, b, nz, ny, nx, C.c_float(lr),
+                                  C.byref(loss), _stream(stream)), "ie_nn_train_step")
     return loss.value
 
 
 def ie_nn_gemm(A, B, Cout, M, N, K, a_trans=0, b_trans=0, splits=1, stream=None):
-    return _check(lib().ie_nn_gemm(_ptr(A), _ptr(B), _ptr(Cout), M, N, K, a_trans, b_trans, splits,
+    ap, bp, cp = _ptrs(None, _arg(A, "A", ("bfloat16", "int16"), M * K),
+                       _arg(B, "B", ("bfloat16", "int16"), K * N),
+                       _arg(Cout, "C", ("float32",), M * N))
+    return _check(lib().ie_nn_gemm(ap, bp, cp, M, N, K, a_trans, b_trans, splits,
                                    _stream(stream)), "ie_nn_gemm")
 
 
 def ie_nn_features(ctx, sigma6, b, x, stream=None):
     """Features into x (bfloat16 [nz, ny, nx, 14]); returns rms(b)."""
+    N, d = _ctx_cells(ctx)
+    s6, bp, xp = _ptrs(d, _tensor6(ctx, sigma6), _field(ctx, b, "b"),
+                       _arg(x, "x", ("bfloat16",), None if N is None else 14 * N))
     r = C.c_double(0)
-    _check(lib().ie_nn_features(C.c_void_p(ctx), _ptr(sigma6), _ptr(b), _ptr(x), C.byref(r),
-                                _stream(stream)), "ie_nn_features")
+    _check(lib().ie_nn_features(C.c_void_p(ctx), s6, bp, xp, C.byref(r), _stream(stream)),
+           "ie_nn_features")
     return r.value
 
 
 def ie_nn_target(ctx, b, E, y, stream=None):
-    return _check(lib().ie_nn_target(C.c_void_p(ctx), _ptr(b), _ptr(E), _ptr(y), _stream(stream)),
+    N, d = _ctx_cells(ctx)
+    bp, ep, yp = _ptrs(d, _field(ctx, b, "b"), _field(ctx, E, "E"),
+                       _arg(y, "y", ("float32",), None if N is None else 6 * N))
+    return _check(lib().ie_nn_target(C.c_void_p(ctx), bp, ep, yp, _stream(stream)),
                   "ie_nn_target")
 
 
 def ie_nn_predict(ctx, nn, sigma6, b, x, stream=None):
     """The network's (unjudged) guess for the full grid into x."""
-    return _check(lib().ie_nn_predict(C.c_void_p(ctx), C.c_void_p(nn), _ptr(sigma6), _ptr(b),
-                                      _ptr(x), _stream(stream)), "ie_nn_predict")
+    s6, bp, xp = _ptrs(_dev_of(ctx), _tensor6(ctx, sigma6), _field(ctx, b, "b"),
+                       _field(ctx, x, "x"))
+    return _check(lib().ie_nn_predict(C.c_void_p(ctx), C.c_void_p(nn), s6, bp, xp,
+                                      _stream(stream)), "ie_nn_predict")
 
 
 def ie_nn_guess(ctx, nn, sigma6, b, x, stream=None):
     """Learned guess on the full grid; returns 1 (learned), 0 (default kept) or 2 (zero)."""
+    s6, bp, xp = _ptrs(_dev_of(ctx), _tensor6(ctx, sigma6), _field(ctx, b, "b"),
+                       _field(ctx, x, "x"))
     acc = C.c_int32(0)
-    _check(lib().ie_nn_guess(C.c_void_p(ctx), C.c_void_p(nn), _ptr(sigma6), _ptr(b), _ptr(x),
-                             C.byref(acc), _stream(stream)), "ie_nn_guess")
+    _check(lib().ie_nn_guess(C.c_void_p(ctx), C.c_void_p(nn), s6, bp, xp, C.byref(acc),
+                             _stream(stream)), "ie_nn_guess")
     return acc.value
