@@ -201,6 +201,28 @@ int ie_background_field(ie_ctx* ctx, const ie_source* sources, int32_t nsources,
 int ie_matvec(ie_ctx* ctx, const double* sigma6, const void* x, void* y, int32_t form,
               int32_t precision, void* stream);
 
+/* Size in bytes of the fixed per-device scratch array of ie_matvec_noalloc. */
+#define IE_NOALLOC_MAX_BYTES (64u << 20)
+
+/*
+ * ie_matvec_noalloc - ie_matvec for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Arguments, forms,
+ * layouts and result are those of ie_matvec (the same kernels and launch variants run).
+ *   Scratch: the prepared contrast tensor, the padded FFT work arrays and a validation flag live
+ *            in one fixed device array of IE_NOALLOC_MAX_BYTES per device, whose address is
+ *            resolved when a context is set up on that device; the call itself allocates
+ *            nothing.  A grid whose scratch exceeds the array is rejected with IE_EINVAL
+ *            (6 r N + 3 s nz LX (ny + LY) bytes, r/s = real/complex size of the precision: up
+ *            to 64^3 cells in IE_MIXED, 48^3 in IE_FP64).
+ *   Sharing: every call on a device uses that device's one array, which keeps the last call's
+ *            contents; calls that overlap in time on one device race and must be serialised
+ *            by the caller (one stream, or events).
+ *   The current device must be the context's (IE_EINVAL otherwise).  Unless form is
+ *   IE_GREEN_ONLY the call synchronises `stream` once to read the tensor validation flag.
+ */
+int ie_matvec_noalloc(ie_ctx* ctx, const double* sigma6, const void* x, void* y, int32_t form,
+                      int32_t precision, void* stream);
+
 /*
  * ie_gmres - solve (I - G dsigma) x = b on the context's full grid by restarted GMRES
  * (section 2.2; restart length from opts, section 3.1 uses 10).

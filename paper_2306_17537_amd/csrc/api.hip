@@ -201,6 +201,7 @@ int ie_green_setup(const ie_grid* grid, const ie_medium* medium, const ie_partit
   c->zb = zb;
   c->prec_mask = precision_mask;
   IE_HIP(hipGetDevice(&c->device));
+  IE_TRY(noalloc_init(c->device));
   Medium& m = c->med;
   m.sigma0 = medium->sigma0;
   m.freq = medium->freq_hz;

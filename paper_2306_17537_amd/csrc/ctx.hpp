@@ -63,6 +63,10 @@ struct Plan {
 
 int fft_len(int n);  // power of two >= 2n - 1 (and >= 2)
 
+// Resolves, once per device, the address of the fixed scratch array of ie_matvec_noalloc
+// (called by ie_green_setup with the context's device current).
+int noalloc_init(int device);
+
 struct Medium {
   double sigma0, freq, mu0, omega;
   double k0re, k0im;  // k0 = sqrt(i omega mu0 sigma0), Im k0 > 0
@@ -71,7 +75,9 @@ struct Medium {
 struct ie_ctx_impl;
 
 // Operator launch: y = a_e e + a_x x - a_m M x + a_s G (M x) on plan p.
-// Fields in MvArgs that are geometry (sizes, work, ghat, tw) are filled in by the launcher.
+// Fields in MvArgs that are geometry (sizes, ghat, tw) are filled in by the launcher; the padded
+// work buffers are the plan's own unless the caller sets both a.T1 and a.T2 (one problem, at
+// least t1_elems()/t2_elems() values each), in which case nothing is allocated.
 // only >= 0 launches that pass alone (0 xfwd, 1 yfwd, 2 zconv, 3 yinv, 4 xinv); vover >= 0
 // replaces the plan's variant (both for the autotuner).
 template <typename T>

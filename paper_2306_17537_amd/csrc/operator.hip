@@ -187,15 +187,20 @@ int launch_matvec(Plan& p, MvArgs<T> a, int batch, hipStream_t s, const cx<T>* t
   const int8_t* var = p.var[dbl ? 0 : 1];
   auto vsel = [&](int pass) { return vover >= 0 ? vover : int(var[pass]); };
   auto want = [&](int pass) { return only < 0 || only == pass; };
-  IE_TRY(p.work(dbl ? IE_FP64 : IE_MIXED, batch));
+  // padded work: the caller's (both T1 and T2 set, one problem) or the plan's own buffers
+  const bool own_work = a.T1 == nullptr || a.T2 == nullptr;
+  if (!own_work && batch != 1) return fail(IE_EINVAL, "caller work buffers hold one problem");
+  if (own_work) {
+    IE_TRY(p.work(dbl ? IE_FP64 : IE_MIXED, batch));
+    a.T1 = dbl ? (cx<T>*)p.t1_64.p : (cx<T>*)p.t1_32.p;
+    a.T2 = dbl ? (cx<T>*)p.t2_64.p : (cx<T>*)p.t2_32.p;
+  }
   a.nx = p.nx;
   a.ny = p.ny;
   a.nz = p.nz;
   a.LX = p.LX;
   a.LY = p.LY;
   a.LZ = p.LZ;
-  a.T1 = dbl ? (cx<T>*)p.t1_64.p : (cx<T>*)p.t1_32.p;
-  a.T2 = dbl ? (cx<T>*)p.t2_64.p : (cx<T>*)p.t2_32.p;
   a.T1_bs = p.t1_elems();
   a.T2_bs = p.t2_elems();
   a.ghat = dbl ? (const cx<T>*)p.ghat64.p : (const cx<T>*)p.ghat32.p;

@@ -101,6 +101,7 @@ def lib():
         L.ie_ctx_destroy.argtypes = [vp]
         L.ie_background_field.argtypes = [vp, C.POINTER(ie_source), i32, vp, vp]
         L.ie_matvec.argtypes = [vp, vp, vp, vp, i32, i32, vp]
+        L.ie_matvec_noalloc.argtypes = [vp, vp, vp, vp, i32, i32, vp]
         L.ie_gmres.argtypes = [vp, vp, vp, vp, C.POINTER(ie_gmres_opts),
                                C.POINTER(ie_gmres_stats), vp]
         L.ie_dd_solve.argtypes = [C.POINTER(vp), i32, C.POINTER(ie_problem),
@@ -126,6 +127,7 @@ def lib():
         L.ie_nn_features.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_double), vp]
         L.ie_nn_target.argtypes = [vp, vp, vp, vp, vp]
         for f in ("ie_green_setup", "ie_ctx_destroy", "ie_background_field", "ie_matvec",
+                  "ie_matvec_noalloc",
                   "ie_gmres", "ie_dd_solve", "ie_profile_begin", "ie_profile_end",
                   "ie_nn_create", "ie_nn_destroy", "ie_nn_num_params", "ie_nn_get_params",
                   "ie_nn_set_params", "ie_nn_forward", "ie_nn_backward", "ie_nn_train_step",
@@ -285,6 +287,12 @@ def ie_matvec(ctx, sigma6, x, y, form=IE_CONVENTIONAL, precision=IE_FP64, stream
     s6, xp, yp = _matvec_args(ctx, sigma6, x, y, form, precision)
     return _check(lib().ie_matvec(C.c_void_p(ctx), s6, xp, yp, form, precision, _stream(stream)),
                   "ie_matvec")
+
+
+def ie_matvec_noalloc(ctx, sigma6, x, y, form=IE_CONVENTIONAL, precision=IE_FP64, stream=None):
+    s6, xp, yp = _matvec_args(ctx, sigma6, x, y, form, precision)
+    return _check(lib().ie_matvec_noalloc(C.c_void_p(ctx), s6, xp, yp, form, precision,
+                                          _stream(stream)), "ie_matvec_noalloc")
 
 
 def ie_gmres(ctx, sigma6, b, x, tol=1e-6, restart=10, max_its=2000, precision=IE_FP64,

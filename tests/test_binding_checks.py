@@ -43,6 +43,8 @@ def test_matvec_rejects_wrong_dtype_size_layout_and_host_memory():
         ie.ie_matvec(CTX, s6, strided, _field())
     with pytest.raises(ValueError, match="GPU"):
         ie.ie_matvec(CTX, s6, _field(), _field())
+    with pytest.raises(ValueError, match="GPU"):
+        ie.ie_matvec_noalloc(CTX, s6, _field(), _field())
     with pytest.raises(ValueError, match="required"):
         ie.ie_matvec(CTX, None, _field(), _field(), form=ie.IE_CIE)
     with pytest.raises(ValueError, match="torch tensor"):
