@@ -227,6 +227,13 @@ def _dev_of(ctx):
     return _ctx_cells(ctx)[1]
 
 
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(stream)
+
+
 def ie_last_error() -> str:
     return lib().ie_last_error().decode()
 

@@ -91,3 +91,47 @@ def test_network_calls_check_their_arrays():
     with pytest.raises(ValueError, match="C: dtype"):
         ie.ie_nn_gemm(torch.zeros(6, dtype=torch.bfloat16), torch.zeros(6, dtype=torch.bfloat16),
                       torch.zeros(4, dtype=torch.float64), 2, 2, 3)
+
+
+def test_every_wrapper_marshals_valid_arrays_through_to_the_library(monkeypatch):
+    """With the device check and the library replaced by stand-ins, each wrapper turns valid
+    arrays into one library call with the C name (catches marshalling mistakes on the CPU)."""
+    import ctypes as C
+    calls = []
+
+    class FakeLib:
+        def __getattr__(self, name):
+            def f(*args):
+                calls.append(name)
+                return 0
+            return f
+
+    monkeypatch.setattr(ie, "lib", lambda: FakeLib())
+    monkeypatch.setattr(ie, "_ptrs", lambda device, *a: [None if x is None else
+                                                          C.c_void_p(x[1].data_ptr()) for x in a])
+    monkeypatch.setattr(ie, "_stream", lambda stream: C.c_void_p(0))
+    s6 = torch.zeros(6 * N, dtype=torch.float64)
+    src = [((0, 0, 5.0), (0, 0, 1), "magnetic")]
+    ie.ie_background_field(CTX, src, _field())
+    ie.ie_matvec(CTX, s6, _field(), _field())
+    ie.ie_matvec_noalloc(CTX, s6, _field(torch.complex64), _field(torch.complex64),
+                         precision=ie.IE_MIXED)
+    ie.ie_gmres(CTX, s6, _field(), _field())
+    g = ie.make_grid((4, 3, 2), 0.25, (0, 0, 0))
+    ie.ie_dd_solve([CTX], [dict(grid=g, sigma6=s6, sources=src, E_total=_field())], ie.dd_opts())
+    ie.ie_receivers(CTX, s6, src, _field(), [[0, 0, 9.0]])
+    x = torch.zeros((1, 2, 3, 4, 14), dtype=torch.bfloat16)
+    y = torch.zeros((1, 2, 3, 4, 6), dtype=torch.float32)
+    ie.ie_nn_forward(NN, x, y)
+    ie.ie_nn_backward(NN, x, y.clone(), y)
+    ie.ie_nn_train_step(NN, x, y, 1e-3)
+    ie.ie_nn_gemm(torch.zeros(6, dtype=torch.bfloat16), torch.zeros(6, dtype=torch.bfloat16),
+                  torch.zeros(4, dtype=torch.float32), 2, 2, 3)
+    ie.ie_nn_features(CTX, s6, _field(), torch.zeros((N, 14), dtype=torch.bfloat16))
+    ie.ie_nn_target(CTX, _field(), _field(), torch.zeros((N, 6), dtype=torch.float32))
+    ie.ie_nn_predict(CTX, NN, s6, _field(), _field())
+    ie.ie_nn_guess(CTX, NN, s6, _field(), _field())
+    assert calls == ["ie_background_field", "ie_matvec", "ie_matvec_noalloc", "ie_gmres",
+                     "ie_dd_solve", "ie_receivers", "ie_nn_forward", "ie_nn_backward",
+                     "ie_nn_train_step", "ie_nn_gemm", "ie_nn_features", "ie_nn_target",
+                     "ie_nn_predict", "ie_nn_guess"]
