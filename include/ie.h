@@ -147,6 +147,8 @@ typedef struct {
     int32_t learned_used;                            /* blocks whose learned guess was accepted */
     int32_t graph_cycles;                            /* inner restart cycles replayed from graphs */
     double  seconds;
+    int32_t best_sweep;   /* stationary sweeps: the sweep whose iterate is returned (smallest e) */
+    int32_t diverged;     /* 1 if stopped because e grew in two consecutive sweeps */
 } ie_dd_stats;
 
 typedef struct {
@@ -245,7 +247,12 @@ int ie_gmres(ie_ctx* ctx, const double* sigma6, const void* b, void* x,
  * Sub-domains without contrast take E(i) = right-hand side with no inner iterations.
  *   ctxs[p], problems[p], stats[p] for p < nproblems (problems may have different grids;
  *   each context must have been set up with a partition).  Problems are advanced together.
- * Returns IE_ENOCONV if any problem hit max_sweeps.  Synchronises with `stream`.
+ * The stationary sweeps converge only when the block splitting contracts (section 2.3); a
+ * problem whose relative residual grows in two consecutive sweeps is stopped (stats.diverged),
+ * and every problem that did not reach opts->tol returns the iterate of smallest residual
+ * (stats.best_sweep) in E_total / E_anom.
+ * Returns IE_ENOCONV if any problem hit max_sweeps or was stopped; the message names the cause.
+ * Synchronises with `stream`.
  */
 int ie_dd_solve(ie_ctx* const* ctxs, int32_t nproblems, const ie_problem* problems,
                 const ie_dd_opts* opts, ie_dd_stats* stats, void* stream);

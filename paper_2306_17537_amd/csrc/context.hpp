@@ -11,6 +11,7 @@ namespace ie {
 // Scratch of the domain-decomposition driver, sized for the largest problem group seen.
 struct DdBufs {
   DevBuf D64, M64, M32, A64, Ai64, E0, E, Eold, rhs, x, active, flags, bad;
+  DevBuf best;  // iterate of smallest full residual per problem (stationary sweeps)
   DevBuf xl;  // learned first-sweep guesses
   DevBuf fv, fz, fw, fpart;  // Krylov outer iteration: basis, preconditioned vectors, work
 };

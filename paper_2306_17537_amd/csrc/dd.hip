@@ -418,6 +418,9 @@ int check_problem(ie_ctx* c, const ie_problem& pr) {
   return check_sources(c, pr.sources, pr.nsources);
 }
 
+// *worst after a group: IE_OK, IE_ENOCONV (sweeps or iterations exhausted) or kDiverged
+constexpr int kDiverged = 2;
+
 int dd_group(ie_ctx* c, const std::vector<int>& idx, const ie_problem* problems,
              const ie_dd_opts& o, ie_dd_stats* stats, hipStream_t s, int* worst) {
   const auto t0 = std::chrono::steady_clock::now();
@@ -546,6 +549,13 @@ int dd_group(ie_ctx* c, const std::vector<int>& idx, const ie_problem* problems,
     std::vector<GmResult> pre(B);  // the judge's cycles in the first sweep of a learned start
     const double inf = std::numeric_limits<double>::infinity();
     bool first = true;
+    // The sweeps converge only when the block splitting contracts (section 2.3: diagonal
+    // dominance); the iterate of smallest full residual is kept, and a problem whose residual
+    // grows in two consecutive sweeps is stopped.
+    IE_TRY(gb.best.ensure(sizeof(c128) * 3 * N * B));
+    c128* best = gb.best.as<c128>();
+    std::vector<double> best_e(e);
+    IE_HIP(hipMemcpyAsync(best, g.E, sizeof(c128) * 3 * N * B, hipMemcpyDeviceToDevice, s));
 
     while (true) {
       bool any = false;
@@ -627,12 +637,32 @@ int dd_group(ie_ctx* c, const std::vector<int>& idx, const ie_problem* problems,
         ie_dd_stats& st = stats[idx[b]];
         for (int i = 0; i < M; ++i) st.total_its += st.block_its[sweeps[b]][i];
         sweeps[b] += 1;
-        st.sweeps = sweeps[b];
-        st.relres[sweeps[b]] = e[b];
+        const int k = sweeps[b];
+        st.sweeps = k;
+        st.relres[k] = e[b];
         st.full_matvecs += 1;
         st.matvecs64 += 1;
-        if (e[b] <= o.tol) act[b] = 0;
+        if (e[b] < best_e[b]) {
+          best_e[b] = e[b];
+          st.best_sweep = k;
+          IE_HIP(hipMemcpyAsync(best + b * 3 * N, g.E + b * 3 * N, sizeof(c128) * 3 * N,
+                                hipMemcpyDeviceToDevice, s));
+        }
+        if (e[b] <= o.tol) {
+          act[b] = 0;
+        } else if (k >= 2 && st.relres[k] > st.relres[k - 1] &&
+                   st.relres[k - 1] > st.relres[k - 2]) {
+          act[b] = 0;
+          st.diverged = 1;
+        }
       }
+    }
+    // a problem that did not reach the tolerance returns its iterate of smallest residual
+    for (int b = 0; b < B; ++b) {
+      if (e[b] <= o.tol || best_e[b] >= e[b]) continue;
+      e[b] = best_e[b];
+      IE_HIP(hipMemcpyAsync(g.E + b * 3 * N, best + b * 3 * N, sizeof(c128) * 3 * N,
+                            hipMemcpyDeviceToDevice, s));
     }
   }  // stationary sweeps
   // outputs
@@ -647,7 +677,7 @@ int dd_group(ie_ctx* c, const std::vector<int>& idx, const ie_problem* problems,
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   for (int b = 0; b < B; ++b) {
     stats[idx[b]].seconds = secs;
-    if (e[b] > o.tol) *worst = IE_ENOCONV;
+    if (e[b] > o.tol) *worst = std::max(*worst, stats[idx[b]].diverged ? kDiverged : IE_ENOCONV);
   }
   return IE_OK;
 }
@@ -759,7 +789,7 @@ extern "C" int ie_dd_solve(ie_ctx* const* ctxs, int32_t nproblems, const ie_prob
         rc = l.rc;
         err = l.err;
       }
-      if (l.worst == IE_ENOCONV) worst = IE_ENOCONV;
+      worst = std::max(worst, l.worst);
     }
     for (auto& l : lanes) {
       if (l.done) (void)hipEventDestroy(l.done);
@@ -768,6 +798,13 @@ extern "C" int ie_dd_solve(ie_ctx* const* ctxs, int32_t nproblems, const ie_prob
     (void)hipEventDestroy(start);
     if (rc < 0) return err.empty() ? fail(rc, "device error in a group") : fail(rc, "%s", err.c_str());
   }
-  if (worst == IE_ENOCONV) return fail(IE_ENOCONV, "at least one problem did not converge");
+  if (worst == kDiverged)
+    return fail(IE_ENOCONV,
+                "the full residual (eq. 9) of at least one problem grew in two consecutive sweeps "
+                "(the block sweep does not contract); its output is the iterate of smallest "
+                "residual (ie_dd_stats.best_sweep)");
+  if (worst == IE_ENOCONV)
+    return fail(IE_ENOCONV, "at least one problem did not converge; outputs of the stationary "
+                            "sweeps are the iterates of smallest residual");
   return IE_OK;
 }

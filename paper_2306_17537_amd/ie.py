@@ -66,7 +66,8 @@ class ie_dd_stats(C.Structure):
                 ("relres", C.c_double * (IE_MAX_SWEEPS + 1)),
                 ("matvecs64", C.c_int32), ("matvecs32", C.c_int32),
                 ("full_matvecs", C.c_int32), ("learned_used", C.c_int32),
-                ("graph_cycles", C.c_int32), ("seconds", C.c_double)]
+                ("graph_cycles", C.c_int32), ("seconds", C.c_double),
+                ("best_sweep", C.c_int32), ("diverged", C.c_int32)]
 
 
 class ie_problem(C.Structure):

@@ -9,7 +9,9 @@ FETCH_SIZE.  ``calibrate()`` issues both; bench.py runs it first under ``--pmc-c
 Summaries are written as markdown with one machine-readable line per kernel variant:
     traffic-json: {"kernel": ..., "fetch_bytes": ..., "write_bytes": ..., "sources": ...}
 ``sources`` is a hash of the kernel source files at measurement time; ``lookup()`` returns
-nothing once the sources have changed, so a stale figure is never reported.
+nothing once the sources have changed, so a stale figure is never reported.  Kernel-trace
+summaries carry the same kind of line per kernel (``trace-json:``, average duration), read by
+``trace_lookup()``.
 
 Usage (from the repository root, after the profiler runs):
     python -m paper_2306_17537_amd.traffic summarize --fetch DIR1 --write DIR2 \\
@@ -129,6 +131,22 @@ def lookup(kernel, profiles_dir=None):
     return None
 
 
+def trace_lookup(kernel, profiles_dir=None):
+    """(average microseconds, calls, summary path) of `kernel` (exact template name) in the
+    committed kernel-trace summaries measured on the current kernel sources, or None."""
+    profiles_dir = profiles_dir or os.path.join(ROOT, "profiles")
+    src = sources_hash()
+    for path in sorted(glob.glob(os.path.join(profiles_dir, "*.md"))):
+        with open(path) as f:
+            for line in f:
+                if not line.startswith("trace-json: "):
+                    continue
+                d = json.loads(line[len("trace-json: "):])
+                if d["kernel"] == kernel and d.get("sources") == src:
+                    return d["avg_us"], d["calls"], path
+    return None
+
+
 def kernel_stats(directory, top=20):
     """Rows (name, calls, avg us, min us, max us, percent) of a --kernel-trace --stats run."""
     paths = glob.glob(os.path.join(directory, "**", "*kernel_stats.csv"), recursive=True)
@@ -147,12 +165,16 @@ def write_stats_markdown(rows, path, command, title, extra=""):
     lines = [f"# {title}", "", "Command (from /tmp with TMPDIR=/tmp, repository at $R):", "", "```",
              command, "```", "", "| kernel | calls | avg us | min us | max us | % time |",
              "|---|---|---|---|---|---|"]
+    src = sources_hash()
+    js = []
     for n, c, a, lo, hi, pc in rows:
         m = re.search(r"(k_\w+(?:<[^>]*>)?|__amd\w+)", n)
         name = m.group(1) if m else re.sub(r"^void ", "", n)
         lines.append(f"| `{name[:80]}` | {c} | {a:.2f} | {lo:.2f} | {hi:.2f} | {pc:.2f} |")
+        js.append("trace-json: " + json.dumps(dict(kernel=name, sources=src, calls=c, avg_us=a)))
     if extra:
         lines += ["", extra]
+    lines += [""] + js
     with open(path, "w") as f:
         f.write("\n".join(lines) + "\n")
 

@@ -353,3 +353,49 @@ def test_four_slab_gauss_seidel_history_matches_oracle(torch):
         assert np.allclose(gpu, oinfo["relres"], rtol=1e-3, atol=0)
     finally:
         ie.ie_ctx_destroy(ctx)
+
+
+def test_diverging_block_sweep_stops_and_returns_the_best_iterate(torch):
+    """Section 2.3: block GS converges only when the splitting contracts.  A strongly contrasted
+    8^3 model over four z slabs makes the oracle's GS residual fall for two sweeps and then grow;
+    the library follows the oracle's residual history, stops once e has grown in two consecutive
+    sweeps (IE_ENOCONV, stats.diverged) and returns the iterate of smallest recorded residual,
+    which equals the oracle's field after that sweep."""
+    from paper_2306_17537_amd import ie
+    from oracle import dd
+    p = synth.random_problem((8, 8, 8), seed=2, contrast=50.0, freq=2.0e6,
+                             z_bounds=(0, 2, 4, 6, 8))
+    st = solve.setup(p)
+    _, info = dd.dd_solve(st, p.z_bounds, scheme="gs", adaptive=False, inner_tol_fixed=1e-10,
+                          tol=1e-8, form="conventional", max_sweeps=4)
+    hist = info["relres"]
+    best = int(np.argmin(hist))
+    assert hist[3] > hist[2] > hist[1] or hist[4] > hist[3] > hist[2]  # the case grows twice
+    E_best, _ = dd.dd_solve(st, p.z_bounds, scheme="gs", adaptive=False, inner_tol_fixed=1e-10,
+                            tol=0.0, form="conventional", max_sweeps=best)
+    ctx, g = context(p, z_bounds=p.z_bounds)
+    try:
+        E = torch.zeros(field_shape(p), dtype=torch.complex128, device="cuda:0")
+        opts = ie.dd_opts(scheme=ie.IE_GS, adaptive=False, tol=1e-8, inner_tol_fixed=1e-10,
+                          precision=ie.IE_FP64, form=ie.IE_CONVENTIONAL, max_sweeps=40)
+        with pytest.raises(ie.IEError) as err:
+            ie.ie_dd_solve([ctx], [dict(grid=g, sigma6=dev(p.sigma6), sources=p.sources,
+                                        E_total=E)], opts)
+        assert err.value.code == ie.IE_ENOCONV and "consecutive" in str(err.value)
+        rc, stats = ie.ie_dd_solve([ctx], [dict(grid=g, sigma6=dev(p.sigma6), sources=p.sources,
+                                                E_total=E)], opts, allow_noconv=True)
+        s = stats[0]
+        gpu_hist = [s.relres[k] for k in range(s.sweeps + 1)]
+        banner(f"  oracle e: {['%.3e' % v for v in hist]}; GPU e: "
+               f"{['%.3e' % v for v in gpu_hist]}; best sweep {s.best_sweep}")
+        assert rc == ie.IE_ENOCONV and s.diverged == 1
+        assert s.sweeps == len(gpu_hist) - 1 and s.sweeps <= 4
+        for a, b in zip(gpu_hist, hist):
+            assert abs(a - b) <= 1e-6 * b
+        assert s.best_sweep == int(np.argmin(gpu_hist)) == best
+        Eh = host(E)
+        assert operator.relres(st.Ghat, st.dsig, Eh, st.E0, p.n) == pytest.approx(
+            gpu_hist[best], rel=1e-8)
+        assert rel(Eh - st.E0, E_best - st.E0) <= 1e-6
+    finally:
+        ie.ie_ctx_destroy(ctx)
