@@ -255,7 +255,7 @@ def main():
                      "measured": "HIP events on the launch stream around every launch, in a "
                                  "profiled replay of the timed step (direct launches)",
                      "rocprof": rocprof},
-        "roofline_alu": zconv_alu(dom, avg_ms),
+        "roofline_alu": pass_alu(dom, avg_ms),
         "cpu_baseline": cpu,
         "chosen_form": chosen,
         "induction_log": receivers_out,
@@ -366,15 +366,16 @@ def config1_legs(ie, torch, args, acc):
         for _ in range(reps):
             ie.ie_matvec(ctx, s6, xx, yy, ie.IE_CIE, prec)
         pr = ie.ie_profile_end()
-        passes = [k for k in pr if k["name"].split()[0] in ("xfwd", "yfwd", "zconv", "yinv",
-                                                             "xinv")]
+        passes = [k for k in pr if k["name"].split()[0] in PASSES]
         t_ms = sum(k["total_ms"] for k in passes) / reps
         byts = sum(k["bytes_per_launch"] * k["launches"] for k in passes) / reps
         tr = measured_traffic({k["name"]: k for k in passes}, tuning, p.n)
         mv[nm] = dict(ms=round(t_ms, 4), algorithmic_bytes=int(byts), cache_resident=True,
                       gbs=round(byts / (t_ms * 1e-3) / 1e9, 1),
                       traffic_bytes=None if tr is None else int(tr),
-                      matvecs_per_s=round(1e3 / t_ms, 1))
+                      matvecs_per_s=round(1e3 / t_ms, 1),
+                      passes_us={k["name"].split()[0]: round(1e3 * k["total_ms"] / k["launches"], 1)
+                                 for k in passes})
     out["matvec"] = mv
     if not args.no_nn:
         out["learned_guess"] = learned_bench(ie, torch, ctx, s6, p, ref)
@@ -383,29 +384,34 @@ def config1_legs(ie, torch, args, acc):
     return out
 
 
-def zconv_alu(dom, avg_ms):
-    """The dominant kernel (the z pass) against the vector-ALU peak: model flops per launch =
-    lines x (6 transforms x 5 L log2 L + 72 L) for L = LZ (three components, forward and
-    inverse, unpruned) plus the 3x3 complex tensor multiply (72 flop per padded point)."""
+def pass_alu(dom, avg_ms):
+    """An operator pass against the vector-ALU peak, model flops per launch: 5 L log2 L per
+    length-L transform (three components, forward and inverse in the x pass, one direction in the
+    others) plus 72 per point for the tensor multiply of the x pass."""
     parts = dom["name"].split()
-    if len(parts) < 3 or parts[0] != "zconv" or not parts[2].startswith("L"):
+    if len(parts) < 3 or parts[0] not in ("xconv", "zfwd", "zinv") or not parts[2].startswith("L"):
         return None
     lx, ly, lz = (int(v) for v in parts[2][1:].split("x"))
     batch = int(parts[-1][1:]) if parts[-1].startswith("b") else 1
-    flops = float(lx * ly * batch) * (6 * 5 * lz * float(np.log2(lz)) + 72 * lz)
+    nz = int(parts[3][2:]) if len(parts) > 3 and parts[3].startswith("nz") else lz // 2
+    if parts[0] == "xconv":
+        flops = float(ly * lz * batch) * (6 * 5 * lx * float(np.log2(lx)) + 72 * lx)
+    else:  # a z pass over the columns of the (ny, nx) plane; ny, nx from LY, LX at 2x padding
+        flops = float((ly // 2) * (lx // 2) * batch) * 3 * 5 * lz * float(np.log2(lz))
     tf = float(flops / (avg_ms * 1e-3) / 1e12)
     return {"bound": "alu", "achieved": round(tf, 2), "peak": VALU_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": round(tf / VALU_PEAK_TFLOPS, 4),
             "flops_per_launch": int(flops), "kernel": dom["name"]}
 
 
-PASS_NAMES = {"xfwd": "k_xfwd", "xinv": "k_xinv", "zconv": "k_zconv", "yfwd": "k_colfft",
+PASSES = ("zfwd", "yfwd", "xconv", "yinv", "zinv")
+PASS_NAMES = {"zfwd": "k_zfwd", "zinv": "k_zinv", "xconv": "k_xconv", "yfwd": "k_colfft",
               "yinv": "k_colfft"}
 
 
 def template_name(prof_name, tuning, grid):
     """Kernel template name (as rocprofv3 prints it) of a library profiler entry on the full
-    grid, with the launch variant the autotuner chose, e.g. 'k_zconv<float, 128, 1>'."""
+    grid, with the launch variant the autotuner chose, e.g. 'k_xconv<double, 256, 0>'."""
     parts = prof_name.split()
     if len(parts) < 3 or parts[0] not in PASS_NAMES:
         return None
@@ -420,7 +426,7 @@ def template_name(prof_name, tuning, grid):
         L = int(dims[0])
         inv = "true" if parts[0] == "yinv" else "false"
         return f"k_colfft<{t}, {L}, {inv}, {m[0]['variant']}>"
-    L = int(dims[2]) if parts[0] == "zconv" else int(dims[0])
+    L = int(dims[0]) if parts[0] == "xconv" else int(dims[2])
     return f"{PASS_NAMES[parts[0]]}<{t}, {L}, {m[0]['variant']}>"
 
 
@@ -491,7 +497,7 @@ def matvec_large(ie, torch, ctx, s6, p):
             ie.ie_matvec(ctx, s6, x, y, ie.IE_CIE, prec)
         pr = ie.ie_profile_end()
         passes = {k["name"].split()[0]: k for k in pr
-                  if k["name"].split()[0] in ("xfwd", "yfwd", "zconv", "yinv", "xinv")}
+                  if k["name"].split()[0] in PASSES}
         t_ms = sum(k["total_ms"] for k in passes.values()) / reps
         byts = sum(k["bytes_per_launch"] * k["launches"] for k in passes.values()) / reps
         tr = measured_traffic(passes, tuning, p.n)

@@ -171,8 +171,8 @@ typedef struct ie_ctx ie_ctx;
  *   precision_mask: IE_FP64 | IE_MIXED - which spectra to keep (complex128, complex64).
  *   stream        : work is queued on it; the call synchronises before returning.
  *   out           : receives the new context (NULL on error).
- * Memory: about 12 nx (ny+1)(nz+1) complex values per spectrum (all kx, half of ky and kz)
- * plus padded work buffers of about 30 nx ny nz complex values per precision.
+ * Memory: about 1.5 (nx+1)(ny+1)(nz+1) complex values per spectrum (one octant of the six
+ * components) plus padded work buffers of about 18 nx ny nz complex values per precision.
  */
 int ie_green_setup(const ie_grid* grid, const ie_medium* medium, const ie_partition* partition,
                    int32_t precision_mask, void* stream, ie_ctx** out);
@@ -214,7 +214,7 @@ int ie_matvec(ie_ctx* ctx, const double* sigma6, const void* x, void* y, int32_t
  *            in one fixed device array of IE_NOALLOC_MAX_BYTES per device, whose address is
  *            resolved when a context is set up on that device; the call itself allocates
  *            nothing.  A grid whose scratch exceeds the array is rejected with IE_EINVAL
- *            (6 r N + 3 s nz LX (ny + LY) bytes, r/s = real/complex size of the precision: up
+ *            (6 r N + 3 s LZ nx (ny + LY) bytes, r/s = real/complex size of the precision: up
  *            to 64^3 cells in IE_MIXED, 48^3 in IE_FP64).
  *   Sharing: every call on a device uses that device's one array, which keeps the last call's
  *            contents; calls that overlap in time on one device race and must be serialised
@@ -377,8 +377,8 @@ int ie_receivers(ie_ctx* ctx, const double* sigma6, const ie_source* src, int32_
  *                  the fastest (cached per device, precision and grid for the process); 0 uses
  *                  the default variant.  Affects contexts set up afterwards.
  *   IE_OPT_FORCE_VARIANT: -1 (default) leaves the choice to the autotuner; 0 .. 7 puts every
- *                  pass of contexts set up afterwards on that variant (passes with four variants
- *                  take it modulo 4): for tests that cover every variant.
+ *                  pass of contexts set up afterwards on that variant (the column passes, which
+ *                  have four variants, take it modulo 4): for tests that cover every variant.
  *   IE_OPT_GROUP_THREADS: 1 (default) lets ie_dd_solve advance the problems of different
  *                  contexts at the same time (one host thread and one stream per context, joined
  *                  to the caller's stream); 0 solves the groups one after the other.  Results are

@@ -133,10 +133,10 @@ namespace {
 bool g_autotune = true;
 int g_force_variant = -1;
 
-// every pass of the plan on one variant (row passes have eight, the others four)
+// every pass of the plan on one variant (the x pass has eight, the column passes four)
 void force_variant(Plan& p, int v) {
   for (int pi = 0; pi < 2; ++pi)
-    for (int q = 0; q < 5; ++q) p.var[pi][q] = int8_t((q == 0 || q == 4) ? v : (v & 3));
+    for (int q = 0; q < 5; ++q) p.var[pi][q] = int8_t(q == 2 ? v : (v & 3));
 }
 }  // namespace
 
@@ -250,7 +250,7 @@ int ie_green_setup(const ie_grid* grid, const ie_medium* medium, const ie_partit
 
 int ie_ctx_tuning(const ie_ctx* ctx, char* buf, int32_t len) {
   if (ctx == nullptr || buf == nullptr || len < 1) return fail(IE_EINVAL, "bad arguments");
-  static const char* pass_names[5] = {"xfwd", "yfwd", "zconv", "yinv", "xinv"};
+  static const char* pass_names[5] = {"zfwd", "yfwd", "xconv", "yinv", "zinv"};
   std::string o = "[";
   auto plan = [&](const Plan& p) {
     for (int pi = 0; pi < 2; ++pi) {

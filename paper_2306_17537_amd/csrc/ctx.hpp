@@ -47,17 +47,17 @@ struct DevBuf {
 struct Plan {
   int nx = 0, ny = 0, nz = 0;
   int LX = 0, LY = 0, LZ = 0;
-  DevBuf ghat64, ghat32;  // [6][LZ/2+1][LY/2+1][LX]
-  DevBuf t1_64, t2_64, t1_32, t2_32;  // padded work, capacity `cap` problems
+  DevBuf ghat64, ghat32;  // [6][LZ/2+1][LY/2+1][LX/2+1]
+  DevBuf t1_64, t2_64, t1_32, t2_32;  // padded work U1, U2, capacity `cap` problems
   int cap64 = 0, cap32 = 0;
-  // launch variant per [precision: 0 float64, 1 complex64][pass: xfwd, yfwd, zconv, yinv, xinv],
+  // launch variant per [precision: 0 float64, 1 complex64][pass: zfwd, yfwd, xconv, yinv, zinv],
   // set by the autotuner (0 when tuning is off)
   int8_t var[2][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
   float tune_us[2][5][8] = {};  // measured average duration per variant (0: not measured)
   long ncell() const { return long(nx) * ny * nz; }
-  long t1_elems() const { return 3L * nz * ny * LX; }
-  long t2_elems() const { return 3L * nz * LY * LX; }
-  long spec_elems() const { return 6L * (LZ / 2 + 1) * (LY / 2 + 1) * LX; }
+  long t1_elems() const { return 3L * LZ * ny * nx; }
+  long t2_elems() const { return 3L * LZ * LY * nx; }
+  long spec_elems() const { return 6L * (LZ / 2 + 1) * (LY / 2 + 1) * (LX / 2 + 1); }
   int work(int prec, int batch);  // make sure work buffers hold `batch` problems
 };
 
@@ -78,7 +78,7 @@ struct ie_ctx_impl;
 // Fields in MvArgs that are geometry (sizes, ghat, tw) are filled in by the launcher; the padded
 // work buffers are the plan's own unless the caller sets both a.T1 and a.T2 (one problem, at
 // least t1_elems()/t2_elems() values each), in which case nothing is allocated.
-// only >= 0 launches that pass alone (0 xfwd, 1 yfwd, 2 zconv, 3 yinv, 4 xinv); vover >= 0
+// only >= 0 launches that pass alone (0 zfwd, 1 yfwd, 2 xconv, 3 yinv, 4 zinv); vover >= 0
 // replaces the plan's variant (both for the autotuner).
 template <typename T>
 int launch_matvec(Plan& p, MvArgs<T> a, int batch, hipStream_t s, const cx<T>* tw, int only = -1,

@@ -73,67 +73,83 @@ int fft_len(int n) {
     }                                                                    \
   }
 
+// Calls F<T, L>::template go<V>(args...) for the plan's variant v of a pass with four.
+#define IE_COL_VARIANTS(v, ...)                                          \
+  switch (v & 3) {                                                       \
+    case 1: return go<1>(__VA_ARGS__);                                   \
+    case 2: return go<2>(__VA_ARGS__);                                   \
+    case 3: return go<3>(__VA_ARGS__);                                   \
+    default: return go<0>(__VA_ARGS__);                                  \
+  }
+
+// number of source planes of an operator application
+template <typename T>
+static int source_planes(const MvArgs<T>& a) {
+  const int z0 = std::max(a.src_z0, 0), z1 = std::min(a.src_z1, a.nz);
+  int zs = std::max(0, z1 - z0);
+  zs -= std::max(0, std::min(a.hole_z1, z1) - std::max(a.hole_z0, z0));
+  return zs;
+}
+
 template <typename T, int L>
-struct XfwdL {
+struct ZfwdL {
   template <int V>
   static int go(const MvArgs<T>& a, int batch, hipStream_t s) {
-    using G = Geo<T, L, V>;
-    const long rows = long(a.nz) * a.ny;
-    dim3 grid(ceil_div(rows, G::NL), 1, batch);
-    const int z0 = std::max(a.src_z0, 0), z1 = std::min(a.src_z1, a.nz);
-    constexpr int threads = G::NL * G::TLR;
-    int zs = std::max(0, z1 - z0);
-    zs -= std::max(0, std::min(a.hole_z1, z1) - std::max(a.hole_z0, z0));
+    using G = GeoC<T, L, V>;
+    const long plane = long(a.ny) * a.nx;
+    dim3 grid(ceil_div(plane, G::W), 1, batch);
     const double cs = sizeof(cx<T>), rs = sizeof(T);
-    const double by = double(batch) * (double(zs) * a.ny * a.nx * (3 * cs + (a.M ? 6 * rs : 0)) +
-                                       double(rows) * L * 3 * cs);
-    ProfScope ps(s, "xfwd", shape_tag(int(cs), a.LX, a.LY, a.LZ, a.nz, batch).c_str(), by);
-    hipLaunchKernelGGL((k_xfwd<T, L, V>), grid, dim3(threads), 0, s, a);
+    const double by = double(batch) * (double(source_planes(a)) * plane *
+                                       (3 * cs + (a.M ? 6 * rs : 0)) + double(L) * plane * 3 * cs);
+    ProfScope ps(s, "zfwd", shape_tag(int(cs), a.LX, a.LY, a.LZ, a.nz, batch).c_str(), by);
+    hipLaunchKernelGGL((k_zfwd<T, L, V>), grid, dim3(G::THREADS), 0, s, a);
     IE_LAUNCH_CHECK();
     return IE_OK;
   }
   static int run(int v, const MvArgs<T>& a, int batch, hipStream_t s) {
-    IE_ROW_VARIANTS(v, a, batch, s);
+    IE_COL_VARIANTS(v, a, batch, s);
   }
 };
 template <typename T, int L>
-struct XinvL {
+struct ZinvL {
   template <int V>
   static int go(const MvArgs<T>& a, int batch, hipStream_t s) {
-    using G = Geo<T, L, V>;
-    const long rows = long(a.out_z1 - a.out_z0) * a.ny;
-    dim3 grid(ceil_div(rows, G::NL), 1, batch);
+    using G = GeoC<T, L, V>;
+    const long plane = long(a.ny) * a.nx;
+    dim3 grid(ceil_div(plane, G::W), 1, batch);
     const double cs = sizeof(cx<T>), rs = sizeof(T);
     const bool ux = a.x && (a.a_x != T(0) || (a.M && a.a_m != T(0)));
     const bool um = a.M && a.a_m != T(0);
     const double per = 3 * cs + (ux ? 3 * cs : 0) + (um ? 6 * rs : 0) + (a.e ? 3 * cs : 0);
-    const double by = double(batch) * (double(rows) * L * 3 * cs + double(rows) * a.nx * per);
-    ProfScope ps(s, "xinv", shape_tag(int(cs), a.LX, a.LY, a.LZ, a.nz, batch).c_str(), by);
-    hipLaunchKernelGGL((k_xinv<T, L, V>), grid, dim3(G::NL * G::TLR), 0, s, a);
+    const double by = double(batch) * (double(L) * plane * 3 * cs +
+                                       double(a.out_z1 - a.out_z0) * plane * per);
+    ProfScope ps(s, "zinv", shape_tag(int(cs), a.LX, a.LY, a.LZ, a.nz, batch).c_str(), by);
+    hipLaunchKernelGGL((k_zinv<T, L, V>), grid, dim3(G::THREADS), 0, s, a);
+    IE_LAUNCH_CHECK();
+    return IE_OK;
+  }
+  static int run(int v, const MvArgs<T>& a, int batch, hipStream_t s) {
+    IE_COL_VARIANTS(v, a, batch, s);
+  }
+};
+template <typename T, int L>
+struct XconvL {
+  template <int V>
+  static int go(const MvArgs<T>& a, int batch, hipStream_t s) {
+    using G = GeoX<T, L, V>;
+    // x extent: the LY/2 + 1 stored rows in groups of NP, rounded up to a multiple of 8 XCDs
+    dim3 grid((ceil_div(a.LY / 2 + 1, G::NP) + 7) / 8 * 8, a.LZ, batch);
+    const double cs = sizeof(cx<T>);
+    // algorithmic bytes count the spectrum at its octant size (the unique values), read once
+    const double oct = 6.0 * (L / 2 + 1) * (a.LY / 2 + 1) * (a.LZ / 2 + 1);
+    const double by = double(batch) * 2.0 * a.LZ * a.LY * a.nx * 3 * cs + oct * cs;
+    ProfScope ps(s, "xconv", shape_tag(int(cs), a.LX, a.LY, a.LZ, a.nz, batch).c_str(), by);
+    hipLaunchKernelGGL((k_xconv<T, L, V>), grid, dim3(G::THREADS), 0, s, a);
     IE_LAUNCH_CHECK();
     return IE_OK;
   }
   static int run(int v, const MvArgs<T>& a, int batch, hipStream_t s) {
     IE_ROW_VARIANTS(v, a, batch, s);
-  }
-};
-template <typename T, int L>
-struct ZconvL {
-  template <int V>
-  static int go(const MvArgs<T>& a, int batch, hipStream_t s) {
-    using G = GeoZ<T, L, V>;
-    dim3 grid(ceil_div(a.LX, G::W), G::PAIR ? a.LY / 2 + 1 : a.LY, batch);
-    const double cs = sizeof(cx<T>);
-    // algorithmic bytes count the spectrum at its octant size (the unique values)
-    const double oct = 6.0 * (a.LX / 2 + 1) * (a.LY / 2 + 1) * (L / 2 + 1);
-    const double by = double(batch) * 3.0 * a.LY * a.LX * cs * (a.nz + (a.out_z1 - a.out_z0)) + oct * cs;
-    ProfScope ps(s, "zconv", shape_tag(int(cs), a.LX, a.LY, a.LZ, a.nz, batch).c_str(), by);
-    hipLaunchKernelGGL((k_zconv<T, L, V>), grid, dim3(G::W * G::TL), 0, s, a);
-    IE_LAUNCH_CHECK();
-    return IE_OK;
-  }
-  static int run(int v, const MvArgs<T>& a, int batch, hipStream_t s) {
-    IE_VARIANTS(v, a, batch, s);
   }
 };
 template <typename T, int L>
@@ -211,38 +227,35 @@ int launch_matvec(Plan& p, MvArgs<T> a, int batch, hipStream_t s, const cx<T>* t
     return fail(IE_EINVAL, "bad output plane range [%d, %d)", a.out_z0, a.out_z1);
   if (batch < 1 || batch > 65535) return fail(IE_EINVAL, "bad batch %d", batch);
 
-  // pass 1: contrast, pad, FFT along x
-  auto xf = [&]() -> int { IE_LEN_CASES(XfwdL, T, p.LX, vsel(0), a, batch, s); };
-  if (want(0)) IE_TRY(xf());
-  // pass 2: FFT along y (ny non-zero rows -> LY)
+  // pass 1: contrast on the source planes, pad, FFT along z (all three components per column)
+  auto zf = [&]() -> int { IE_LEN_CASES(ZfwdL, T, p.LZ, vsel(0), a, batch, s); };
+  if (want(0)) IE_TRY(zf());
+  // pass 2: FFT along y (ny non-zero rows -> LY) on every kz plane
   ColArgs c{};
-  c.ncols = p.LX;
-  c.nzp = p.nz;
+  c.ncols = p.nx;
+  c.nzp = p.LZ;
   c.z0 = 0;
-  c.in_cs = long(p.nz) * p.ny * p.LX;
-  c.in_zs = long(p.ny) * p.LX;
-  c.in_ls = p.LX;
-  c.out_cs = long(p.nz) * p.LY * p.LX;
-  c.out_zs = long(p.LY) * p.LX;
-  c.out_ls = p.LX;
+  c.in_cs = long(p.LZ) * p.ny * p.nx;
+  c.in_zs = long(p.ny) * p.nx;
+  c.in_ls = p.nx;
+  c.out_cs = long(p.LZ) * p.LY * p.nx;
+  c.out_zs = long(p.LY) * p.nx;
+  c.out_ls = p.nx;
   c.rows_in = p.ny;
   c.rows_out = p.LY;
   c.in_bs = a.T1_bs;
   c.out_bs = a.T2_bs;
   c.active = a.active;
   c.active_bs = a.active_bs;
-  auto col = [&](const cx<T>* in, cx<T>* out, const ColArgs& cc, int np, bool inv) -> int {
-    IE_LEN_CASES(ColL, T, p.LY, vsel(inv ? 3 : 1), in, out, cc, np, batch, inv, s, tw);
+  auto col = [&](const cx<T>* in, cx<T>* out, const ColArgs& cc, bool inv) -> int {
+    IE_LEN_CASES(ColL, T, p.LY, vsel(inv ? 3 : 1), in, out, cc, 3 * p.LZ, batch, inv, s, tw);
   };
-  if (want(1)) IE_TRY(col(a.T1, a.T2, c, 3 * p.nz, false));
-  // pass 3: FFT along z, tensor multiply with G^, inverse FFT along z
-  auto zc = [&]() -> int { IE_LEN_CASES(ZconvL, T, p.LZ, vsel(2), a, batch, s); };
-  if (want(2)) IE_TRY(zc());
-  // pass 4: inverse FFT along y on the kept planes (LY -> ny rows)
-  const int nzo = a.out_z1 - a.out_z0;
+  if (want(1)) IE_TRY(col(a.T1, a.T2, c, false));
+  // pass 3: FFT along x, tensor multiply with G^, inverse FFT along x (rows of every (ky, kz))
+  auto xc = [&]() -> int { IE_LEN_CASES(XconvL, T, p.LX, vsel(2), a, batch, s); };
+  if (want(2)) IE_TRY(xc());
+  // pass 4: inverse FFT along y (LY -> ny rows)
   ColArgs d = c;
-  d.nzp = nzo;
-  d.z0 = a.out_z0;
   d.in_cs = c.out_cs;
   d.in_zs = c.out_zs;
   d.in_ls = c.out_ls;
@@ -253,10 +266,10 @@ int launch_matvec(Plan& p, MvArgs<T> a, int batch, hipStream_t s, const cx<T>* t
   d.rows_out = p.ny;
   d.in_bs = a.T2_bs;
   d.out_bs = a.T1_bs;
-  if (want(3)) IE_TRY(col(a.T2, a.T1, d, 3 * nzo, true));
-  // pass 5: inverse FFT along x, crop, combine
-  auto xi = [&]() -> int { IE_LEN_CASES(XinvL, T, p.LX, vsel(4), a, batch, s); };
-  if (want(4)) IE_TRY(xi());
+  if (want(3)) IE_TRY(col(a.T2, a.T1, d, true));
+  // pass 5: inverse FFT along z, keep the output planes, combine
+  auto zi = [&]() -> int { IE_LEN_CASES(ZinvL, T, p.LZ, vsel(4), a, batch, s); };
+  if (want(4)) IE_TRY(zi());
   return IE_OK;
 }
 
@@ -317,7 +330,7 @@ static int tune_one(Plan& p, const cx<T>* tw, hipStream_t s, int8_t var[5],
   for (int pass = 0; pass < 5 && rc == IE_OK; ++pass) {
     float best = 0;
     var[pass] = 0;
-    const int nv = (pass == 0 || pass == 4) ? kRowVariants : kVariants;
+    const int nv = pass == 2 ? kRowVariants : kVariants;
     for (int v = 0; v < nv && rc == IE_OK; ++v) {
       rc = launch_matvec<T>(p, a, 1, s, tw, pass, v);
       if (rc != IE_OK) break;
@@ -459,17 +472,18 @@ struct RowL {
   }
 };
 
-// the stored part of the spectrum: all kx, ky <= LY/2, kz <= LZ/2 ([6][LZ/2+1][LY/2+1][LX])
-__global__ void k_halfspec(const c128* __restrict__ full, c128* __restrict__ o64,
-                           c64* __restrict__ o32, int LX, int LY, int LZ, double scale) {
-  const int hy = LY / 2 + 1, hz = LZ / 2 + 1;
-  const long n = 6L * LX * hy * hz;
+// the stored octant of the spectrum: kx <= LX/2, ky <= LY/2, kz <= LZ/2
+// ([6][LZ/2+1][LY/2+1][LX/2+1]); the other octants follow from the parity of each component
+__global__ void k_octspec(const c128* __restrict__ full, c128* __restrict__ o64,
+                          c64* __restrict__ o32, int LX, int LY, int LZ, double scale) {
+  const int hx = LX / 2 + 1, hy = LY / 2 + 1, hz = LZ / 2 + 1;
+  const long n = 6L * hx * hy * hz;
   const long idx = long(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= n) return;
-  const int ox = int(idx % LX);
-  const int oy = int((idx / LX) % hy);
-  const int oz = int((idx / (long(LX) * hy)) % hz);
-  const int c = int(idx / (long(LX) * hy * hz));
+  const int ox = int(idx % hx);
+  const int oy = int((idx / hx) % hy);
+  const int oz = int((idx / (long(hx) * hy)) % hz);
+  const int c = int(idx / (long(hx) * hy * hz));
   const long Lt = long(LX) * LY * LZ;
   const c128 v = scale * full[c * Lt + (long(oz) * LY + oy) * LX + ox];
   if (o64) o64[idx] = v;
@@ -531,7 +545,7 @@ int build_green(Plan& p, double h, const Medium& m, int prec_mask, const c128* t
     IE_TRY(p.ghat32.ensure(sizeof(c64) * no));
     o32 = p.ghat32.as<c64>();
   }
-  hipLaunchKernelGGL(k_halfspec, dim3(ceil_div(no, 256)), dim3(256), 0, s, full.as<c128>(), o64, o32,
+  hipLaunchKernelGGL(k_octspec, dim3(ceil_div(no, 256)), dim3(256), 0, s, full.as<c128>(), o64, o32,
                      p.LX, p.LY, p.LZ, 1.0 / double(Lt));
   IE_LAUNCH_CHECK();
   IE_HIP(hipStreamSynchronize(s));  // `full` is released on return

@@ -1,16 +1,20 @@
 // Kernels of the FFT-accelerated operator (eq. 10 with 2x zero padding), five passes:
 //
-//   xfwd : per-cell 3x3 contrast J = M x (eq. 3 integrand), zero-pad to LX, FFT along x
-//          -> T1[3][nz][ny][LX]
-//   yfwd : FFT along y of the ny non-zero rows, padded to LY          -> T2[3][nz][LY][LX]
-//   zconv: per (kx, ky) column, FFT along z of the nz non-zero planes, S^_p = sum_q G^_pq J^_q
-//          with the six stored components of G^ (G_pq = G_qp, each even or odd per axis; the
-//          half kept for ky <= LY/2, kz <= LZ/2 serves the row pair ky, LY - ky of one block),
-//          inverse FFT along z, keep the output planes                  -> T2 (in place)
-//   yinv : inverse FFT along y, keep ny rows                             -> T1
-//   xinv : inverse FFT along x, keep nx cells, combine
+//   zfwd : per-cell 3x3 contrast J = M x (eq. 3 integrand) on the source planes, zero-pad to
+//          LZ, FFT along z of all three components of a column       -> U1[3][LZ][ny][nx]
+//   yfwd : FFT along y of the ny non-zero rows, padded to LY          -> U2[3][LZ][LY][nx]
+//   xconv: per (ky, kz) row, FFT along x of the nx non-zero cells padded to LX,
+//          S^_p = sum_q G^_pq J^_q with the six stored components of G^ (G_pq = G_qp, each even
+//          or odd per axis, so one octant kx <= LX/2, ky <= LY/2, kz <= LZ/2 is stored and the
+//          row pair ky, LY - ky of one block share each value fetched), inverse FFT along x,
+//          keep nx cells                                                -> U2 (in place)
+//   yinv : inverse FFT along y, keep ny rows                             -> U1
+//   zinv : inverse FFT along z, keep the output planes, combine
 //          y = a_e e + a_x x - a_m (M x) + a_s S                          -> y
 //
+// The strided axes (z, y) are transformed by column passes that read and write whole 128-byte
+// row segments; the spectrum multiply sits in the pass along the contiguous axis, whose rows
+// and whose stored spectrum rows are read as whole contiguous lines.
 // 1 / (LX LY LZ) is folded into the stored G^.  Every kernel returns at once when the
 // problem's `active` flag is 0 (used to retire converged Krylov iterations without a host
 // round trip).  blockIdx.z indexes a batch of problems of the same shape; per-problem arrays
@@ -56,11 +60,11 @@ struct MvArgs {
   int M_zoff;
   int src_z0, src_z1;    // source planes outside [src_z0, src_z1) are zero
   int hole_z0, hole_z1;  // and so are planes inside [hole_z0, hole_z1)
-  // work
+  // work: T1 = U1[3][LZ][ny][nx], T2 = U2[3][LZ][LY][nx]
   cx<T>* T1;
   cx<T>* T2;
   long T1_bs, T2_bs;
-  const cx<T>* ghat;  // [6][LZ/2+1][LY/2+1][LX], scaled by 1/(LX LY LZ)
+  const cx<T>* ghat;  // [6][LZ/2+1][LY/2+1][LX/2+1], scaled by 1/(LX LY LZ)
   long ghat_bs;
   // output planes and combination
   int out_z0, out_z1;
@@ -83,12 +87,11 @@ __device__ __forceinline__ bool retired(const MvArgs<T>& a, int b) {
 
 // ---------------------------------------------------------------------------------------
 // launch geometry per (precision, length, variant)
-// Variant V (chosen per plan by the autotuner): bit 0 halves the values per thread of the column
-// passes (twice the threads per line, more waves in flight, one more LDS exchange) and doubles
-// those of the row passes (8 instead of 4: half the threads per line, one LDS exchange fewer,
-// 128-byte instead of 256-byte row segments per load); bit 1 doubles the columns per block of
-// the column passes (256-byte row segments) and the rows per block of the row passes.  Row
-// passes (x) have four more: V + 4 uses the LDS layout padded every 4 positions.
+// Variant V (chosen per plan by the autotuner): bit 0 halves the values per thread of the y
+// column passes (twice the threads per line, more waves in flight, one more LDS exchange) and
+// doubles those of the row pass (8 instead of 4: half the threads per line, one LDS exchange
+// fewer); bit 1 doubles the columns per block of the y column passes (256-byte row segments).
+// The row pass (x) has four more: V + 4 uses the LDS layout padded every 4 positions.
 // ---------------------------------------------------------------------------------------
 constexpr int kVariants = 4;
 constexpr int kRowVariants = 8;
@@ -127,63 +130,6 @@ __device__ __forceinline__ void tensor_apply(const T m[6], const cx<T> v[3], cx<
                  m[3] * v[0].im + m[1] * v[1].im + m[5] * v[2].im};
   out[2] = cx<T>{m[4] * v[0].re + m[5] * v[1].re + m[2] * v[2].re,
                  m[4] * v[0].im + m[5] * v[1].im + m[2] * v[2].im};
-}
-
-// ---------------------------------------------------------------------------------------
-// xfwd: contrast, pad, FFT along x.  Block: NL rows x TL threads; thread (row, t).
-// ---------------------------------------------------------------------------------------
-template <typename T, int LX, int V>
-__global__ void __launch_bounds__((Geo<T, LX, V>::NL * Geo<T, LX, V>::TLR))
-    k_xfwd(const MvArgs<T> a) {
-  using G = Geo<T, LX, V>;
-  constexpr int E = G::ER, TL = G::TLR, NL = G::NL;
-  __shared__ cx<T> lds[NL * G::LP];
-  const int b = blockIdx.z;
-  if (retired(a, b)) return;
-  const int t = threadIdx.x % TL;
-  const int line = threadIdx.x / TL;
-  const long row = long(blockIdx.x) * NL + line;  // (z, y) row
-  const long nrows = long(a.nz) * a.ny;
-  const bool live = row < nrows;
-  const int z = live ? int(row / a.ny) : 0;
-  const int yy = live ? int(row % a.ny) : 0;
-  const bool zero = !live || z < a.src_z0 || z >= a.src_z1 || (z >= a.hole_z0 && z < a.hole_z1);
-  const cx<T>* x = a.x + b * a.x_bs + (long(z - a.x_zoff) * a.ny + yy) * a.nx;
-  const T* M = a.M ? a.M + b * a.M_bs + (long(z - a.M_zoff) * a.ny + yy) * a.nx : nullptr;
-  const T xs = a.xscale ? T(a.xscale[b * a.xscale_bs]) : T(1);
-  cx<T> v[3][E];
-#pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int i = t + m * TL;
-    cx<T> xv[3] = {{0, 0}, {0, 0}, {0, 0}};
-    if (!zero && i < a.nx) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) xv[c] = xs * x[c * a.x_cs + i];
-    }
-    if (M != nullptr && !zero && i < a.nx) {
-      T mm[6];
-#pragma unroll
-      for (int c = 0; c < 6; ++c) mm[c] = M[c * a.M_cs + i];
-      cx<T> j3[3];
-      tensor_apply(mm, xv, j3);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) v[c][m] = j3[c];
-    } else {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) v[c][m] = xv[c];
-    }
-  }
-  const typename G::RowLds addr{line * G::LP};
-  cx<T>* out = a.T1 + b * a.T1_bs + (long(z) * a.ny + yy) * LX;
-  const long cs = long(a.nz) * a.ny * LX;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    fft_line<T, LX, E, false>(v[c], lds, addr, t, a.tw);
-    if (live) {
-#pragma unroll
-      for (int m = 0; m < E; ++m) store_stream(&out[c * cs + t + m * TL], v[c][m]);
-    }
-  }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -235,168 +181,128 @@ __global__ void __launch_bounds__((Geo<T, L, V>::W * Geo<T, L, V>::TL))
 }
 
 // ---------------------------------------------------------------------------------------
-// zconv: FFT along z, tensor multiply with G^, inverse FFT along z (in place in T2).
-// A block takes W kx-columns of one row ky, or (pair form) of the rows ky and LY - ky, so that
-// both use each spectrum value fetched once.  G^ is stored for all kx, ky <= LY/2 and
-// kz <= LZ/2 ([6][LZ/2+1][LY/2+1][LX]); mirrored ky and kz follow from the parity of each
-// component (xy odd in y, xz odd in z, yz odd in y and z).
+// z column passes: all three components of W adjacent columns (y, x) of the xy plane, so that
+// the per-cell tensors apply on load (zfwd) and on store (zinv).  Variants: V & 1 doubles the
+// values per thread (4 -> 8 complex128, 8 -> 16 complex64); V & 2 doubles the columns per block
+// (256-byte row segments).  The three lines go through the FFT stages in lockstep (twiddles
+// loaded once per stage) and through LDS one after the other.
 // ---------------------------------------------------------------------------------------
-// Variants: V & 2 selects the row pair form (else one row per block).  Values per thread:
-// V0 8 (complex64) / 4 (complex128), V1 twice that, V2 half of V0 (pair), V3 as V0 (pair).
-// Columns per block fill a 128-byte row segment within 1024 (pair: 512) threads per block.
 template <typename T, int L, int V = 0>
-struct GeoZ {
-  static constexpr bool PAIR = (V & 2) != 0;
+struct GeoC {
   static constexpr int Esm = sizeof(T) == 8 ? 4 : 8;
-  static constexpr int Edef = V == 1 ? 2 * Esm : (V == 2 ? Esm / 2 : Esm);
-  static constexpr int E = L < Edef ? L : Edef;
+  static constexpr int E1 = (V & 1) ? 2 * Esm : Esm;
+  static constexpr int E = L < E1 ? L : E1;
   static constexpr int TL = L / E;
-  static constexpr int Wc = 128 / int(sizeof(cx<T>));
+  static constexpr int Wc = (128 / int(sizeof(cx<T>))) * ((V & 2) ? 2 : 1);
   static constexpr int Wm = (64 / TL) > Wc ? (64 / TL) : Wc;
   static constexpr int Wl = (65536 / int(L * sizeof(cx<T>))) < 1 ? 1 : (65536 / int(L * sizeof(cx<T>)));
-  static constexpr int Tmax = PAIR ? 512 : 1024;  // the pair form needs more registers
-  static constexpr int Wt = (Tmax / TL) < 1 ? 1 : (Tmax / TL);
+  static constexpr int Wt = (1024 / TL) < 1 ? 1 : (1024 / TL);
   static constexpr int W1 = Wm < Wl ? Wm : Wl;
   static constexpr int W = W1 < Wt ? W1 : Wt;
-  static constexpr int ROWS = PAIR ? 2 : 1;
+  static constexpr int THREADS = W * TL;
 };
 
+template <typename T>
+__device__ __forceinline__ bool source_plane(const MvArgs<T>& a, int z) {
+  return z < a.nz && z >= a.src_z0 && z < a.src_z1 && !(z >= a.hole_z0 && z < a.hole_z1);
+}
+
+// zfwd: J = M x on the source planes (zero elsewhere), zero-padded to LZ, FFT along z.
 template <typename T, int LZ, int V>
-__global__ void __launch_bounds__((GeoZ<T, LZ, V>::W * GeoZ<T, LZ, V>::TL))
-    k_zconv(const MvArgs<T> a) {
-  using G = GeoZ<T, LZ, V>;
-  constexpr int E = G::E, TL = G::TL, W = G::W, R = G::ROWS;
+__global__ void __launch_bounds__((GeoC<T, LZ, V>::THREADS)) k_zfwd(const MvArgs<T> a) {
+  using G = GeoC<T, LZ, V>;
+  constexpr int E = G::E, TL = G::TL, W = G::W;
   __shared__ cx<T> lds[W * LZ];
   const int b = blockIdx.z;
   if (retired(a, b)) return;
   const int w = threadIdx.x % W;
   const int t = threadIdx.x / W;
-  const int kx = blockIdx.x * W + w;
-  // pair form: rows ky and LY - ky (one row when ky is 0 or LY/2); single form: row ky, in the
-  // launch order 0, LY/2, 1, LY-1, 2, LY-2, ... so that the two rows reading the same stored
-  // spectrum row run at the same time (their blocks are LX/W apart in launch order) and the
-  // second read finds the row in cache
-  const int hy = a.LY / 2;
-  const int by = blockIdx.y;
-  const int ky = G::PAIR ? by : (by < 2 ? by * hy : ((by & 1) ? a.LY - (by >> 1) : (by >> 1)));
-  const bool two = G::PAIR && ky != 0 && ky != hy;  // block-uniform
-  const int nr = two ? 2 : 1;
-  const int oy = ky > hy ? a.LY - ky : ky;            // stored row of G^
-  const T sy0 = ky > hy ? T(-1) : T(1);                // parity of the first row
-  const bool live = kx < a.LX;
-  const long ls = long(a.LY) * a.LX;  // z stride
-  const long cs = long(a.nz) * ls;
-  cx<T>* row[R];
-  row[0] = a.T2 + b * a.T2_bs + long(ky) * a.LX + kx;
-  if constexpr (R == 2) row[1] = a.T2 + b * a.T2_bs + long(two ? a.LY - ky : ky) * a.LX + kx;
-  cx<T> v[R][3][E];
+  const long plane = long(a.ny) * a.nx;
+  const long col = long(blockIdx.x) * W + w;
+  const bool live = col < plane;
+  const cx<T>* x = a.x + b * a.x_bs + col;
+  const T* M = a.M ? a.M + b * a.M_bs + col : nullptr;
+  const T xs = a.xscale ? T(a.xscale[b * a.xscale_bs]) : T(1);
+  cx<T> v[3][E];
 #pragma unroll
-  for (int r = 0; r < R; ++r)
+  for (int m = 0; m < E; ++m) {
+    const int z = t + m * TL;
+    cx<T> xv[3] = {{0, 0}, {0, 0}, {0, 0}};
+    const bool on = live && source_plane(a, z);
+    if (on) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) xv[c] = xs * x[c * a.x_cs + long(z - a.x_zoff) * plane];
+    }
+    if (M != nullptr && on) {
+      T mm[6];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) mm[q] = M[q * a.M_cs + long(z - a.M_zoff) * plane];
+      cx<T> j3[3];
+      tensor_apply(mm, xv, j3);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) v[c][m] = j3[c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) v[c][m] = xv[c];
+    }
+  }
+  fft_lines<T, LZ, E, false, 3>(v, lds, LdsInterleaved{W, w}, t, a.tw);
+  if (live) {
+    cx<T>* out = a.T1 + b * a.T1_bs + col;
+    const long cs = long(LZ) * plane;
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int m = 0; m < E; ++m) {
-        const int z = t + m * TL;
-        v[r][c][m] = (r < nr && live && z < a.nz) ? row[r][c * cs + z * ls] : cx<T>{0, 0};
-      }
-  const LdsInterleaved addr{W, w};
-  // all lines of the block in lockstep (twiddles loaded once per stage); a single row in the
-  // pair form transforms zeros in place of its missing mirror row
-  auto& lines = reinterpret_cast<cx<T>(&)[R * 3][E]>(v);
-  fft_lines<T, LZ, E, false, R * 3>(lines, lds, addr, t, a.tw);
-  const int hz = LZ / 2;
-  const long gzs = long(hy + 1) * a.LX;  // per kz
-  const long gcs = long(hz + 1) * gzs;   // per component
-  const cx<T>* gh = a.ghat + b * a.ghat_bs + long(oy) * a.LX + (live ? kx : 0);
-#pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int kz = t + m * TL;
-    const int oz = kz > hz ? LZ - kz : kz;
-    const T sz = kz > hz ? T(-1) : T(1);
-    const cx<T>* g = gh + oz * gzs;
-    const cx<T> gxx = g[0], gyy = g[gcs], gzz = g[2 * gcs];
-    const cx<T> gxy = g[3 * gcs];
-    const cx<T> gxz = sz * g[4 * gcs];
-    const cx<T> gyz = sz * g[5 * gcs];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const T sy = r == 0 ? sy0 : T(-1);  // the mirrored row flips the y-odd components
-      const cx<T> hxy = sy * gxy, hyz = sy * gyz;
-      const cx<T> j0 = v[r][0][m], j1 = v[r][1][m], j2 = v[r][2][m];
-      v[r][0][m] = gxx * j0 + hxy * j1 + gxz * j2;
-      v[r][1][m] = hxy * j0 + gyy * j1 + hyz * j2;
-      v[r][2][m] = gxz * j0 + hyz * j1 + gzz * j2;
-    }
-  }
-  fft_lines<T, LZ, E, true, R * 3>(lines, lds, addr, t, a.tw);
-  if (live) {
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if (r >= nr) break;
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int m = 0; m < E; ++m) {
-          const int z = t + m * TL;
-          if (z >= a.out_z0 && z < a.out_z1) store_stream(&row[r][c * cs + z * ls], v[r][c][m]);
-        }
-    }
+      for (int m = 0; m < E; ++m) store_stream(&out[c * cs + long(t + m * TL) * plane], v[c][m]);
   }
 }
 
-// ---------------------------------------------------------------------------------------
-// xinv: inverse FFT along x, crop, combine.  Rows (z, y) for z in [out_z0, out_z1).
-// ---------------------------------------------------------------------------------------
-template <typename T, int LX, int V>
-__global__ void __launch_bounds__((Geo<T, LX, V>::NL * Geo<T, LX, V>::TLR))
-    k_xinv(const MvArgs<T> a) {
-  using G = Geo<T, LX, V>;
-  constexpr int E = G::ER, TL = G::TLR, NL = G::NL;
-  __shared__ cx<T> lds[NL * G::LP];
+// zinv: inverse FFT along z, keep the output planes [out_z0, out_z1), combine
+// y = a_e e + a_x x - a_m (M x) + a_s S.
+template <typename T, int LZ, int V>
+__global__ void __launch_bounds__((GeoC<T, LZ, V>::THREADS)) k_zinv(const MvArgs<T> a) {
+  using G = GeoC<T, LZ, V>;
+  constexpr int E = G::E, TL = G::TL, W = G::W;
+  __shared__ cx<T> lds[W * LZ];
   const int b = blockIdx.z;
   if (retired(a, b)) return;
-  const int t = threadIdx.x % TL;
-  const int line = threadIdx.x / TL;
-  const long row = long(blockIdx.x) * NL + line;
-  const long nrows = long(a.out_z1 - a.out_z0) * a.ny;
-  const bool live = row < nrows;
-  const int z = live ? a.out_z0 + int(row / a.ny) : a.out_z0;
-  const int yy = live ? int(row % a.ny) : 0;
-  const cx<T>* in = a.T1 + b * a.T1_bs + (long(z) * a.ny + yy) * LX;
-  const long cs = long(a.nz) * a.ny * LX;
+  const int w = threadIdx.x % W;
+  const int t = threadIdx.x / W;
+  const long plane = long(a.ny) * a.nx;
+  const long col = long(blockIdx.x) * W + w;
+  const bool live = col < plane;
+  const cx<T>* in = a.T1 + b * a.T1_bs + (live ? col : 0);
+  const long cs = long(LZ) * plane;
   cx<T> v[3][E];
-  const typename G::RowLds addr{line * G::LP};
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
+  for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[c][m] = live ? in[c * cs + t + m * TL] : cx<T>{0, 0};
-    fft_line<T, LX, E, true>(v[c], lds, addr, t, a.tw);
-  }
+    for (int m = 0; m < E; ++m)
+      v[c][m] = live ? in[c * cs + long(t + m * TL) * plane] : cx<T>{0, 0};
+  fft_lines<T, LZ, E, true, 3>(v, lds, LdsInterleaved{W, w}, t, a.tw);
   if (!live) return;
-  const long cell = long(yy) * a.nx;
-  cx<T>* y = a.y + b * a.y_bs + long(z - a.y_zoff) * a.ny * a.nx + cell;
-  const cx<T>* x = a.x ? a.x + b * a.x_bs + long(z - a.x_zoff) * a.ny * a.nx + cell : nullptr;
-  const cx<T>* e = a.e ? a.e + b * a.e_bs + long(z - a.e_zoff) * a.ny * a.nx + cell : nullptr;
-  const T* M = (a.M && a.a_m != T(0)) ? a.M + b * a.M_bs + long(z - a.M_zoff) * a.ny * a.nx + cell
-                                       : nullptr;
+  cx<T>* y = a.y + b * a.y_bs + col;
+  const cx<T>* x = a.x ? a.x + b * a.x_bs + col : nullptr;
+  const cx<T>* e = a.e ? a.e + b * a.e_bs + col : nullptr;
+  const T* M = (a.M && a.a_m != T(0)) ? a.M + b * a.M_bs + col : nullptr;
   const T xs = a.xscale ? T(a.xscale[b * a.xscale_bs]) : T(1);
 #pragma unroll
   for (int m = 0; m < E; ++m) {
-    const int i = t + m * TL;
-    if (i >= a.nx) continue;
+    const int z = t + m * TL;
+    if (z < a.out_z0 || z >= a.out_z1) continue;
     cx<T> r[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) r[c] = a.a_s * v[c][m];
     if (x != nullptr && (a.a_x != T(0) || M != nullptr)) {
       cx<T> xv[3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) xv[c] = xs * x[c * a.x_cs + i];
+      for (int c = 0; c < 3; ++c) xv[c] = xs * x[c * a.x_cs + long(z - a.x_zoff) * plane];
 #pragma unroll
       for (int c = 0; c < 3; ++c) r[c] = r[c] + a.a_x * xv[c];
       if (M != nullptr) {
         T mm[6];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) mm[c] = M[c * a.M_cs + i];
+        for (int q = 0; q < 6; ++q) mm[q] = M[q * a.M_cs + long(z - a.M_zoff) * plane];
         cx<T> mx[3];
         tensor_apply(mm, xv, mx);
 #pragma unroll
@@ -405,10 +311,92 @@ __global__ void __launch_bounds__((Geo<T, LX, V>::NL * Geo<T, LX, V>::TLR))
     }
     if (e != nullptr) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) r[c] = r[c] + a.a_e * e[c * a.e_cs + i];
+      for (int c = 0; c < 3; ++c)
+        r[c] = r[c] + a.a_e * e[c * a.e_cs + long(z - a.e_zoff) * plane];
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) store_stream(&y[c * a.y_cs + i], r[c]);
+    for (int c = 0; c < 3; ++c) store_stream(&y[c * a.y_cs + long(z - a.y_zoff) * plane], r[c]);
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// xconv: per block the row pair (ky, LY - ky) of one kz (one row when ky is 0 or LY/2), each
+// row with its three components: FFT along x (nx cells zero-padded to LX), tensor multiply with
+// G^, inverse FFT, keep nx cells, in place in U2.  Both rows read the same stored spectrum row
+// (the second fetch is served by the CU's cache); kz runs in the order 0, LZ/2, 1, LZ-1, 2,
+// LZ-2, ... along blockIdx.y, and the grid's x extent is a multiple of 8, so the blocks of kz
+// and LZ - kz that read the same stored row run next to each other on the same XCD (blocks are
+// dealt to the eight XCDs in turn).  Thread layout and variants as the row geometry Geo, except
+// that V & 2 puts two row pairs (consecutive stored rows) in a block.
+// ---------------------------------------------------------------------------------------
+template <typename T, int LX, int V>
+struct GeoX {  // x pass: NP row pairs per block (V & 2: two), row geometry of Geo
+  static constexpr int NP = (V & 2) ? 2 : 1;
+  static constexpr int THREADS = 2 * NP * Geo<T, LX, V>::TLR;
+};
+
+template <typename T, int LX, int V>
+__global__ void __launch_bounds__((GeoX<T, LX, V>::THREADS)) k_xconv(const MvArgs<T> a) {
+  using G = Geo<T, LX, V>;
+  constexpr int E = G::ER, TL = G::TLR, NP = GeoX<T, LX, V>::NP;
+  __shared__ cx<T> lds[2 * NP * G::LP];
+  const int b = blockIdx.z;
+  if (retired(a, b)) return;
+  const int hx = LX / 2, hy = a.LY / 2, hz = a.LZ / 2;
+  const int t = threadIdx.x % TL;
+  const int rr = threadIdx.x / TL;  // row of the block: pair rr / 2, member rr % 2
+  const int r = rr & 1;             // 0: row ky = oy, 1: its mirror LY - oy
+  const int oy = blockIdx.x * NP + (rr >> 1);  // stored y row; rows beyond LY/2 pad the grid
+  const bool two = oy != 0 && oy != hy;
+  const bool live = oy <= hy && (r == 0 || two);
+  const int ky = r == 0 ? oy : a.LY - oy;
+  const int bz = blockIdx.y;
+  const int kz = bz < 2 ? bz * hz : ((bz & 1) ? a.LZ - (bz >> 1) : (bz >> 1));
+  const int oz = kz > hz ? a.LZ - kz : kz;
+  const T sy = r == 0 ? T(1) : T(-1);
+  const T sz = kz > hz ? T(-1) : T(1);
+  const long rs = long(a.LY) * a.nx;  // per kz
+  const long cs = long(a.LZ) * rs;    // per component
+  cx<T>* row = a.T2 + b * a.T2_bs + long(kz) * rs + long(ky) * a.nx;
+  cx<T> v[3][E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int i = t + m * TL;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c][m] = (live && i < a.nx) ? row[c * cs + i] : cx<T>{0, 0};
+  }
+  const typename G::RowLds addr{rr * G::LP};
+  // the three lines in lockstep: each stage's twiddles are loaded once
+  fft_lines<T, LX, E, false, 3>(v, lds, addr, t, a.tw);
+  const long gys = hx + 1;
+  const long gzs = long(hy + 1) * gys;
+  const long gcs = long(hz + 1) * gzs;
+  const cx<T>* gh = a.ghat + b * a.ghat_bs + long(oz) * gzs + long(live ? oy : 0) * gys;
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int kx = t + m * TL;
+    const int ox = kx > hx ? LX - kx : kx;
+    const T sx = kx > hx ? T(-1) : T(1);
+    const cx<T>* g = gh + ox;
+    const cx<T> gxx = g[0], gyy = g[gcs], gzz = g[2 * gcs];
+    const cx<T> gxy = (sx * sy) * g[3 * gcs];
+    const cx<T> gxz = (sx * sz) * g[4 * gcs];
+    const cx<T> gyz = (sy * sz) * g[5 * gcs];
+    const cx<T> j0 = v[0][m], j1 = v[1][m], j2 = v[2][m];
+    v[0][m] = gxx * j0 + gxy * j1 + gxz * j2;
+    v[1][m] = gxy * j0 + gyy * j1 + gyz * j2;
+    v[2][m] = gxz * j0 + gyz * j1 + gzz * j2;
+  }
+  fft_lines<T, LX, E, true, 3>(v, lds, addr, t, a.tw);
+  if (live) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int i = t + m * TL;
+      if (i < a.nx) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) store_stream(&row[c * cs + i], v[c][m]);
+      }
+    }
   }
 }
 

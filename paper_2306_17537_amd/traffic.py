@@ -15,7 +15,7 @@ summaries carry the same kind of line per kernel (``trace-json:``, average durat
 
 Usage (from the repository root, after the profiler runs):
     python -m paper_2306_17537_amd.traffic summarize --fetch DIR1 --write DIR2 \\
-        --kernel 'k_zconv<float, 128' --out profiles/NAME.md --command '...'
+        --kernel 'k_xconv<float, 128' --out profiles/NAME.md --command '...'
     python -m paper_2306_17537_amd.traffic stats --dir DIR --out profiles/NAME.md \\
         --command '...' [--top 20] [--extra TEXT]
 """
