@@ -373,9 +373,10 @@ int ie_receivers(ie_ctx* ctx, const double* sigma6, const ie_source* src, int32_
  *   IE_OPT_GRAPHS: 1 (default) replays each Krylov restart cycle as a captured hipGraph; 0 issues
  *                  every kernel launch directly (the launch profiler always uses direct launches).
  *   IE_OPT_AUTOTUNE: 1 (default) makes ie_green_setup time the launch variants of each FFT pass
- *                  (values per thread, columns or rows per block) on every grid it builds and keep
- *                  the fastest (cached per device, precision and grid for the process); 0 uses
- *                  the default variant.  Affects contexts set up afterwards.
+ *                  (values per thread, columns or rows per block) inside the whole operator on
+ *                  every grid it builds and keep the fastest (cached per device, precision and
+ *                  grid for the process); 0 uses the default variant.  Affects contexts set up
+ *                  afterwards.
  *   IE_OPT_FORCE_VARIANT: -1 (default) leaves the choice to the autotuner; 0 .. 7 puts every
  *                  pass of contexts set up afterwards on that variant (the column passes, which
  *                  have four variants, take it modulo 4): for tests that cover every variant.
@@ -393,7 +394,8 @@ int ie_set_option(int32_t option, int32_t value);
 
 /*
  * The autotuner's decisions for a context as JSON text in buf (HOST, len bytes): one object per
- * (grid, precision, pass) with the chosen variant and the measured microseconds per variant.
+ * (grid, precision, pass) with the chosen variant and, per variant of that pass, the measured
+ * microseconds of one whole operator application with the pass at that variant.
  * IE_EINVAL if buf is too small.
  */
 int ie_ctx_tuning(const ie_ctx* ctx, char* buf, int32_t len);

@@ -277,9 +277,10 @@ template int launch_matvec<double>(Plan&, MvArgs<double>, int, hipStream_t, cons
 template int launch_matvec<float>(Plan&, MvArgs<float>, int, hipStream_t, const c64*, int, int);
 
 // ---------------------------------------------------------------------------------------
-// Autotuner: every launch variant of every pass is timed (HIP events, one warm-up launch, then
-// the average of kReps launches) on the plan's own work buffers with zero inputs, and the
-// fastest is kept.  Results are cached per (device, precision, grid) for the process.
+// Autotuner: every launch variant of every pass is timed inside the whole operator (HIP events,
+// one warm-up application, then the average of kReps applications) on the plan's own work
+// buffers with zero inputs, and the fastest is kept.  Results are cached per (device, precision,
+// grid) for the process.
 // ---------------------------------------------------------------------------------------
 namespace {
 struct TuneEntry {
@@ -326,16 +327,22 @@ static int tune_one(Plan& p, const cx<T>* tw, hipStream_t s, int8_t var[5],
   hipEvent_t e0, e1;
   IE_HIP(hipEventCreate(&e0));
   IE_HIP(hipEventCreate(&e1));
+  // one sweep over the passes: each variant of a pass is timed inside the whole operator (the
+  // other passes at their current choice), so that every pass reads its input from wherever the
+  // previous pass left it, as in use
+  int8_t* pv = p.var[dbl ? 0 : 1];
+  for (int q = 0; q < 5; ++q) pv[q] = 0;
   int rc = IE_OK;
   for (int pass = 0; pass < 5 && rc == IE_OK; ++pass) {
     float best = 0;
-    var[pass] = 0;
+    int8_t keep = 0;
     const int nv = pass == 2 ? kRowVariants : kVariants;
     for (int v = 0; v < nv && rc == IE_OK; ++v) {
-      rc = launch_matvec<T>(p, a, 1, s, tw, pass, v);
+      pv[pass] = int8_t(v);
+      rc = launch_matvec<T>(p, a, 1, s, tw);
       if (rc != IE_OK) break;
       if (hipEventRecord(e0, s) != hipSuccess) rc = fail(IE_EDEVICE, "hipEventRecord failed");
-      for (int r = 0; r < kReps && rc == IE_OK; ++r) rc = launch_matvec<T>(p, a, 1, s, tw, pass, v);
+      for (int r = 0; r < kReps && rc == IE_OK; ++r) rc = launch_matvec<T>(p, a, 1, s, tw);
       if (rc != IE_OK) break;
       float ms = 0;
       if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -346,10 +353,12 @@ static int tune_one(Plan& p, const cx<T>* tw, hipStream_t s, int8_t var[5],
       us[pass][v] = 1e3f * ms / kReps;
       if (v == 0 || us[pass][v] < best) {
         best = us[pass][v];
-        var[pass] = int8_t(v);
+        keep = int8_t(v);
       }
     }
+    pv[pass] = keep;
   }
+  for (int q = 0; q < 5; ++q) var[q] = pv[q];
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return rc;

@@ -202,6 +202,17 @@ struct GeoC {
   static constexpr int THREADS = W * TL;
 };
 
+// Column block of a z pass for launch slot p of nb: the blocks that read the two halves of one
+// 128-byte line of the real per-cell tensor (W columns of 8-byte doubles, or of 4-byte floats
+// for complex64, are 64 bytes) get slots 8 apart, so they run on the same XCD (blocks are dealt
+// to the eight XCDs in turn) and its L2 fetches the line once.  A partial last group of 16
+// keeps its order.
+__device__ __forceinline__ long zcol_block(long p, long nb) {
+  const long g = p / 16, w = p % 16;
+  if ((g + 1) * 16 > nb) return p;
+  return g * 16 + (w % 8) * 2 + w / 8;
+}
+
 template <typename T>
 __device__ __forceinline__ bool source_plane(const MvArgs<T>& a, int z) {
   return z < a.nz && z >= a.src_z0 && z < a.src_z1 && !(z >= a.hole_z0 && z < a.hole_z1);
@@ -218,7 +229,7 @@ __global__ void __launch_bounds__((GeoC<T, LZ, V>::THREADS)) k_zfwd(const MvArgs
   const int w = threadIdx.x % W;
   const int t = threadIdx.x / W;
   const long plane = long(a.ny) * a.nx;
-  const long col = long(blockIdx.x) * W + w;
+  const long col = zcol_block(blockIdx.x, gridDim.x) * W + w;
   const bool live = col < plane;
   const cx<T>* x = a.x + b * a.x_bs + col;
   const T* M = a.M ? a.M + b * a.M_bs + col : nullptr;
@@ -269,7 +280,7 @@ __global__ void __launch_bounds__((GeoC<T, LZ, V>::THREADS)) k_zinv(const MvArgs
   const int w = threadIdx.x % W;
   const int t = threadIdx.x / W;
   const long plane = long(a.ny) * a.nx;
-  const long col = long(blockIdx.x) * W + w;
+  const long col = zcol_block(blockIdx.x, gridDim.x) * W + w;
   const bool live = col < plane;
   const cx<T>* in = a.T1 + b * a.T1_bs + (live ? col : 0);
   const long cs = long(LZ) * plane;
