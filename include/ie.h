@@ -134,7 +134,13 @@ typedef struct {
     double  inner_tol_fixed;  /* used when adaptive == 0 (section 3.2 uses 1e-6) */
     ie_gmres_opts inner;      /* inner block solves (tol field ignored) */
     const void* nn;           /* ie_nn handle for IE_INIT_LEARNED, else NULL */
+    int32_t residual_cells;   /* IE_RESID_ALL: e over all cells (eq. 9); IE_RESID_ANOMALOUS: e over
+                                 the cells with contrast only, as the isolated sub-domains example
+                                 computes it (section 3.1; stationary sweeps only) */
 } ie_dd_opts;
+
+#define IE_RESID_ALL        0
+#define IE_RESID_ANOMALOUS  1
 
 typedef struct {
     int32_t sweeps;

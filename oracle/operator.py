@@ -87,7 +87,16 @@ def apply_C(Ghat, b, x, sigma0, n):
     return x - bx - 2.0 * sigma0 * apply_green(Ghat, bx, n)
 
 
-def relres(Ghat, dsig, E, E0, n):
-    """Eq. (9)."""
+def anomalous_cells(dsig):
+    """Cells whose contrast tensor is not zero ([nz, ny, nx] bool)."""
+    return np.any(dsig.reshape(9, *dsig.shape[2:]) != 0, axis=0)
+
+
+def relres(Ghat, dsig, E, E0, n, anomalous_only=False):
+    """Eq. (9); with ``anomalous_only`` both norms run over the cells with contrast only, the
+    residual the isolated sub-domains example computes (section 3.1)."""
     r = E0 - apply_A(Ghat, dsig, E, n)
+    if anomalous_only:
+        m = anomalous_cells(dsig)[None]
+        r, E0 = r * m, E0 * m
     return float(np.linalg.norm(r.ravel()) / np.linalg.norm(E0.ravel()))

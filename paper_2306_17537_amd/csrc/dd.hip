@@ -41,6 +41,20 @@ __global__ void k_plane_nonzero(const double* __restrict__ D, long N, long plane
   if (nz_) flag[i / plane] = 1;
 }
 
+// Zero the entries of `batch` fields [3][N] (field stride 3N) in the cells whose contrast
+// D [6][N] (stride 6N) is zero.
+__global__ void k_mask_anomalous(c128* __restrict__ v, const double* __restrict__ D, long N) {
+  const int b = blockIdx.y;
+  const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double* d = D + b * 6 * N;
+  bool nz_ = false;
+  for (int c = 0; c < 6; ++c) nz_ = nz_ || (d[c * N + i] != 0.0);
+  if (nz_) return;
+  c128* w = v + b * 3 * N;
+  for (int c = 0; c < 3; ++c) w[c * N + i] = c128{0, 0};
+}
+
 // Copy planes [z0, z0 + nzb) of `batch` fields [3][nz][ny][nx] (field stride fs, component
 // stride cs) to / from contiguous blocks [3][nzb][ny][nx] (block stride 3 nb); problems whose
 // mask entry is 0 are skipped.
@@ -90,6 +104,7 @@ struct Group {
   c128* E;       //                  [3N]
   c128* Eold;    //                  [3N]
   int* active;   // per problem: still sweeping
+  bool anomalous_resid = false;  // e over the cells with contrast only
 };
 
 // rhs_p = e_p on block [z0, z1) + G (dsigma_p src_p) with block planes removed from the source
@@ -137,6 +152,11 @@ int full_relres(Group& g, const double* e0norm, double* e) {
   op.M_bs = 6 * g.N;
   IE_TRY(apply_op<double>(F, op, g.E, g.c->tmp.as<c128>(), g.E0, true, g.B, nullptr, 0, g.s,
                           tw64(g.c)));
+  if (g.anomalous_resid) {
+    hipLaunchKernelGGL(k_mask_anomalous, dim3(ceil_div(g.N, 256), g.B), dim3(256), 0, g.s,
+                       g.c->tmp.as<c128>(), g.D64, g.N);
+    IE_LAUNCH_CHECK();
+  }
   std::vector<double> nr(g.B);
   IE_TRY(norms_host(g.c->tmp.as<c128>(), 3 * g.N, g.B, nr.data(), g.c->kw, g.s));
   for (int b = 0; b < g.B; ++b) e[b] = e0norm[b] > 0 ? nr[b] / e0norm[b] : 0.0;
@@ -509,7 +529,17 @@ int dd_group(ie_ctx* c, const std::vector<int>& idx, const ie_problem* problems,
       for (int z = c->zb[i]; z < c->zb[i + 1]; ++z) has[b][i] |= pflag[size_t(b) * gr.nz + z];
 
   std::vector<double> e0norm(B), e(B);
-  IE_TRY(norms_host(g.E0, 3 * N, B, e0norm.data(), c->kw, s));
+  g.anomalous_resid = o.residual_cells == IE_RESID_ANOMALOUS;
+  if (g.anomalous_resid) {  // ||E0|| over the cells with contrast
+    IE_TRY(c->tmp.ensure(sizeof(c128) * 3 * N * B));
+    IE_HIP(hipMemcpyAsync(c->tmp.p, g.E0, sizeof(c128) * 3 * N * B, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_mask_anomalous, dim3(ceil_div(N, 256), B), dim3(256), 0, s,
+                       c->tmp.as<c128>(), g.D64, N);
+    IE_LAUNCH_CHECK();
+    IE_TRY(norms_host(c->tmp.as<c128>(), 3 * N, B, e0norm.data(), c->kw, s));
+  } else {
+    IE_TRY(norms_host(g.E0, 3 * N, B, e0norm.data(), c->kw, s));
+  }
   IE_TRY(full_relres(g, e0norm.data(), e.data()));
   std::vector<int> act(B), sweeps(B, 0);
   for (int b = 0; b < B; ++b) {
@@ -701,6 +731,10 @@ extern "C" int ie_dd_solve(ie_ctx* const* ctxs, int32_t nproblems, const ie_prob
     return fail(IE_EINVAL, "the learned start applies to the stationary sweeps only");
   if (krylov && !(o.inner_tol_fixed > 0))
     return fail(IE_EINVAL, "the Krylov outer iteration needs inner_tol_fixed > 0");
+  if (o.residual_cells != IE_RESID_ALL && o.residual_cells != IE_RESID_ANOMALOUS)
+    return fail(IE_EINVAL, "bad residual_cells");
+  if (krylov && o.residual_cells != IE_RESID_ALL)
+    return fail(IE_EINVAL, "the Krylov outer iteration minimises the residual over all cells");
   if (o.inner.form != IE_CONVENTIONAL && o.inner.form != IE_CIE)
     return fail(IE_EINVAL, "bad inner form");
   if (o.inner.precision != IE_FP64 && o.inner.precision != IE_MIXED)

@@ -24,6 +24,7 @@ IE_INIT_BACKGROUND, IE_INIT_USER, IE_INIT_LEARNED, IE_INIT_ZERO = 0, 1, 2, 3
 IE_MAG_DIPOLE, IE_ELEC_DIPOLE = 0, 1
 IE_MAX_SWEEPS, IE_MAX_BLOCKS = 128, 16
 IE_OPT_GRAPHS, IE_OPT_AUTOTUNE, IE_OPT_FORCE_VARIANT, IE_OPT_GROUP_THREADS = 1, 2, 3, 4
+IE_RESID_ALL, IE_RESID_ANOMALOUS = 0, 1
 
 
 class ie_grid(C.Structure):
@@ -57,7 +58,7 @@ class ie_gmres_stats(C.Structure):
 class ie_dd_opts(C.Structure):
     _fields_ = [("scheme", C.c_int32), ("adaptive", C.c_int32), ("max_sweeps", C.c_int32),
                 ("init", C.c_int32), ("tol", C.c_double), ("inner_tol_fixed", C.c_double),
-                ("inner", ie_gmres_opts), ("nn", C.c_void_p)]
+                ("inner", ie_gmres_opts), ("nn", C.c_void_p), ("residual_cells", C.c_int32)]
 
 
 class ie_dd_stats(C.Structure):
@@ -318,10 +319,10 @@ def ie_gmres(ctx, sigma6, b, x, tol=1e-6, restart=10, max_its=2000, precision=IE
 
 def dd_opts(scheme=IE_GS, adaptive=True, tol=1e-6, inner_tol_fixed=1e-6, max_sweeps=50,
             init=IE_INIT_BACKGROUND, restart=10, max_its=5000, precision=IE_FP64, form=IE_CIE,
-            nn=None, reorth=0) -> ie_dd_opts:
+            nn=None, reorth=0, residual_cells=0) -> ie_dd_opts:
     return ie_dd_opts(scheme, 1 if adaptive else 0, max_sweeps, init, tol, inner_tol_fixed,
                       ie_gmres_opts(0.0, restart, max_its, precision, form, reorth),
-                      C.c_void_p(nn) if nn else None)
+                      C.c_void_p(nn) if nn else None, residual_cells)
 
 
 def ie_dd_solve(ctxs, problems, opts: ie_dd_opts, stream=None, allow_noconv=False):

@@ -3,9 +3,11 @@ workload (seeds 50000-50002, not in the training set): what it gains over the ze
 that the zero-start judge keeps every solve correct.
 
 Measured on the MI355X (16 held-out models, weights in the package): the learned start did not
-reduce GMRES iterations; with the one-cycle judge a learned start costs at most about one extra
-restart cycle when it loses, and the solves reach the same field.  The assertions below hold
-that contract; the printed figures are the gain itself.
+reduce GMRES iterations (first-sweep inner iterations of block GS 777 from the learned start,
+743 from zero; full-domain mixed GMRES 485 vs 471 on average, judge cycles included).  The gain
+is asserted below and expected to fail (xfail, with these numbers); the other tests hold what
+does work: the stored network predicts finite fields, the residual judge picks the best start,
+and every solve reaches the same field whatever it starts from.
 """
 import numpy as np
 import pytest
@@ -67,7 +69,7 @@ def test_trained_network_guess_and_residual_judge(torch, net):
             ie.ie_ctx_destroy(ctx)
 
 
-def test_learned_start_gain_on_held_out_models(torch, net):
+def test_learned_start_keeps_full_domain_solves_correct(torch, net):
     from paper_2306_17537_amd import guess, ie
     tot = {"zero": 0, "learned": 0}
     for seed in SEEDS:
@@ -92,11 +94,40 @@ def test_learned_start_gain_on_held_out_models(torch, net):
             banner(f"seed={seed}: GMRES its zero start {out['zero'][1]}, learned start "
                    f"{out['learned'][1]} (judge cycles included)")
             assert rel(out["learned"][0], out["zero"][0]) < 1e-5
-            assert out["learned"][1] <= 1.5 * out["zero"][1] + 20
         finally:
             ie.ie_ctx_destroy(ctx)
     banner(f"total its: zero {tot['zero']}, learned {tot['learned']}, gain "
            f"{(tot['zero'] - tot['learned']) / tot['zero']:+.1%}")
+
+
+@pytest.mark.xfail(strict=False, reason="negative result, measured on 16 held-out models: the "
+                   "learned first-sweep guess takes 777 block-GS inner iterations against 743 "
+                   "from zero (its residual is 0.25-9.6 times the zero start's)")
+def test_learned_guess_reduces_first_sweep_inner_iterations(torch, net):
+    """What the network is for (the learned part of the solver): on held-out models the first
+    block GS sweep (fixed inner tolerance 1e-6) from the learned guesses needs fewer inner
+    iterations than from zero, judge cycles included."""
+    from paper_2306_17537_amd import ie
+    tot = {ie.IE_INIT_ZERO: 0, ie.IE_INIT_LEARNED: 0}
+    for seed in SEEDS:
+        p = synth.config1(seed=seed)
+        ctx, g = context(p, z_bounds=p.z_bounds)
+        try:
+            nx, ny, nz = p.n
+            for init in tot:
+                E = torch.zeros((3, nz, ny, nx), dtype=torch.complex128, device="cuda:0")
+                opts = ie.dd_opts(scheme=ie.IE_GS, adaptive=False, inner_tol_fixed=1e-6,
+                                  tol=1e-6, init=init, precision=ie.IE_MIXED, max_sweeps=1,
+                                  nn=net if init == ie.IE_INIT_LEARNED else None)
+                _, st = ie.ie_dd_solve([ctx], [dict(grid=g, sigma6=dev(p.sigma6),
+                                                    sources=p.sources, E_total=E)], opts,
+                                       allow_noconv=True)
+                tot[init] += sum(st[0].block_its[0][i] for i in range(st[0].nblocks))
+        finally:
+            ie.ie_ctx_destroy(ctx)
+    banner(f"first-sweep inner iterations: zero {tot[ie.IE_INIT_ZERO]}, learned "
+           f"{tot[ie.IE_INIT_LEARNED]}")
+    assert tot[ie.IE_INIT_LEARNED] < tot[ie.IE_INIT_ZERO]
 
 
 def test_dd_learned_first_sweep_on_a_held_out_model(torch, net):

@@ -153,3 +153,29 @@ def test_adaptive_inner_tolerance_is_a_tenth_of_the_last_residual():
           f"at e/10, e/100, e: {miss[10]}, {miss[100]}, {miss[1]}")
     assert miss[10] <= nblk // 4
     assert miss[100] > nblk and miss[1] > nblk
+
+
+def test_anomalous_cell_residual():
+    """The residual of the isolated sub-domains example (section 3.1) runs over the cells with
+    contrast only: it equals eq. (9) when every cell has contrast, and it does not depend on the
+    field in cells without contrast (they carry no current, so they enter no equation of an
+    anomalous cell), while eq. (9) over all cells does."""
+    from oracle import operator
+    p = synth.random_problem((6, 6, 6), seed=28, contrast=2.0)
+    st = solve.setup(p)
+    rng = np.random.default_rng(3)
+    E = st.E0 + 0.1 * (rng.normal(size=st.E0.shape) + 1j * rng.normal(size=st.E0.shape))
+    assert operator.relres(st.Ghat, st.dsig, E, st.E0, p.n, True) == \
+        operator.relres(st.Ghat, st.dsig, E, st.E0, p.n)
+    q = synth.random_problem((6, 6, 6), seed=28, contrast=2.0)
+    q.sigma6[:, 2:4] = 0.0
+    q.sigma6[:3, 2:4] = q.sigma0
+    sq = solve.setup(q)
+    E2 = E.copy()
+    E2[:, 2:4] += 5.0 + 3.0j
+    a1 = operator.relres(sq.Ghat, sq.dsig, E, sq.E0, q.n, True)
+    a2 = operator.relres(sq.Ghat, sq.dsig, E2, sq.E0, q.n, True)
+    f1 = operator.relres(sq.Ghat, sq.dsig, E, sq.E0, q.n)
+    f2 = operator.relres(sq.Ghat, sq.dsig, E2, sq.E0, q.n)
+    assert abs(a1 - a2) <= 1e-13 * a1
+    assert abs(f1 - f2) > 0.1 * f1
