@@ -623,31 +623,44 @@ def learned_bench(ie, torch, ctx, s6, p, ref):
 def batch_bench(ie, torch):
     """Logging run: 64 tool positions x 2 frequencies = 128 solves on tool-centred grids of
     three shapes, one block each (full-domain mixed GMRES), all in ONE ie_dd_solve call;
-    problems sharing (shape, frequency) are advanced as one batch (blockIdx.z)."""
+    problems sharing (shape, frequency) are advanced as one batch (blockIdx.z).  Run with the
+    default FFT lengths (3 * 2^k where shorter than the power of two) and again with powers of
+    two only."""
     import dataclasses
     import synth
     args = parse()
     probs = [dataclasses.replace(p, z_bounds=(0, p.n[2])) for p in synth.config2()]
-    ctxs, grids = {}, {}
-    t0 = time.perf_counter()
-    for p in probs:
-        key = (p.n, p.freq)
-        if key not in ctxs:
-            g = ie.make_grid(p.n, p.h, p.origin)
-            ctxs[key] = ie.ie_green_setup(g, ie.ie_medium(p.sigma0, p.freq, 0.0), p.z_bounds)
-            grids[key] = g
-    torch.cuda.synchronize()
-    t_setup = time.perf_counter() - t0
     opts = ie.dd_opts(tol=1e-6, adaptive=False, inner_tol_fixed=5e-7, precision=ie.IE_MIXED,
                       max_its=5000, restart=CHOSEN_RESTART)
-    data = []
-    for p in probs:
-        key = (p.n, p.freq)
-        E = torch.zeros((3, p.n[2], p.n[1], p.n[0]), dtype=torch.complex128, device="cuda:0")
-        data.append((ctxs[key], dict(grid=grids[key], sigma6=torch.from_numpy(p.sigma6).cuda(),
-                                     sources=p.sources, E_total=E)))
 
-    def run(sel):
+    def build(pow2):
+        ctxs, grids = {}, {}
+        ie.ie_set_option(ie.IE_OPT_FFT_LENGTHS, pow2)
+        try:
+            t0 = time.perf_counter()
+            for p in probs:
+                key = (p.n, p.freq)
+                if key not in ctxs:
+                    g = ie.make_grid(p.n, p.h, p.origin)
+                    ctxs[key] = ie.ie_green_setup(g, ie.ie_medium(p.sigma0, p.freq, 0.0),
+                                                  p.z_bounds)
+                    grids[key] = g
+            torch.cuda.synchronize()
+            t_setup = time.perf_counter() - t0
+        finally:
+            ie.ie_set_option(ie.IE_OPT_FFT_LENGTHS, 0)
+        data = []
+        for p in probs:
+            key = (p.n, p.freq)
+            E = torch.zeros((3, p.n[2], p.n[1], p.n[0]), dtype=torch.complex128,
+                            device="cuda:0")
+            data.append((ctxs[key], dict(grid=grids[key],
+                                         sigma6=torch.from_numpy(p.sigma6).cuda(),
+                                         sources=p.sources, E_total=E)))
+        lengths = sorted({(k[0], tuple(ie.ie_ctx_tuning(c)[0]["fft"])) for k, c in ctxs.items()})
+        return ctxs, data, t_setup, {f"{n[0]}x{n[1]}x{n[2]}": list(L) for n, L in lengths}
+
+    def run(data, sel):
         torch.cuda.synchronize()
         t = time.perf_counter()
         _, st = ie.ie_dd_solve([data[i][0] for i in sel], [data[i][1] for i in sel], opts)
@@ -655,16 +668,26 @@ def batch_bench(ie, torch):
         return time.perf_counter() - t, st
 
     allsel = list(range(len(probs)))
-    run(allsel[:12])  # warm-up of every kernel shape
+    ctxs, data, t_setup, lengths = build(0)
+    run(data, allsel[:12])  # warm-up of every kernel shape
     log("logging run: 128 solves in one call")
-    t_all, st = run(allsel)
+    t_all, st = run(data, allsel)
     mv = sum(s.matvecs32 + s.matvecs64 for s in st)
     worst = max(s.relres[s.sweeps] for s in st)
     nseq = min(args.batch_seq, len(probs))
-    t_seq = sum(run([i])[0] for i in range(nseq))
-    t_bat, _ = run(list(range(nseq)))
+    t_seq = sum(run(data, [i])[0] for i in range(nseq))
+    t_bat, _ = run(data, list(range(nseq)))
     for c in ctxs.values():
         ie.ie_ctx_destroy(c)
+    del data
+    log("logging run: powers-of-two FFT lengths")
+    ctxs2, data2, t_setup2, lengths2 = build(1)
+    run(data2, allsel[:12])
+    t_all2, st2 = run(data2, allsel)
+    mv2 = sum(s.matvecs32 + s.matvecs64 for s in st2)
+    for c in ctxs2.values():
+        ie.ie_ctx_destroy(c)
+    del data2
     out = dict(workload="config2: 64 positions x {400 kHz, 2 MHz} = 128 solves, grids "
                         "32^3 / 48x48x64 / 64x64x96 (seed 202), full-domain mixed "
                         f"GMRES({CHOSEN_RESTART}), "
@@ -672,9 +695,14 @@ def batch_bench(ie, torch):
                solves=len(probs), groups=len(ctxs), wall_s=round(t_all, 4),
                solves_per_s=round(len(probs) / t_all, 2), matvecs=mv,
                matvecs_per_s=round(mv / t_all, 1), worst_relres=worst,
-               green_setup_s=round(t_setup, 3),
+               green_setup_s=round(t_setup, 3), fft_lengths=lengths,
                subset=dict(problems=nseq, one_call_each_s=round(t_seq, 4),
-                           batched_s=round(t_bat, 4), speedup=round(t_seq / t_bat, 3)))
+                           batched_s=round(t_bat, 4), speedup=round(t_seq / t_bat, 3)),
+               pow2_lengths=dict(fft_lengths=lengths2, wall_s=round(t_all2, 4),
+                                 solves_per_s=round(len(probs) / t_all2, 2), matvecs=mv2,
+                                 worst_relres=max(s.relres[s.sweeps] for s in st2),
+                                 green_setup_s=round(t_setup2, 3),
+                                 speedup_of_default=round(t_all2 / t_all, 3)))
     log(f"batch: {out}")
     return out
 

@@ -390,18 +390,24 @@ int ie_receivers(ie_ctx* ctx, const double* sigma6, const ie_source* src, int32_
  *                  contexts at the same time (one host thread and one stream per context, joined
  *                  to the caller's stream); 0 solves the groups one after the other.  Results are
  *                  the same either way.
+ *   IE_OPT_FFT_LENGTHS: 0 (default) pads each axis of n cells to the shorter of the smallest
+ *                  power of two and the smallest 3 * 2^k (24 .. 768) that is >= 2n - 1 (the
+ *                  linear convolution of eq. 10 needs 2n - 1 points; 48 cells take 96, not 128);
+ *                  1 uses powers of two only.  Affects contexts set up afterwards.
  * Returns IE_EINVAL for an unknown option or value.
  */
 #define IE_OPT_GRAPHS 1
 #define IE_OPT_AUTOTUNE 2
 #define IE_OPT_FORCE_VARIANT 3
 #define IE_OPT_GROUP_THREADS 4
+#define IE_OPT_FFT_LENGTHS 5
 int ie_set_option(int32_t option, int32_t value);
 
 /*
  * The autotuner's decisions for a context as JSON text in buf (HOST, len bytes): one object per
- * (grid, precision, pass) with the chosen variant and, per variant of that pass, the measured
- * microseconds of one whole operator application with the pass at that variant.
+ * (grid, precision, pass) with the grid's FFT lengths ("fft": [LX, LY, LZ]), the chosen variant
+ * and, per variant of that pass, the measured microseconds of one whole operator application
+ * with the pass at that variant.
  * IE_EINVAL if buf is too small.
  */
 int ie_ctx_tuning(const ie_ctx* ctx, char* buf, int32_t len);

@@ -167,6 +167,11 @@ int ie_set_option(int32_t option, int32_t value) {
     g_group_threads = value != 0;
     return IE_OK;
   }
+  if (option == IE_OPT_FFT_LENGTHS) {
+    if (value != 0 && value != 1) return fail(IE_EINVAL, "IE_OPT_FFT_LENGTHS takes 0 or 1");
+    g_pow2_lengths = value != 0;
+    return IE_OK;
+  }
   return fail(IE_EINVAL, "unknown option %d", option);
 }
 
@@ -259,10 +264,12 @@ int ie_ctx_tuning(const ie_ctx* ctx, char* buf, int32_t len) {
         char t[384];
         const float* u = p.tune_us[pi][q];
         snprintf(t, sizeof(t),
-                 "%s{\"grid\": [%d, %d, %d], \"precision\": \"%s\", \"pass\": \"%s\", "
-                 "\"variant\": %d, \"us\": [%.2f, %.2f, %.2f, %.2f, %.2f, %.2f, %.2f, %.2f]}",
-                 o.size() > 1 ? ", " : "", p.nx, p.ny, p.nz, pi == 0 ? "c128" : "c64",
-                 pass_names[q], p.var[pi][q], u[0], u[1], u[2], u[3], u[4], u[5], u[6], u[7]);
+                 "%s{\"grid\": [%d, %d, %d], \"fft\": [%d, %d, %d], \"precision\": \"%s\", "
+                 "\"pass\": \"%s\", \"variant\": %d, "
+                 "\"us\": [%.2f, %.2f, %.2f, %.2f, %.2f, %.2f, %.2f, %.2f]}",
+                 o.size() > 1 ? ", " : "", p.nx, p.ny, p.nz, p.LX, p.LY, p.LZ,
+                 pi == 0 ? "c128" : "c64", pass_names[q], p.var[pi][q], u[0], u[1], u[2], u[3],
+                 u[4], u[5], u[6], u[7]);
         o += t;
       }
     }

@@ -74,9 +74,9 @@ int fail(int code, const char* fmt, ...);  // records the message, returns code
 
 inline int ceil_div(long a, long b) { return int((a + b - 1) / b); }
 
-// FFT twiddle table length: entries exp(-2 pi i k / TW_N); any power-of-two FFT length up to
-// TW_N reads its twiddles at stride TW_N / L.
-constexpr int TW_N = 1024;
+// FFT twiddle table length: entries exp(-2 pi i k / TW_N); every FFT length (2^k or 3 * 2^k up
+// to MAX_FFT_LEN) divides TW_N and reads its twiddles at stride TW_N / L.
+constexpr int TW_N = 3072;
 constexpr int MAX_FFT_LEN = 1024;
 
 // A field view: element (c, z, y, x) at p[c * cs + ((z - zoff) * ny + y) * nx + x].

@@ -61,7 +61,10 @@ struct Plan {
   int work(int prec, int batch);  // make sure work buffers hold `batch` problems
 };
 
-int fft_len(int n);  // power of two >= 2n - 1 (and >= 2)
+// FFT length for n cells: the shorter of the smallest power of two >= 2n - 1 and the smallest
+// 3 * 2^k >= 2n - 1 (k >= 3, at most 768); powers of two only when g_pow2_lengths is set
+int fft_len(int n);
+extern bool g_pow2_lengths;
 
 // Resolves, once per device, the address of the fixed scratch array of ie_matvec_noalloc
 // (called by ie_green_setup with the context's device current).

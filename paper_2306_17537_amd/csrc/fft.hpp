@@ -1,4 +1,4 @@
-// Register-resident Stockham FFT with LDS exchanges, for power-of-two lengths L <= 1024.
+// Register-resident Stockham FFT with LDS exchanges, for lengths L = 2^k or 3 * 2^k up to 1024.
 //
 // A line of length L is owned by TL = L / E threads; thread t holds the E values at the
 // natural positions t + m * TL (m = 0 .. E-1) before and after every stage.  A stage of radix
@@ -11,9 +11,11 @@
 // round trips and the first and last stages read/write global memory directly (coalesced:
 // consecutive t touch consecutive positions).
 //
-// Radix sequence: E, E, ..., then the remainder (< E) if L is not a power of E.
+// Radix sequence: per stage the largest divisor of E that divides what is left (E, E, ..., then
+// the remainder for powers of two; E is a multiple of 3 for the 3 * 2^k lengths).
 // Twiddles come from a float64 table of TW_N entries exp(-2 pi i k / TW_N) computed on the
-// host from the definition; the complex64 path uses the same table rounded to float.
+// host from the definition (TW_N is a multiple of every supported L); the complex64 path uses
+// the same table rounded to float.
 #pragma once
 
 #include <utility>
@@ -22,38 +24,46 @@
 
 namespace ie {
 
-// cos / sin of 2 pi k / 16
-__device__ constexpr double kC16[16] = {
-    1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
-    0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
-    -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
-    0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
-__device__ constexpr double kS16[16] = {
-    0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
-    1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
-    0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
-    -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173};
+// cos / sin of 2 pi k / 48 (every angle a radix of 2, 3, 4, 6, 8, 12 or 16 needs)
+__device__ constexpr double kC48[48] = {
+    1.0, 0.99144486137381041114, 0.96592582628906828675, 0.92387953251128675613,
+    0.86602540378443864676, 0.79335334029123516458, 0.70710678118654752440,
+    0.60876142900872063942, 0.5, 0.38268343236508977173, 0.25881904510252076235,
+    0.13052619222005159155, 0.0, -0.13052619222005159155, -0.25881904510252076235,
+    -0.38268343236508977173, -0.5, -0.60876142900872063942, -0.70710678118654752440,
+    -0.79335334029123516458, -0.86602540378443864676, -0.92387953251128675613,
+    -0.96592582628906828675, -0.99144486137381041114, -1.0, -0.99144486137381041114,
+    -0.96592582628906828675, -0.92387953251128675613, -0.86602540378443864676,
+    -0.79335334029123516458, -0.70710678118654752440, -0.60876142900872063942, -0.5,
+    -0.38268343236508977173, -0.25881904510252076235, -0.13052619222005159155, 0.0,
+    0.13052619222005159155, 0.25881904510252076235, 0.38268343236508977173, 0.5,
+    0.60876142900872063942, 0.70710678118654752440, 0.79335334029123516458,
+    0.86602540378443864676, 0.92387953251128675613, 0.96592582628906828675,
+    0.99144486137381041114};
 
-// x * W_R^K with W_R = exp(-+ 2 pi i / R) (minus for the forward transform); R <= 16.
+// x * W_R^K with W_R = exp(-+ 2 pi i / R) (minus for the forward transform); R divides 48.
 template <int K, int R, bool INV, typename T>
 __device__ __forceinline__ cx<T> mul_wr(cx<T> x) {
-  constexpr int k16 = ((K * 16) / R) & 15;
-  if constexpr (k16 == 0) {
+  static_assert(48 % R == 0, "radix must divide 48");
+  constexpr int k48 = ((K * 48) / R) % 48;
+  if constexpr (k48 == 0) {
     return x;
-  } else if constexpr (k16 == 4) {
+  } else if constexpr (k48 == 12) {
     return INV ? cx<T>{-x.im, x.re} : cx<T>{x.im, -x.re};
-  } else if constexpr (k16 == 8) {
+  } else if constexpr (k48 == 24) {
     return cx<T>{-x.re, -x.im};
-  } else if constexpr (k16 == 12) {
+  } else if constexpr (k48 == 36) {
     return INV ? cx<T>{x.im, -x.re} : cx<T>{-x.im, x.re};
   } else {
-    const T c = T(kC16[k16]);
-    const T s = INV ? T(kS16[k16]) : T(-kS16[k16]);
+    const T c = T(kC48[k48]);
+    const T sn = T(kC48[(k48 + 36) % 48]);  // sin(a) = cos(a - pi/2)
+    const T s = INV ? sn : -sn;
     return cx<T>{x.re * c - x.im * s, x.re * s + x.im * c};
   }
 }
 
-// In-register DFT of size R (power of two <= 16), recursive radix-2 decimation in time.
+// In-register DFT of size R: radix-2 decimation in time down to sizes 1 or 3, so R is a power
+// of two or three times one (R divides 48).
 template <typename T, int R, bool INV>
 struct Dft {
   template <int... K>
@@ -68,6 +78,7 @@ struct Dft {
         ...);
   }
   static __device__ __forceinline__ void run(cx<T>* u) {
+    static_assert(R % 2 == 0, "even radix expected");
     cx<T> e[R / 2], o[R / 2];
 #pragma unroll
     for (int i = 0; i < R / 2; ++i) {
@@ -83,6 +94,20 @@ template <typename T, bool INV>
 struct Dft<T, 1, INV> {
   static __device__ __forceinline__ void run(cx<T>*) {}
 };
+// size 3: X0 = a + b + c, X1,2 = a - (b + c)/2 -+ i (sqrt 3 / 2)(b - c) (forward; signs swap
+// for the inverse)
+template <typename T, bool INV>
+struct Dft<T, 3, INV> {
+  static __device__ __forceinline__ void run(cx<T>* u) {
+    constexpr T h = T(0.86602540378443864676);  // sqrt(3)/2
+    const cx<T> a = u[0], t1 = u[1] + u[2], t2 = u[1] - u[2];
+    const cx<T> m = {a.re - T(0.5) * t1.re, a.im - T(0.5) * t1.im};
+    const cx<T> r = INV ? cx<T>{-h * t2.im, h * t2.re} : cx<T>{h * t2.im, -h * t2.re};
+    u[0] = a + t1;
+    u[1] = m + r;
+    u[2] = m - r;
+  }
+};
 
 template <typename T, bool INV>
 __device__ __forceinline__ cx<T> twiddle(const cx<T>* __restrict__ tw, int idx) {
@@ -93,18 +118,26 @@ __device__ __forceinline__ cx<T> twiddle(const cx<T>* __restrict__ tw, int idx) 
 
 constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
 
+// Radix of the next stage for `rem` points still to combine: the largest divisor of the register
+// width E that divides rem (E, E, ..., then the remainder for powers of two; for 3 * 2^k lengths
+// the factor 3 goes into the first stage).
+constexpr int pick_radix(int rem, int E) {
+  for (int d = E; d >= 2; --d)
+    if (E % d == 0 && rem % d == 0) return d;
+  return 1;
+}
 // Radix of stage s for length L, register width E.
 template <int L, int E>
 constexpr int stage_radix(int s) {
   int rem = L;
-  for (int i = 0; i < s; ++i) rem /= (rem >= E ? E : rem);
-  return rem >= E ? E : rem;
+  for (int i = 0; i < s; ++i) rem /= pick_radix(rem, E);
+  return pick_radix(rem, E);
 }
 template <int L, int E>
 constexpr int num_stages() {
   int rem = L, k = 0;
   while (rem > 1) {
-    rem /= (rem >= E ? E : rem);
+    rem /= pick_radix(rem, E);
     ++k;
   }
   return k;
@@ -149,7 +182,7 @@ __device__ __forceinline__ void fft_stage(cx<T> (&v)[E], cx<T>* __restrict__ lds
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int j = t + b * TL;
-    const int k = j & (NS - 1);
+    const int k = j % NS;
     cx<T> u[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) u[r] = v[b + r * NB];
@@ -169,7 +202,7 @@ __device__ __forceinline__ void fft_stage(cx<T> (&v)[E], cx<T>* __restrict__ lds
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       const int j = t + b * TL;
-      const int k = j & (NS - 1);
+      const int k = j % NS;
       const int base = (j / NS) * NS * R + k;
 #pragma unroll
       for (int r = 0; r < R; ++r) lds[addr(base + r * NS)] = out[b + r * NB];
@@ -215,7 +248,7 @@ __device__ __forceinline__ void fft_stage_multi(cx<T> (&v)[NC][E], cx<T>* __rest
     constexpr int step = TW_N / (NS * R);
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      const int k = (t + b * TL) & (NS - 1);
+      const int k = (t + b * TL) % NS;
 #pragma unroll
       for (int r = 1; r < R; ++r) w[b][r] = twiddle<T, INV>(tw, r * k * step);
     }
@@ -243,7 +276,7 @@ __device__ __forceinline__ void fft_stage_multi(cx<T> (&v)[NC][E], cx<T>* __rest
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const int j = t + b * TL;
-        const int k = j & (NS - 1);
+        const int k = j % NS;
         const int base = (j / NS) * NS * R + k;
 #pragma unroll
         for (int r = 0; r < R; ++r) lds[addr(base + r * NS)] = out[b + r * NB];

@@ -21,24 +21,36 @@ static std::string shape_tag(int esz, int LX, int LY, int LZ, int nz, int batch)
   return b;
 }
 
+bool g_pow2_lengths = false;
+
 int fft_len(int n) {
   int L = 2;
   while (L < 2 * n - 1) L *= 2;
-  return L;
+  if (g_pow2_lengths) return L;
+  // 3 * 2^k from 24 up when it is the shorter admissible length
+  int L3 = 24;
+  while (L3 < 2 * n - 1) L3 *= 2;
+  return (L3 < L && L3 <= 768) ? L3 : L;
 }
 
-// Calls F<T, L>::run(args...) for the power-of-two length L.
+// Calls F<T, L>::run(args...) for the FFT length L (2^k, or 3 * 2^k from 24).
 #define IE_LEN_CASES(F, T, L, ...)                      \
   switch (L) {                                          \
     case 2: return F<T, 2>::run(__VA_ARGS__);           \
     case 4: return F<T, 4>::run(__VA_ARGS__);           \
     case 8: return F<T, 8>::run(__VA_ARGS__);           \
     case 16: return F<T, 16>::run(__VA_ARGS__);         \
+    case 24: return F<T, 24>::run(__VA_ARGS__);         \
     case 32: return F<T, 32>::run(__VA_ARGS__);         \
+    case 48: return F<T, 48>::run(__VA_ARGS__);         \
     case 64: return F<T, 64>::run(__VA_ARGS__);         \
+    case 96: return F<T, 96>::run(__VA_ARGS__);         \
     case 128: return F<T, 128>::run(__VA_ARGS__);       \
+    case 192: return F<T, 192>::run(__VA_ARGS__);       \
     case 256: return F<T, 256>::run(__VA_ARGS__);       \
+    case 384: return F<T, 384>::run(__VA_ARGS__);       \
     case 512: return F<T, 512>::run(__VA_ARGS__);       \
+    case 768: return F<T, 768>::run(__VA_ARGS__);       \
     case 1024: return F<T, 1024>::run(__VA_ARGS__);     \
     default: return fail(IE_EINVAL, "unsupported FFT length %d", L); \
   }
@@ -287,7 +299,7 @@ struct TuneEntry {
   int8_t var[5];
   float us[5][kRowVariants];
 };
-std::map<std::tuple<int, int, int, int, int>, TuneEntry> g_tune_cache;
+std::map<std::tuple<int, int, int, int, int, int, int, int>, TuneEntry> g_tune_cache;
 std::mutex g_tune_mu;
 constexpr int kReps = 5;
 }  // namespace
@@ -370,7 +382,7 @@ int autotune(Plan& p, int prec_mask, const c128* tw64, const c64* tw32, hipStrea
   for (int pi = 0; pi < 2; ++pi) {
     const bool dbl = pi == 0;
     if (!(prec_mask & (dbl ? IE_FP64 : IE_MIXED))) continue;
-    const auto key = std::make_tuple(dev, pi, p.nx, p.ny, p.nz);
+    const auto key = std::make_tuple(dev, pi, p.nx, p.ny, p.nz, p.LX, p.LY, p.LZ);
     {
       std::lock_guard<std::mutex> g(g_tune_mu);
       auto it = g_tune_cache.find(key);

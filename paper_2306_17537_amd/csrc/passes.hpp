@@ -93,6 +93,12 @@ __device__ __forceinline__ bool retired(const MvArgs<T>& a, int b) {
 // fewer); bit 1 doubles the columns per block of the y column passes (256-byte row segments).
 // The row pass (x) has four more: V + 4 uses the LDS layout padded every 4 positions.
 // ---------------------------------------------------------------------------------------
+// Register width of a length-L transform: for L = 3 * 2^k it is 12 (L itself when shorter), so
+// that one stage takes the factor 3 and the others radix 4 or 2; e2 otherwise.
+constexpr int reg_width(int L, int e2) {
+  return L % 3 == 0 ? (L < 12 ? L : 12) : (L < e2 ? L : e2);
+}
+
 constexpr int kVariants = 4;
 constexpr int kRowVariants = 8;
 
@@ -102,7 +108,7 @@ struct Geo {
   // row segment is one (V & 2: two) 128-byte line(s); at least 64 threads per block; LDS <= 64 KB
   static constexpr int Edef = sizeof(T) == 8 ? 8 : 16;
   static constexpr int E1 = L < Edef ? L : Edef;
-  static constexpr int E = ((V & 1) && E1 >= 4) ? E1 / 2 : E1;
+  static constexpr int E = L % 3 == 0 ? reg_width(L, 0) : (((V & 1) && E1 >= 4) ? E1 / 2 : E1);
   static constexpr int TL = L / E;
   static constexpr int Wc = (128 / int(sizeof(cx<T>))) * ((V & 2) ? 2 : 1);
   static constexpr int Wm = (64 / TL) > Wc ? (64 / TL) : Wc;
@@ -111,7 +117,7 @@ struct Geo {
   // row passes (x): ER values per thread, TLR threads per line, NL rows per block (~128 threads,
   // V & 2: ~256)
   static constexpr int ER1 = L < 4 ? L : 4;
-  static constexpr int ER = ((V & 1) && L >= 16) ? 2 * ER1 : ER1;
+  static constexpr int ER = L % 3 == 0 ? reg_width(L, 0) : (((V & 1) && L >= 16) ? 2 * ER1 : ER1);
   static constexpr int TLR = L / ER;
   static constexpr int NL0 = ((V & 2) ? 256 : 128) / TLR;
   static constexpr int NL = NL0 < 1 ? 1 : NL0;
@@ -191,7 +197,7 @@ template <typename T, int L, int V = 0>
 struct GeoC {
   static constexpr int Esm = sizeof(T) == 8 ? 4 : 8;
   static constexpr int E1 = (V & 1) ? 2 * Esm : Esm;
-  static constexpr int E = L < E1 ? L : E1;
+  static constexpr int E = reg_width(L, E1);
   static constexpr int TL = L / E;
   static constexpr int Wc = (128 / int(sizeof(cx<T>))) * ((V & 2) ? 2 : 1);
   static constexpr int Wm = (64 / TL) > Wc ? (64 / TL) : Wc;
@@ -341,8 +347,10 @@ __global__ void __launch_bounds__((GeoC<T, LZ, V>::THREADS)) k_zinv(const MvArgs
 // that V & 2 puts two row pairs (consecutive stored rows) in a block.
 // ---------------------------------------------------------------------------------------
 template <typename T, int LX, int V>
-struct GeoX {  // x pass: NP row pairs per block (V & 2: two), row geometry of Geo
-  static constexpr int NP = (V & 2) ? 2 : 1;
+struct GeoX {  // x pass: NP row pairs per block (V & 2: two; at least a wavefront), row geometry of Geo
+  static constexpr int NP0 = (V & 2) ? 2 : 1;
+  static constexpr int NPW = 32 / Geo<T, LX, V>::TLR;
+  static constexpr int NP = NP0 > NPW ? NP0 : NPW;
   static constexpr int THREADS = 2 * NP * Geo<T, LX, V>::TLR;
 };
 

@@ -24,6 +24,7 @@ IE_INIT_BACKGROUND, IE_INIT_USER, IE_INIT_LEARNED, IE_INIT_ZERO = 0, 1, 2, 3
 IE_MAG_DIPOLE, IE_ELEC_DIPOLE = 0, 1
 IE_MAX_SWEEPS, IE_MAX_BLOCKS = 128, 16
 IE_OPT_GRAPHS, IE_OPT_AUTOTUNE, IE_OPT_FORCE_VARIANT, IE_OPT_GROUP_THREADS = 1, 2, 3, 4
+IE_OPT_FFT_LENGTHS = 5
 IE_RESID_ALL, IE_RESID_ANOMALOUS = 0, 1
 
 

@@ -9,7 +9,11 @@ from tests.gpu_common import banner, context, dev, field_shape, host, rel
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(8, 8, 8), (5, 7, 3), (16, 12, 9), (1, 1, 1), (2, 3, 1), (33, 20, 17), (24, 40, 32)]
+# FFT lengths (default mode) span 2..64 and the 3 * 2^k lengths 24..768 on every axis:
+# (16, 12, 9) -> 32, 24, 24; (33, 20, 17) -> 96, 48, 48; (80, 6, 5) -> 192 along x;
+# (5, 150, 3) -> 384 along y; (3, 4, 300) -> 768 along z
+SHAPES = [(8, 8, 8), (5, 7, 3), (16, 12, 9), (1, 1, 1), (2, 3, 1), (33, 20, 17), (24, 40, 32),
+          (80, 6, 5), (5, 150, 3), (3, 4, 300)]
 
 
 def _rand(shape, seed):
@@ -206,19 +210,64 @@ def test_invalid_tensor_is_rejected(torch):
         ie.ie_ctx_destroy(ctx)
 
 
+def _fft_len(m, pow2):
+    """Padded length of an axis of m cells: the smallest power of two >= 2m - 1, or with
+    pow2 == 0 the smallest 3 * 2^k (24 .. 768) when that is shorter."""
+    L = 2
+    while L < 2 * m - 1:
+        L *= 2
+    L3 = 24
+    while L3 < 2 * m - 1:
+        L3 *= 2
+    return L if pow2 or L3 > min(L, 768) else L3
+
+
+def test_fft_length_modes_give_the_same_operator(torch):
+    """The same grid padded to 3 * 2^k lengths (96, 48, 48) and to powers of two (128, 64, 64):
+    both are exact linear convolutions (eq. 10), so the operators agree to rounding."""
+    from paper_2306_17537_amd import ie
+    n = (33, 20, 17)
+    p = synth.random_problem(n, seed=5, freq=4e5, contrast=10.0)
+    x = dev(_rand(field_shape(p), 2))
+    s6 = dev(p.sigma6)
+    ys = {}
+    for pow2 in (0, 1):
+        ie.ie_set_option(ie.IE_OPT_FFT_LENGTHS, pow2)
+        try:
+            ctx, _ = context(p)
+        finally:
+            ie.ie_set_option(ie.IE_OPT_FFT_LENGTHS, 0)
+        try:
+            assert ie.ie_ctx_tuning(ctx)[0]["fft"] == [_fft_len(m, pow2) for m in n]
+            for prec, dt in ((ie.IE_FP64, torch.complex128), (ie.IE_MIXED, torch.complex64)):
+                y = torch.zeros(field_shape(p), dtype=dt, device="cuda:0")
+                ie.ie_matvec(ctx, s6, x.to(dt), y, ie.IE_CIE, prec)
+                ys[pow2, prec] = host(y).astype(np.complex128)
+        finally:
+            ie.ie_ctx_destroy(ctx)
+    assert rel(ys[0, ie.IE_FP64], ys[1, ie.IE_FP64]) < 1e-13
+    assert rel(ys[0, ie.IE_MIXED], ys[1, ie.IE_MIXED]) < 2e-6
+    with pytest.raises(ie.IEError):
+        ie.ie_set_option(ie.IE_OPT_FFT_LENGTHS, 2)
+
+
+@pytest.mark.parametrize("pow2", [0, 1])
 @pytest.mark.parametrize("variant", range(8))
 @pytest.mark.parametrize("n", [(33, 20, 17), (64, 48, 40), (100, 30, 12)])
-def test_every_launch_variant_matches_oracle(torch, variant, n):
+def test_every_launch_variant_matches_oracle(torch, variant, n, pow2):
     """Every launch variant the autotuner can pick, forced on all passes (the x pass has eight,
-    the column passes four), on shapes whose FFT lengths span 32..256."""
+    the column passes four), on shapes whose FFT lengths span 24..256: with the default lengths
+    (96, 48, 48 / 128, 96, 96 / 256, 64, 24) and with powers of two only (32..256)."""
     from paper_2306_17537_amd import ie
-    banner(f"matvec variant={variant} n={n}")
+    banner(f"matvec variant={variant} n={n} pow2={pow2}")
     p = synth.random_problem(n, seed=sum(n) + variant, freq=2.0e6, contrast=3.0)
     ie.ie_set_option(ie.IE_OPT_FORCE_VARIANT, variant)
+    ie.ie_set_option(ie.IE_OPT_FFT_LENGTHS, pow2)
     try:
         ctx, _ = context(p)
     finally:
         ie.ie_set_option(ie.IE_OPT_FORCE_VARIANT, -1)
+        ie.ie_set_option(ie.IE_OPT_FFT_LENGTHS, 0)
     try:
         k0 = green.wavenumber(p.sigma0, p.freq)
         Ghat = green.kernel_spectrum(p.n, p.h, k0, p.sigma0)
@@ -237,5 +286,6 @@ def test_every_launch_variant_matches_oracle(torch, variant, n):
         tun = ie.ie_ctx_tuning(ctx)
         assert all(r["variant"] == (variant if r["pass"] == "xconv" else variant & 3)
                    for r in tun)
+        assert all(r["fft"] == [_fft_len(m, pow2) for m in n] for r in tun)
     finally:
         ie.ie_ctx_destroy(ctx)
