@@ -393,7 +393,9 @@ int ie_receivers(ie_ctx* ctx, const double* sigma6, const ie_source* src, int32_
  *   IE_OPT_FFT_LENGTHS: 0 (default) pads each axis of n cells to the shorter of the smallest
  *                  power of two and the smallest 3 * 2^k (24 .. 768) that is >= 2n - 1 (the
  *                  linear convolution of eq. 10 needs 2n - 1 points; 48 cells take 96, not 128);
- *                  1 uses powers of two only.  Affects contexts set up afterwards.
+ *                  1 uses powers of two only; 2 sets up both where they differ, times one
+ *                  operator application of each (after autotuning each) and keeps the faster
+ *                  (about twice the setup time).  Affects contexts set up afterwards.
  * Returns IE_EINVAL for an unknown option or value.
  */
 #define IE_OPT_GRAPHS 1
@@ -405,12 +407,29 @@ int ie_set_option(int32_t option, int32_t value);
 
 /*
  * The autotuner's decisions for a context as JSON text in buf (HOST, len bytes): one object per
- * (grid, precision, pass) with the grid's FFT lengths ("fft": [LX, LY, LZ]), the chosen variant
- * and, per variant of that pass, the measured microseconds of one whole operator application
- * with the pass at that variant.
+ * (grid, precision, pass) with the grid's FFT lengths ("fft": [LX, LY, LZ]), the operator
+ * microseconds of the shortest and the power-of-two lengths when IE_OPT_FFT_LENGTHS = 2 chose
+ * between them ("lengths_us", zeros otherwise), the chosen variant and, per variant of that
+ * pass, the measured microseconds of one whole operator application with the pass at that
+ * variant.
  * IE_EINVAL if buf is too small.
  */
 int ie_ctx_tuning(const ie_ctx* ctx, char* buf, int32_t len);
+
+/*
+ * The autotuner's process-wide cache as a file, so that later processes skip the timing:
+ * ie_tuning_save writes every entry measured or loaded so far to `path` (HOST string; the file
+ * is replaced) as a JSON array of objects {"arch": GPU architecture name, "precision": "c128" |
+ * "c64", "grid": [nx, ny, nz], "fft": [LX, LY, LZ], "variant": [5 launch variants: zfwd, yfwd,
+ * xconv, yinv, zinv], "us": [5 x 8 microseconds]}.  ie_tuning_load reads such a file and adds
+ * its entries to the cache (replacing entries with the same key); a context set up afterwards
+ * on a device of that architecture, for that grid, precision and FFT lengths, takes the stored
+ * variants without timing.  Neither call touches the GPU.  IE_EINVAL if the file cannot be
+ * opened or written, or (load) is not in this format or holds an out-of-range variant, grid or
+ * length; nothing is loaded from a file that fails.
+ */
+int ie_tuning_save(const char* path);
+int ie_tuning_load(const char* path);
 
 /* Description of the last error on this thread (never NULL). */
 const char* ie_last_error(void);

@@ -110,14 +110,14 @@ static int valid_grid(const ie_grid* g) {
   return IE_OK;
 }
 
-static std::unique_ptr<Plan> make_plan(int nx, int ny, int nz) {
+static std::unique_ptr<Plan> make_plan(int nx, int ny, int nz, bool pow2) {
   auto p = std::make_unique<Plan>();
   p->nx = nx;
   p->ny = ny;
   p->nz = nz;
-  p->LX = fft_len(nx);
-  p->LY = fft_len(ny);
-  p->LZ = fft_len(nz);
+  p->LX = fft_len(nx, pow2);
+  p->LY = fft_len(ny, pow2);
+  p->LZ = fft_len(nz, pow2);
   return p;
 }
 
@@ -132,11 +132,38 @@ bool g_group_threads = true;
 namespace {
 bool g_autotune = true;
 int g_force_variant = -1;
+int g_fft_lengths = 0;  // 0 shortest, 1 powers of two, 2 the faster of the two by timing
 
 // every pass of the plan on one variant (the x pass has eight, the column passes four)
 void force_variant(Plan& p, int v) {
   for (int pi = 0; pi < 2; ++pi)
     for (int q = 0; q < 5; ++q) p.var[pi][q] = int8_t(q == 2 ? v : (v & 3));
+}
+
+// Plan of one grid shape with its Green spectrum and launch variants, at the FFT lengths the
+// length mode asks for.
+int setup_plan(ie_ctx* c, int nx, int ny, int nz, hipStream_t s, std::unique_ptr<Plan>& out) {
+  auto build = [&](bool pow2, std::unique_ptr<Plan>& p) {
+    p = make_plan(nx, ny, nz, pow2);
+    IE_TRY(build_green(*p, c->grid.h, c->med, c->prec_mask, tw64(c), tw32(c), s));
+    if (g_force_variant >= 0)
+      force_variant(*p, g_force_variant);
+    else if (g_autotune)
+      IE_TRY(autotune(*p, c->prec_mask, tw64(c), tw32(c), s));
+    return IE_OK;
+  };
+  IE_TRY(build(g_fft_lengths == 1, out));
+  if (g_fft_lengths != 2) return IE_OK;
+  std::unique_ptr<Plan> q;
+  IE_TRY(build(true, q));
+  if (q->LX == out->LX && q->LY == out->LY && q->LZ == out->LZ) return IE_OK;
+  float a = 0, b = 0;
+  IE_TRY(operator_us(*out, c->prec_mask, tw64(c), tw32(c), s, a));
+  IE_TRY(operator_us(*q, c->prec_mask, tw64(c), tw32(c), s, b));
+  if (b < a) out = std::move(q);
+  out->len_us[0] = a;
+  out->len_us[1] = b;
+  return IE_OK;
 }
 }  // namespace
 
@@ -168,8 +195,8 @@ int ie_set_option(int32_t option, int32_t value) {
     return IE_OK;
   }
   if (option == IE_OPT_FFT_LENGTHS) {
-    if (value != 0 && value != 1) return fail(IE_EINVAL, "IE_OPT_FFT_LENGTHS takes 0 or 1");
-    g_pow2_lengths = value != 0;
+    if (value < 0 || value > 2) return fail(IE_EINVAL, "IE_OPT_FFT_LENGTHS takes 0, 1 or 2");
+    g_fft_lengths = value;
     return IE_OK;
   }
   return fail(IE_EINVAL, "unknown option %d", option);
@@ -230,22 +257,13 @@ int ie_green_setup(const ie_grid* grid, const ie_medium* medium, const ie_partit
     IE_HIP(hipMemcpy(c->tw64.p, t64.data(), sizeof(c128) * TW_N, hipMemcpyHostToDevice));
     IE_HIP(hipMemcpy(c->tw32.p, t32.data(), sizeof(c64) * TW_N, hipMemcpyHostToDevice));
   }
-  c->full = make_plan(grid->nx, grid->ny, grid->nz);
-  IE_TRY(build_green(*c->full, grid->h, m, precision_mask, tw64(c.get()), tw32(c.get()), s));
-  if (g_force_variant >= 0)
-    force_variant(*c->full, g_force_variant);
-  else if (g_autotune)
-    IE_TRY(autotune(*c->full, precision_mask, tw64(c.get()), tw32(c.get()), s));
+  IE_TRY(setup_plan(c.get(), grid->nx, grid->ny, grid->nz, s, c->full));
   if (partition != nullptr) {
     for (size_t i = 0; i + 1 < c->zb.size(); ++i) {
       const int nzb = c->zb[i + 1] - c->zb[i];
       if (c->blocks.count(nzb)) continue;
-      auto p = make_plan(grid->nx, grid->ny, nzb);
-      IE_TRY(build_green(*p, grid->h, m, precision_mask, tw64(c.get()), tw32(c.get()), s));
-      if (g_force_variant >= 0)
-        force_variant(*p, g_force_variant);
-      else if (g_autotune)
-        IE_TRY(autotune(*p, precision_mask, tw64(c.get()), tw32(c.get()), s));
+      std::unique_ptr<Plan> p;
+      IE_TRY(setup_plan(c.get(), grid->nx, grid->ny, nzb, s, p));
       c->blocks[nzb] = std::move(p);
     }
   }
@@ -264,12 +282,13 @@ int ie_ctx_tuning(const ie_ctx* ctx, char* buf, int32_t len) {
         char t[384];
         const float* u = p.tune_us[pi][q];
         snprintf(t, sizeof(t),
-                 "%s{\"grid\": [%d, %d, %d], \"fft\": [%d, %d, %d], \"precision\": \"%s\", "
+                 "%s{\"grid\": [%d, %d, %d], \"fft\": [%d, %d, %d], "
+                 "\"lengths_us\": [%.2f, %.2f], \"precision\": \"%s\", "
                  "\"pass\": \"%s\", \"variant\": %d, "
                  "\"us\": [%.2f, %.2f, %.2f, %.2f, %.2f, %.2f, %.2f, %.2f]}",
-                 o.size() > 1 ? ", " : "", p.nx, p.ny, p.nz, p.LX, p.LY, p.LZ,
-                 pi == 0 ? "c128" : "c64", pass_names[q], p.var[pi][q], u[0], u[1], u[2], u[3],
-                 u[4], u[5], u[6], u[7]);
+                 o.size() > 1 ? ", " : "", p.nx, p.ny, p.nz, p.LX, p.LY, p.LZ, p.len_us[0],
+                 p.len_us[1], pi == 0 ? "c128" : "c64", pass_names[q], p.var[pi][q], u[0], u[1],
+                 u[2], u[3], u[4], u[5], u[6], u[7]);
         o += t;
       }
     }
@@ -280,6 +299,16 @@ int ie_ctx_tuning(const ie_ctx* ctx, char* buf, int32_t len) {
   if (int(o.size()) + 1 > len) return fail(IE_EINVAL, "buffer needs %zu bytes", o.size() + 1);
   std::memcpy(buf, o.c_str(), o.size() + 1);
   return IE_OK;
+}
+
+int ie_tuning_save(const char* path) {
+  if (path == nullptr) return fail(IE_EINVAL, "path is NULL");
+  return tuning_save(path);
+}
+
+int ie_tuning_load(const char* path) {
+  if (path == nullptr) return fail(IE_EINVAL, "path is NULL");
+  return tuning_load(path);
 }
 
 int ie_ctx_destroy(ie_ctx* ctx) {

@@ -54,6 +54,9 @@ struct Plan {
   // set by the autotuner (0 when tuning is off)
   int8_t var[2][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
   float tune_us[2][5][8] = {};  // measured average duration per variant (0: not measured)
+  // operator microseconds (precisions of the context summed) of the two candidate length sets,
+  // shortest and powers of two, when the lengths were chosen by timing (0 otherwise)
+  float len_us[2] = {0, 0};
   long ncell() const { return long(nx) * ny * nz; }
   long t1_elems() const { return 3L * LZ * ny * nx; }
   long t2_elems() const { return 3L * LZ * LY * nx; }
@@ -61,10 +64,9 @@ struct Plan {
   int work(int prec, int batch);  // make sure work buffers hold `batch` problems
 };
 
-// FFT length for n cells: the shorter of the smallest power of two >= 2n - 1 and the smallest
-// 3 * 2^k >= 2n - 1 (k >= 3, at most 768); powers of two only when g_pow2_lengths is set
-int fft_len(int n);
-extern bool g_pow2_lengths;
+// FFT length for n cells: the smallest power of two >= 2n - 1 (pow2), else the shorter of that
+// and the smallest 3 * 2^k >= 2n - 1 (k >= 3, at most 768)
+int fft_len(int n, bool pow2);
 
 // Resolves, once per device, the address of the fixed scratch array of ie_matvec_noalloc
 // (called by ie_green_setup with the context's device current).
@@ -89,6 +91,13 @@ int launch_matvec(Plan& p, MvArgs<T> a, int batch, hipStream_t s, const cx<T>* t
 
 // Times every launch variant of every pass on the plan's own buffers and keeps the fastest.
 int autotune(Plan& p, int prec_mask, const c128* tw64, const c64* tw32, hipStream_t s);
+// Time of one operator application at the plan's current variants (precisions in the mask
+// summed).
+int operator_us(Plan& p, int prec_mask, const c128* tw64, const c64* tw32, hipStream_t s,
+                float& us);
+// The autotuner's cache as a JSON file (host only).
+int tuning_save(const char* path);
+int tuning_load(const char* path);
 
 // Green setup of one plan (both precisions as requested).
 int build_green(Plan& p, double h, const Medium& m, int prec_mask, const c128* tw64,

@@ -1,14 +1,18 @@
 // Operator-level launches: the five-pass FFT convolution (eq. 10), the precomputed spectrum of
 // the discretised Green's tensor (eqs. 5-7, section 2.2), the background field of point dipoles
 // and the per-cell contrast tensors (eq. 3 and the contraction form).
-#include <cmath>
 #include <algorithm>
+#include <cctype>
+#include <cmath>
 #include <complex>
-#include <string>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
+#include <vector>
 
 #include "ctx.hpp"
 #include "prof.hpp"
@@ -21,12 +25,10 @@ static std::string shape_tag(int esz, int LX, int LY, int LZ, int nz, int batch)
   return b;
 }
 
-bool g_pow2_lengths = false;
-
-int fft_len(int n) {
+int fft_len(int n, bool pow2) {
   int L = 2;
   while (L < 2 * n - 1) L *= 2;
-  if (g_pow2_lengths) return L;
+  if (pow2) return L;
   // 3 * 2^k from 24 up when it is the shorter admissible length
   int L3 = 24;
   while (L3 < 2 * n - 1) L3 *= 2;
@@ -291,78 +293,108 @@ template int launch_matvec<float>(Plan&, MvArgs<float>, int, hipStream_t, const 
 // ---------------------------------------------------------------------------------------
 // Autotuner: every launch variant of every pass is timed inside the whole operator (HIP events,
 // one warm-up application, then the average of kReps applications) on the plan's own work
-// buffers with zero inputs, and the fastest is kept.  Results are cached per (device, precision,
-// grid) for the process.
+// buffers with zero inputs, and the fastest is kept.  Results are cached per (GPU architecture,
+// precision, grid, FFT lengths) for the process, and can be saved to and loaded from a file.
 // ---------------------------------------------------------------------------------------
 namespace {
 struct TuneEntry {
   int8_t var[5];
   float us[5][kRowVariants];
 };
-std::map<std::tuple<int, int, int, int, int, int, int, int>, TuneEntry> g_tune_cache;
+using TuneKey = std::tuple<std::string, int, int, int, int, int, int, int>;
+std::map<TuneKey, TuneEntry> g_tune_cache;
 std::mutex g_tune_mu;
 constexpr int kReps = 5;
+
+int device_arch(std::string& arch) {
+  int dev = 0;
+  IE_HIP(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  IE_HIP(hipGetDeviceProperties(&prop, dev));
+  arch = prop.gcnArchName;
+  return IE_OK;
+}
+
+// The contraction-form operator on zero inputs over the plan's own work buffers, timed with HIP
+// events on stream s at the plan's current variants.
+template <typename T>
+struct OpTimer {
+  Plan& p;
+  const cx<T>* tw;
+  hipStream_t s;
+  DevBuf x, y, M;
+  MvArgs<T> a{};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  OpTimer(Plan& p_, const cx<T>* tw_, hipStream_t s_) : p(p_), tw(tw_), s(s_) {}
+  ~OpTimer() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  }
+  int init() {
+    constexpr bool dbl = sizeof(T) == 8;
+    IE_TRY(p.work(dbl ? IE_FP64 : IE_MIXED, 1));
+    const long N = p.ncell();
+    IE_TRY(x.ensure(sizeof(cx<T>) * 3 * N));
+    IE_TRY(y.ensure(sizeof(cx<T>) * 3 * N));
+    IE_TRY(M.ensure(sizeof(T) * 6 * N));
+    IE_HIP(hipMemsetAsync(x.p, 0, sizeof(cx<T>) * 3 * N, s));
+    IE_HIP(hipMemsetAsync(M.p, 0, sizeof(T) * 6 * N, s));
+    IE_HIP(hipMemsetAsync(dbl ? p.t1_64.p : p.t1_32.p, 0, sizeof(cx<T>) * p.t1_elems(), s));
+    IE_HIP(hipMemsetAsync(dbl ? p.t2_64.p : p.t2_32.p, 0, sizeof(cx<T>) * p.t2_elems(), s));
+    a.x = x.as<const cx<T>>();  // reads x and the contrast, writes y
+    a.x_cs = N;
+    a.x_bs = 3 * N;
+    a.M = M.as<const T>();
+    a.M_cs = N;
+    a.M_bs = 6 * N;
+    a.src_z0 = 0;
+    a.src_z1 = p.nz;
+    a.hole_z0 = a.hole_z1 = -1;
+    a.out_z0 = 0;
+    a.out_z1 = p.nz;
+    a.y = y.as<cx<T>>();
+    a.y_cs = N;
+    a.y_bs = 3 * N;
+    a.a_x = 1;
+    a.a_m = 1;
+    a.a_s = -1;
+    IE_HIP(hipEventCreate(&e0));
+    IE_HIP(hipEventCreate(&e1));
+    return IE_OK;
+  }
+  // one warm-up application, then the average of kReps
+  int time(float& us) {
+    IE_TRY(launch_matvec<T>(p, a, 1, s, tw));
+    IE_HIP(hipEventRecord(e0, s));
+    for (int r = 0; r < kReps; ++r) IE_TRY(launch_matvec<T>(p, a, 1, s, tw));
+    float ms = 0;
+    IE_HIP(hipEventRecord(e1, s));
+    IE_HIP(hipEventSynchronize(e1));
+    IE_HIP(hipEventElapsedTime(&ms, e0, e1));
+    us = 1e3f * ms / kReps;
+    return IE_OK;
+  }
+};
 }  // namespace
 
 template <typename T>
 static int tune_one(Plan& p, const cx<T>* tw, hipStream_t s, int8_t var[5],
                     float us[5][kRowVariants]) {
   constexpr bool dbl = sizeof(T) == 8;
-  IE_TRY(p.work(dbl ? IE_FP64 : IE_MIXED, 1));
-  const long N = p.ncell();
-  DevBuf x, y, M;
-  IE_TRY(x.ensure(sizeof(cx<T>) * 3 * N));
-  IE_TRY(y.ensure(sizeof(cx<T>) * 3 * N));
-  IE_TRY(M.ensure(sizeof(T) * 6 * N));
-  IE_HIP(hipMemsetAsync(x.p, 0, sizeof(cx<T>) * 3 * N, s));
-  IE_HIP(hipMemsetAsync(M.p, 0, sizeof(T) * 6 * N, s));
-  IE_HIP(hipMemsetAsync(dbl ? p.t1_64.p : p.t1_32.p, 0, sizeof(cx<T>) * p.t1_elems(), s));
-  IE_HIP(hipMemsetAsync(dbl ? p.t2_64.p : p.t2_32.p, 0, sizeof(cx<T>) * p.t2_elems(), s));
-  MvArgs<T> a{};  // the contraction-form operator: reads x and the contrast, writes y
-  a.x = x.as<const cx<T>>();
-  a.x_cs = N;
-  a.x_bs = 3 * N;
-  a.M = M.as<const T>();
-  a.M_cs = N;
-  a.M_bs = 6 * N;
-  a.src_z0 = 0;
-  a.src_z1 = p.nz;
-  a.hole_z0 = a.hole_z1 = -1;
-  a.out_z0 = 0;
-  a.out_z1 = p.nz;
-  a.y = y.as<cx<T>>();
-  a.y_cs = N;
-  a.y_bs = 3 * N;
-  a.a_x = 1;
-  a.a_m = 1;
-  a.a_s = -1;
-  hipEvent_t e0, e1;
-  IE_HIP(hipEventCreate(&e0));
-  IE_HIP(hipEventCreate(&e1));
+  OpTimer<T> tm(p, tw, s);
+  IE_TRY(tm.init());
   // one sweep over the passes: each variant of a pass is timed inside the whole operator (the
   // other passes at their current choice), so that every pass reads its input from wherever the
   // previous pass left it, as in use
   int8_t* pv = p.var[dbl ? 0 : 1];
   for (int q = 0; q < 5; ++q) pv[q] = 0;
-  int rc = IE_OK;
-  for (int pass = 0; pass < 5 && rc == IE_OK; ++pass) {
+  for (int pass = 0; pass < 5; ++pass) {
     float best = 0;
     int8_t keep = 0;
     const int nv = pass == 2 ? kRowVariants : kVariants;
-    for (int v = 0; v < nv && rc == IE_OK; ++v) {
+    for (int v = 0; v < nv; ++v) {
       pv[pass] = int8_t(v);
-      rc = launch_matvec<T>(p, a, 1, s, tw);
-      if (rc != IE_OK) break;
-      if (hipEventRecord(e0, s) != hipSuccess) rc = fail(IE_EDEVICE, "hipEventRecord failed");
-      for (int r = 0; r < kReps && rc == IE_OK; ++r) rc = launch_matvec<T>(p, a, 1, s, tw);
-      if (rc != IE_OK) break;
-      float ms = 0;
-      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-        rc = fail(IE_EDEVICE, "event timing failed");
-        break;
-      }
-      us[pass][v] = 1e3f * ms / kReps;
+      IE_TRY(tm.time(us[pass][v]));
       if (v == 0 || us[pass][v] < best) {
         best = us[pass][v];
         keep = int8_t(v);
@@ -371,18 +403,16 @@ static int tune_one(Plan& p, const cx<T>* tw, hipStream_t s, int8_t var[5],
     pv[pass] = keep;
   }
   for (int q = 0; q < 5; ++q) var[q] = pv[q];
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  return rc;
+  return IE_OK;
 }
 
 int autotune(Plan& p, int prec_mask, const c128* tw64, const c64* tw32, hipStream_t s) {
-  int dev = 0;
-  IE_HIP(hipGetDevice(&dev));
+  std::string arch;
+  IE_TRY(device_arch(arch));
   for (int pi = 0; pi < 2; ++pi) {
     const bool dbl = pi == 0;
     if (!(prec_mask & (dbl ? IE_FP64 : IE_MIXED))) continue;
-    const auto key = std::make_tuple(dev, pi, p.nx, p.ny, p.nz, p.LX, p.LY, p.LZ);
+    const TuneKey key{arch, pi, p.nx, p.ny, p.nz, p.LX, p.LY, p.LZ};
     {
       std::lock_guard<std::mutex> g(g_tune_mu);
       auto it = g_tune_cache.find(key);
@@ -402,6 +432,194 @@ int autotune(Plan& p, int prec_mask, const c128* tw64, const c64* tw32, hipStrea
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune_cache[key] = t;
   }
+  return IE_OK;
+}
+
+int operator_us(Plan& p, int prec_mask, const c128* tw64, const c64* tw32, hipStream_t s,
+                float& us) {
+  us = 0;
+  for (int pi = 0; pi < 2; ++pi) {
+    float t = 0;
+    if (!(prec_mask & (pi == 0 ? IE_FP64 : IE_MIXED))) continue;
+    if (pi == 0) {
+      OpTimer<double> tm(p, tw64, s);
+      IE_TRY(tm.init());
+      IE_TRY(tm.time(t));
+    } else {
+      OpTimer<float> tm(p, tw32, s);
+      IE_TRY(tm.init());
+      IE_TRY(tm.time(t));
+    }
+    us += t;
+  }
+  return IE_OK;
+}
+
+// ---- saving and loading the cache ----------------------------------------------------------
+// File format: a JSON array with one object per (architecture, precision, grid, FFT lengths):
+//   {"arch": "...", "precision": "c128"|"c64", "grid": [nx, ny, nz], "fft": [LX, LY, LZ],
+//    "variant": [5 ints], "us": [[8 numbers] x 5]}
+namespace {
+struct JsonIn {  // minimal reader for the format above
+  const std::string& t;
+  size_t i = 0;
+  explicit JsonIn(const std::string& s) : t(s) {}
+  void ws() {
+    while (i < t.size() && std::isspace(static_cast<unsigned char>(t[i]))) ++i;
+  }
+  bool eat(char c) {
+    ws();
+    if (i < t.size() && t[i] == c) {
+      ++i;
+      return true;
+    }
+    return false;
+  }
+  bool str(std::string& out) {
+    if (!eat('"')) return false;
+    out.clear();
+    while (i < t.size() && t[i] != '"') {
+      if (t[i] == '\\') return false;  // no escapes in this format
+      out += t[i++];
+    }
+    return eat('"');
+  }
+  bool num(double& v) {
+    ws();
+    const char* b = t.c_str() + i;
+    char* e = nullptr;
+    v = std::strtod(b, &e);
+    if (e == b) return false;
+    i += size_t(e - b);
+    return true;
+  }
+  bool ints(int* v, int n) {
+    if (!eat('[')) return false;
+    for (int k = 0; k < n; ++k) {
+      double d;
+      if ((k > 0 && !eat(',')) || !num(d) || d != double(int(d))) return false;
+      v[k] = int(d);
+    }
+    return eat(']');
+  }
+  bool nums(float* v, int n) {
+    if (!eat('[')) return false;
+    for (int k = 0; k < n; ++k) {
+      double d;
+      if ((k > 0 && !eat(',')) || !num(d)) return false;
+      v[k] = float(d);
+    }
+    return eat(']');
+  }
+};
+
+bool valid_len(int n, int L) {
+  return L >= 2 && L >= 2 * n - 1 && L <= MAX_FFT_LEN && (L == fft_len(n, true) || L == fft_len(n, false));
+}
+}  // namespace
+
+int tuning_save(const char* path) {
+  std::string o = "[";
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    for (const auto& kv : g_tune_cache) {
+      const auto& k = kv.first;
+      const TuneEntry& e = kv.second;
+      char t[320];
+      snprintf(t, sizeof(t),
+               "%s\n{\"arch\": \"%s\", \"precision\": \"%s\", \"grid\": [%d, %d, %d], "
+               "\"fft\": [%d, %d, %d], \"variant\": [%d, %d, %d, %d, %d], \"us\": [",
+               o.size() > 1 ? "," : "", std::get<0>(k).c_str(), std::get<1>(k) == 0 ? "c128" : "c64",
+               std::get<2>(k), std::get<3>(k), std::get<4>(k), std::get<5>(k), std::get<6>(k),
+               std::get<7>(k), e.var[0], e.var[1], e.var[2], e.var[3], e.var[4]);
+      o += t;
+      for (int q = 0; q < 5; ++q) {
+        o += q ? ", [" : "[";
+        for (int v = 0; v < kRowVariants; ++v) {
+          snprintf(t, sizeof(t), "%s%.9g", v ? ", " : "", double(e.us[q][v]));
+          o += t;
+        }
+        o += "]";
+      }
+      o += "]}";
+    }
+  }
+  o += "\n]\n";
+  FILE* f = std::fopen(path, "wb");
+  if (f == nullptr) return fail(IE_EINVAL, "cannot open %s for writing", path);
+  const bool ok = std::fwrite(o.data(), 1, o.size(), f) == o.size();
+  if (std::fclose(f) != 0 || !ok) return fail(IE_EINVAL, "cannot write %s", path);
+  return IE_OK;
+}
+
+int tuning_load(const char* path) {
+  FILE* f = std::fopen(path, "rb");
+  if (f == nullptr) return fail(IE_EINVAL, "cannot open %s", path);
+  std::string text;
+  char buf[4096];
+  size_t got;
+  while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
+  std::fclose(f);
+  JsonIn in(text);
+  std::vector<std::pair<TuneKey, TuneEntry>> entries;
+  if (!in.eat('[')) return fail(IE_EINVAL, "%s: expected a JSON array", path);
+  bool first = true;
+  while (!in.eat(']')) {
+    if (!first && !in.eat(',')) return fail(IE_EINVAL, "%s: expected ',' at byte %zu", path, in.i);
+    first = false;
+    std::string arch, prec;
+    int grid[3] = {0, 0, 0}, fft[3] = {0, 0, 0}, var[5] = {0, 0, 0, 0, 0};
+    TuneEntry e{};
+    bool have[6] = {false, false, false, false, false, false};
+    if (!in.eat('{')) return fail(IE_EINVAL, "%s: expected an object at byte %zu", path, in.i);
+    bool firstk = true;
+    while (!in.eat('}')) {
+      std::string key;
+      if ((!firstk && !in.eat(',')) || !in.str(key) || !in.eat(':'))
+        return fail(IE_EINVAL, "%s: bad key at byte %zu", path, in.i);
+      firstk = false;
+      bool ok = false;
+      if (key == "arch") {
+        ok = in.str(arch);
+        have[0] = true;
+      } else if (key == "precision") {
+        ok = in.str(prec);
+        have[1] = true;
+      } else if (key == "grid") {
+        ok = in.ints(grid, 3);
+        have[2] = true;
+      } else if (key == "fft") {
+        ok = in.ints(fft, 3);
+        have[3] = true;
+      } else if (key == "variant") {
+        ok = in.ints(var, 5);
+        have[4] = true;
+      } else if (key == "us") {
+        ok = in.eat('[');
+        for (int q = 0; q < 5 && ok; ++q) ok = (q == 0 || in.eat(',')) && in.nums(e.us[q], kRowVariants);
+        ok = ok && in.eat(']');
+        have[5] = true;
+      }
+      if (!ok) return fail(IE_EINVAL, "%s: bad value of \"%s\" at byte %zu", path, key.c_str(), in.i);
+    }
+    for (bool h : have)
+      if (!h) return fail(IE_EINVAL, "%s: entry %zu lacks a field", path, entries.size());
+    if (prec != "c128" && prec != "c64")
+      return fail(IE_EINVAL, "%s: entry %zu: unknown precision", path, entries.size());
+    for (int a = 0; a < 3; ++a)
+      if (grid[a] < 1 || grid[a] > 512 || !valid_len(grid[a], fft[a]))
+        return fail(IE_EINVAL, "%s: entry %zu: grid or FFT length out of range", path, entries.size());
+    for (int q = 0; q < 5; ++q) {
+      if (var[q] < 0 || var[q] >= (q == 2 ? kRowVariants : kVariants))
+        return fail(IE_EINVAL, "%s: entry %zu: variant out of range", path, entries.size());
+      e.var[q] = int8_t(var[q]);
+    }
+    entries.emplace_back(TuneKey{arch, prec == "c128" ? 0 : 1, grid[0], grid[1], grid[2], fft[0],
+                                 fft[1], fft[2]},
+                         e);
+  }
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  for (const auto& kv : entries) g_tune_cache[kv.first] = kv.second;
   return IE_OK;
 }
 

@@ -111,6 +111,9 @@ def lib():
                                   C.POINTER(ie_dd_opts), C.POINTER(ie_dd_stats), vp]
         L.ie_set_option.argtypes = [i32, i32]
         L.ie_set_option.restype = C.c_int
+        for f in (L.ie_tuning_save, L.ie_tuning_load):
+            f.argtypes = [C.c_char_p]
+            f.restype = C.c_int
         L.ie_profile_begin.argtypes = []
         L.ie_profile_end.argtypes = [C.POINTER(ie_kernel_stat), i32, C.POINTER(i32)]
         L.ie_nn_create.argtypes = [C.POINTER(ie_nn_config), vp, C.POINTER(vp)]
@@ -392,6 +395,16 @@ def ie_ctx_tuning(ctx):
 
 def ie_set_option(option, value):
     return _check(lib().ie_set_option(option, value), "ie_set_option")
+
+
+def ie_tuning_save(path):
+    """Write the autotuner's cache to a JSON file."""
+    return _check(lib().ie_tuning_save(os.fsencode(path)), "ie_tuning_save")
+
+
+def ie_tuning_load(path):
+    """Add the entries of a file written by ie_tuning_save to the autotuner's cache."""
+    return _check(lib().ie_tuning_load(os.fsencode(path)), "ie_tuning_load")
 
 
 # ----------------------------------------------------------------------------------------

@@ -248,7 +248,7 @@ def test_fft_length_modes_give_the_same_operator(torch):
     assert rel(ys[0, ie.IE_FP64], ys[1, ie.IE_FP64]) < 1e-13
     assert rel(ys[0, ie.IE_MIXED], ys[1, ie.IE_MIXED]) < 2e-6
     with pytest.raises(ie.IEError):
-        ie.ie_set_option(ie.IE_OPT_FFT_LENGTHS, 2)
+        ie.ie_set_option(ie.IE_OPT_FFT_LENGTHS, 3)
 
 
 @pytest.mark.parametrize("pow2", [0, 1])
@@ -287,5 +287,78 @@ def test_every_launch_variant_matches_oracle(torch, variant, n, pow2):
         assert all(r["variant"] == (variant if r["pass"] == "xconv" else variant & 3)
                    for r in tun)
         assert all(r["fft"] == [_fft_len(m, pow2) for m in n] for r in tun)
+    finally:
+        ie.ie_ctx_destroy(ctx)
+
+
+def test_tuning_file_sets_the_variants_of_later_contexts(torch, tmp_path):
+    """Variants saved by ie_tuning_save and loaded back (edited) are the ones a later context on
+    the same grid runs, without timing, and that context still matches the oracle."""
+    import json
+    from paper_2306_17537_amd import ie
+    n = (33, 20, 17)
+    p = synth.random_problem(n, seed=9, freq=2.0e6, contrast=3.0)
+    ctx, _ = context(p)
+    tun = {(r["precision"], r["pass"]): r["variant"] for r in ie.ie_ctx_tuning(ctx)}
+    ie.ie_ctx_destroy(ctx)
+    saved = tmp_path / "tune.json"
+    ie.ie_tuning_save(str(saved))
+    entries = json.loads(saved.read_text())
+    names = ["zfwd", "yfwd", "xconv", "yinv", "zinv"]
+    mine = [e for e in entries if e["grid"] == list(n) and e["fft"] == [96, 48, 48]]
+    assert sorted(e["precision"] for e in mine) == ["c128", "c64"]
+    for e in mine:
+        assert e["variant"] == [tun[e["precision"], q] for q in names]
+        e["variant"] = [(v + 3) % 8 if q == 2 else (v + 1) % 4 for q, v in enumerate(e["variant"])]
+    edited = tmp_path / "edited.json"
+    edited.write_text(json.dumps(mine))
+    ie.ie_tuning_load(str(edited))
+    try:
+        ctx, _ = context(p)
+        try:
+            got = {(r["precision"], r["pass"]): r["variant"] for r in ie.ie_ctx_tuning(ctx)}
+            for e in mine:
+                assert [got[e["precision"], q] for q in names] == e["variant"]
+            k0 = green.wavenumber(p.sigma0, p.freq)
+            Ghat = green.kernel_spectrum(p.n, p.h, k0, p.sigma0)
+            dsig = operator.contrast(p.sigma6, p.sigma0)
+            b, _, _ = operator.cie_tensors(dsig, p.sigma0)
+            x = _rand(field_shape(p), 4)
+            want = operator.apply_C(Ghat, b, x, p.sigma0, p.n)
+            yd = torch.zeros(field_shape(p), dtype=torch.complex128, device="cuda:0")
+            ie.ie_matvec(ctx, dev(p.sigma6), dev(x), yd, ie.IE_CIE, ie.IE_FP64)
+            assert rel(host(yd), want) < 1e-12
+        finally:
+            ie.ie_ctx_destroy(ctx)
+    finally:
+        ie.ie_tuning_load(str(saved))  # the measured choice again for later tests
+
+
+def test_timed_length_choice_keeps_the_faster_operator(torch):
+    """IE_OPT_FFT_LENGTHS = 2: both length sets are set up and timed; the context keeps the
+    faster, reports both times, and matches the oracle."""
+    from paper_2306_17537_amd import ie
+    n = (48, 48, 64)
+    p = synth.random_problem(n, seed=12, freq=4e5, contrast=3.0)
+    ie.ie_set_option(ie.IE_OPT_FFT_LENGTHS, 2)
+    try:
+        ctx, _ = context(p)
+    finally:
+        ie.ie_set_option(ie.IE_OPT_FFT_LENGTHS, 0)
+    try:
+        r = ie.ie_ctx_tuning(ctx)[0]
+        a, b = r["lengths_us"]
+        banner(f"timed lengths: shortest {a:.1f} us, powers of two {b:.1f} us -> {r['fft']}")
+        assert a > 0 and b > 0
+        assert r["fft"] == [_fft_len(m, int(b < a)) for m in n]
+        k0 = green.wavenumber(p.sigma0, p.freq)
+        Ghat = green.kernel_spectrum(p.n, p.h, k0, p.sigma0)
+        dsig = operator.contrast(p.sigma6, p.sigma0)
+        b6, _, _ = operator.cie_tensors(dsig, p.sigma0)
+        x = _rand(field_shape(p), 6)
+        want = operator.apply_C(Ghat, b6, x, p.sigma0, p.n)
+        y32 = torch.zeros(field_shape(p), dtype=torch.complex64, device="cuda:0")
+        ie.ie_matvec(ctx, dev(p.sigma6), dev(x.astype(np.complex64)), y32, ie.IE_CIE, ie.IE_MIXED)
+        assert rel(host(y32).astype(np.complex128), want) < 2e-6
     finally:
         ie.ie_ctx_destroy(ctx)
