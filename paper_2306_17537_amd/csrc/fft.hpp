@@ -109,6 +109,30 @@ struct Dft<T, 3, INV> {
   }
 };
 
+// DFT of size R (even) whose inputs R/2 .. R-1 are zero, by decimation in frequency: the even
+// outputs are the R/2-point DFT of the first half, the odd outputs that of the first half
+// multiplied by W_R^r.
+template <typename T, int R, bool INV>
+struct DftHalfIn {
+  template <int... K>
+  static __device__ __forceinline__ void split(const cx<T>* u, cx<T>* e, cx<T>* o,
+                                               std::integer_sequence<int, K...>) {
+    ((e[K] = u[K], o[K] = mul_wr<K, R, INV>(u[K])), ...);
+  }
+  static __device__ __forceinline__ void run(cx<T>* u) {
+    static_assert(R % 2 == 0, "even radix expected");
+    cx<T> e[R / 2], o[R / 2];
+    split(u, e, o, std::make_integer_sequence<int, R / 2>{});
+    Dft<T, R / 2, INV>::run(e);
+    Dft<T, R / 2, INV>::run(o);
+#pragma unroll
+    for (int k = 0; k < R / 2; ++k) {
+      u[2 * k] = e[k];
+      u[2 * k + 1] = o[k];
+    }
+  }
+};
+
 template <typename T, bool INV>
 __device__ __forceinline__ cx<T> twiddle(const cx<T>* __restrict__ tw, int idx) {
   cx<T> w = tw[idx];
@@ -169,7 +193,10 @@ struct LdsPadded4 {
   static constexpr __host__ __device__ int padded_len(int L) { return L + L / 4 + 16; }
 };
 
-template <typename T, int L, int E, int S, bool INV, typename Addr>
+// ZIN: the positions L/2 .. L-1 are zero on entry (registers E/2 .. E-1), so the first stage
+// takes the zero upper half of each butterfly's inputs into account.  TWL: length of the
+// twiddle table tw (entries exp(-2 pi i k / TWL); a multiple of L).
+template <typename T, int L, int E, int S, bool INV, bool ZIN, int TWL, typename Addr>
 __device__ __forceinline__ void fft_stage(cx<T> (&v)[E], cx<T>* __restrict__ lds, Addr addr,
                                           int t, const cx<T>* __restrict__ tw) {
   constexpr int R = stage_radix<L, E>(S);
@@ -187,11 +214,14 @@ __device__ __forceinline__ void fft_stage(cx<T> (&v)[E], cx<T>* __restrict__ lds
 #pragma unroll
     for (int r = 0; r < R; ++r) u[r] = v[b + r * NB];
     if constexpr (NS > 1) {
-      constexpr int step = TW_N / (NS * R);
+      constexpr int step = TWL / (NS * R);
 #pragma unroll
       for (int r = 1; r < R; ++r) u[r] = u[r] * twiddle<T, INV>(tw, r * k * step);
     }
-    Dft<T, R, INV>::run(u);
+    if constexpr (ZIN && S == 0 && R % 2 == 0)
+      DftHalfIn<T, R, INV>::run(u);
+    else
+      Dft<T, R, INV>::run(u);
 #pragma unroll
     for (int r = 0; r < R; ++r) out[b + r * NB] = u[r];
   }
@@ -214,26 +244,28 @@ __device__ __forceinline__ void fft_stage(cx<T> (&v)[E], cx<T>* __restrict__ lds
   }
 }
 
-template <typename T, int L, int E, bool INV, typename Addr, int... S>
+template <typename T, int L, int E, bool INV, bool ZIN, int TWL, typename Addr, int... S>
 __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], cx<T>* lds, Addr addr, int t,
                                            const cx<T>* tw, std::integer_sequence<int, S...>) {
-  (fft_stage<T, L, E, S, INV>(v, lds, addr, t, tw), ...);
+  (fft_stage<T, L, E, S, INV, ZIN, TWL>(v, lds, addr, t, tw), ...);
 }
 
 // Full length-L FFT of the line held in v (natural positions t + m L/E on entry and exit).
-// Every thread of the block must call it (it contains __syncthreads when L > E).
-template <typename T, int L, int E, bool INV, typename Addr>
+// Every thread of the block must call it (it contains __syncthreads when L > E).  ZIN: the upper
+// half of the line is zero on entry (v[E/2 ..] are not read).  TWL: length of the twiddle table
+// (the global table of TW_N entries, or a copy of the L entries of this length in LDS).
+template <typename T, int L, int E, bool INV, bool ZIN = false, int TWL = TW_N, typename Addr>
 __device__ __forceinline__ void fft_line(cx<T> (&v)[E], cx<T>* lds, Addr addr, int t,
                                          const cx<T>* __restrict__ tw) {
-  static_assert(L % E == 0 && L <= MAX_FFT_LEN, "bad FFT length");
-  fft_stages<T, L, E, INV>(v, lds, addr, t, tw,
-                           std::make_integer_sequence<int, num_stages<L, E>()>{});
+  static_assert(L % E == 0 && L <= MAX_FFT_LEN && TWL % L == 0, "bad FFT length");
+  fft_stages<T, L, E, INV, ZIN, TWL>(v, lds, addr, t, tw,
+                                     std::make_integer_sequence<int, num_stages<L, E>()>{});
 }
 
 // The same FFT for NC lines held by one thread (v[c], c < NC), in lockstep: the twiddles of
 // each stage are loaded once and applied to every line, and the lines go through LDS one after
 // the other (one line of LDS space).
-template <typename T, int L, int E, int S, bool INV, int NC, typename Addr>
+template <typename T, int L, int E, int S, bool INV, int NC, bool ZIN, int TWL, typename Addr>
 __device__ __forceinline__ void fft_stage_multi(cx<T> (&v)[NC][E], cx<T>* __restrict__ lds,
                                                 Addr addr, int t,
                                                 const cx<T>* __restrict__ tw) {
@@ -245,7 +277,7 @@ __device__ __forceinline__ void fft_stage_multi(cx<T> (&v)[NC][E], cx<T>* __rest
   static_assert(E % R == 0, "radix must divide the register width");
   cx<T> w[NB][R];
   if constexpr (NS > 1) {
-    constexpr int step = TW_N / (NS * R);
+    constexpr int step = TWL / (NS * R);
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       const int k = (t + b * TL) % NS;
@@ -265,7 +297,10 @@ __device__ __forceinline__ void fft_stage_multi(cx<T> (&v)[NC][E], cx<T>* __rest
 #pragma unroll
         for (int r = 1; r < R; ++r) u[r] = u[r] * w[b][r];
       }
-      Dft<T, R, INV>::run(u);
+      if constexpr (ZIN && S == 0 && R % 2 == 0)
+        DftHalfIn<T, R, INV>::run(u);
+      else
+        Dft<T, R, INV>::run(u);
 #pragma unroll
       for (int r = 0; r < R; ++r) out[b + r * NB] = u[r];
     }
@@ -289,19 +324,46 @@ __device__ __forceinline__ void fft_stage_multi(cx<T> (&v)[NC][E], cx<T>* __rest
   }
 }
 
-template <typename T, int L, int E, bool INV, int NC, typename Addr, int... S>
+template <typename T, int L, int E, bool INV, int NC, bool ZIN, int TWL, typename Addr,
+          int... S>
 __device__ __forceinline__ void fft_stages_multi(cx<T> (&v)[NC][E], cx<T>* lds, Addr addr, int t,
                                                  const cx<T>* tw,
                                                  std::integer_sequence<int, S...>) {
-  (fft_stage_multi<T, L, E, S, INV, NC>(v, lds, addr, t, tw), ...);
+  (fft_stage_multi<T, L, E, S, INV, NC, ZIN, TWL>(v, lds, addr, t, tw), ...);
 }
 
-template <typename T, int L, int E, bool INV, int NC, typename Addr>
+// ZIN and TWL as for fft_line.
+template <typename T, int L, int E, bool INV, int NC, bool ZIN = false, int TWL = TW_N,
+          typename Addr>
 __device__ __forceinline__ void fft_lines(cx<T> (&v)[NC][E], cx<T>* lds, Addr addr, int t,
                                           const cx<T>* __restrict__ tw) {
-  static_assert(L % E == 0 && L <= MAX_FFT_LEN, "bad FFT length");
-  fft_stages_multi<T, L, E, INV, NC>(v, lds, addr, t, tw,
-                                     std::make_integer_sequence<int, num_stages<L, E>()>{});
+  static_assert(L % E == 0 && L <= MAX_FFT_LEN && TWL % L == 0, "bad FFT length");
+  fft_stages_multi<T, L, E, INV, NC, ZIN, TWL>(
+      v, lds, addr, t, tw, std::make_integer_sequence<int, num_stages<L, E>()>{});
 }
+
+// The L twiddles exp(-2 pi i k / L) of one length, copied from the global table into LDS by the
+// NT threads of a block in two steps: load() issues the global reads into registers (call it
+// before the block's other global reads, so that waiting for these leaves those in flight),
+// store() writes them to LDS; a barrier must follow before the table is read.
+template <typename T, int L, int NT>
+struct TwStage {
+  static constexpr int K = (L + NT - 1) / NT;
+  cx<T> r[K];
+  __device__ __forceinline__ void load(const cx<T>* __restrict__ tw, int tid) {
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const int k = tid + i * NT;
+      r[i] = k < L ? tw[k * (TW_N / L)] : cx<T>{0, 0};
+    }
+  }
+  __device__ __forceinline__ void store(cx<T>* tab, int tid) const {
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const int k = tid + i * NT;
+      if (k < L) tab[k] = r[i];
+    }
+  }
+};
 
 }  // namespace ie

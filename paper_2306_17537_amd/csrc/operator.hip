@@ -150,15 +150,22 @@ template <typename T, int L>
 struct XconvL {
   template <int V>
   static int go(const MvArgs<T>& a, int batch, hipStream_t s) {
-    using G = GeoX<T, L, V>;
-    // x extent: the LY/2 + 1 stored rows in groups of NP, rounded up to a multiple of 8 XCDs
-    dim3 grid((ceil_div(a.LY / 2 + 1, G::NP) + 7) / 8 * 8, a.LZ, batch);
     const double cs = sizeof(cx<T>);
     // algorithmic bytes count the spectrum at its octant size (the unique values), read once
     const double oct = 6.0 * (L / 2 + 1) * (a.LY / 2 + 1) * (a.LZ / 2 + 1);
     const double by = double(batch) * 2.0 * a.LZ * a.LY * a.nx * 3 * cs + oct * cs;
     ProfScope ps(s, "xconv", shape_tag(int(cs), a.LX, a.LY, a.LZ, a.nz, batch).c_str(), by);
-    hipLaunchKernelGGL((k_xconv<T, L, V>), grid, dim3(G::THREADS), 0, s, a);
+    // variants 4..7: one line per thread group where its LDS fits, else 0..3
+    if constexpr (V >= 4 && GeoX2<T, L, V & 3>::FITS) {
+      using G = GeoX2<T, L, V & 3>;
+      // x extent: the LY/2 + 1 stored rows in groups of NP, rounded up to a multiple of 8 XCDs
+      dim3 grid((ceil_div(a.LY / 2 + 1, G::NP) + 7) / 8 * 8, a.LZ, batch);
+      hipLaunchKernelGGL((k_xconv2<T, L, V & 3>), grid, dim3(G::THREADS), 0, s, a);
+    } else {
+      using G = GeoX<T, L, V & 3>;
+      dim3 grid((ceil_div(a.LY / 2 + 1, G::NP) + 7) / 8 * 8, a.LZ, batch);
+      hipLaunchKernelGGL((k_xconv<T, L, V & 3>), grid, dim3(G::THREADS), 0, s, a);
+    }
     IE_LAUNCH_CHECK();
     return IE_OK;
   }
@@ -168,9 +175,11 @@ struct XconvL {
 };
 template <typename T, int L>
 struct ColL {
+  // half: the operator's half-size lines (forward rows_in, inverse rows_out <= L/2); otherwise
+  // a full-length forward transform (variant 0 only, for the Green setup)
   template <int V>
   static int go(const cx<T>* in, cx<T>* out, const ColArgs& c, int nplanes, int batch, bool inv,
-                hipStream_t s, const cx<T>* tw) {
+                bool half, hipStream_t s, const cx<T>* tw) {
     using G = Geo<T, L, V>;
     dim3 grid(ceil_div(c.ncols, G::W), nplanes, batch);
     const double cs = sizeof(cx<T>);
@@ -179,17 +188,31 @@ struct ColL {
     snprintf(tg, sizeof(tg), "%s L%d planes%d cols%d b%d", cs == 8 ? "c64" : "c128", L, nplanes,
              c.ncols, batch);
     ProfScope ps(s, inv ? "yinv" : "yfwd", tg, by);
-    if (inv)
-      hipLaunchKernelGGL((k_colfft<T, L, true, V>), grid, dim3(G::W * G::TL), 0, s, in, out, c, tw);
-    else
-      hipLaunchKernelGGL((k_colfft<T, L, false, V>), grid, dim3(G::W * G::TL), 0, s, in, out, c,
-                         tw);
+    if (half) {
+      if (2 * (inv ? c.rows_out : c.rows_in) > L)
+        return fail(IE_EINVAL, "column pass: %d rows exceed half of length %d",
+                    inv ? c.rows_out : c.rows_in, L);
+      if (inv)
+        hipLaunchKernelGGL((k_colfft<T, L, true, V, true>), grid, dim3(G::W * G::TL), 0, s, in,
+                           out, c, tw);
+      else
+        hipLaunchKernelGGL((k_colfft<T, L, false, V, true>), grid, dim3(G::W * G::TL), 0, s, in,
+                           out, c, tw);
+    } else {
+      if constexpr (V == 0) {
+        if (inv) return fail(IE_EINVAL, "full-length inverse column pass is not built");
+        hipLaunchKernelGGL((k_colfft<T, L, false, 0, false>), grid, dim3(G::W * G::TL), 0, s, in,
+                           out, c, tw);
+      } else {
+        return fail(IE_EINVAL, "full-length column pass has variant 0 only");
+      }
+    }
     IE_LAUNCH_CHECK();
     return IE_OK;
   }
   static int run(int v, const cx<T>* in, cx<T>* out, const ColArgs& c, int nplanes, int batch,
-                 bool inv, hipStream_t s, const cx<T>* tw) {
-    IE_VARIANTS(v, in, out, c, nplanes, batch, inv, s, tw);
+                 bool inv, bool half, hipStream_t s, const cx<T>* tw) {
+    IE_VARIANTS(v, in, out, c, nplanes, batch, inv, half, s, tw);
   }
 };
 
@@ -262,7 +285,8 @@ int launch_matvec(Plan& p, MvArgs<T> a, int batch, hipStream_t s, const cx<T>* t
   c.active = a.active;
   c.active_bs = a.active_bs;
   auto col = [&](const cx<T>* in, cx<T>* out, const ColArgs& cc, bool inv) -> int {
-    IE_LEN_CASES(ColL, T, p.LY, vsel(inv ? 3 : 1), in, out, cc, 3 * p.LZ, batch, inv, s, tw);
+    IE_LEN_CASES(ColL, T, p.LY, vsel(inv ? 3 : 1), in, out, cc, 3 * p.LZ, batch, inv, true, s,
+                 tw);
   };
   if (want(1)) IE_TRY(col(a.T1, a.T2, c, false));
   // pass 3: FFT along x, tensor multiply with G^, inverse FFT along x (rows of every (ky, kz))
@@ -760,7 +784,9 @@ int build_green(Plan& p, double h, const Medium& m, int prec_mask, const c128* t
     ca.in_ls = ca.out_ls = p.LX;
     ca.rows_in = ca.rows_out = p.LY;
     {
-      auto f = [&]() -> int { IE_LEN_CASES(ColL, double, p.LY, 0, b, b, ca, p.LZ, 1, false, s, tw64); };
+      auto f = [&]() -> int {
+        IE_LEN_CASES(ColL, double, p.LY, 0, b, b, ca, p.LZ, 1, false, false, s, tw64);
+      };
       IE_TRY(f());
     }
     // z axis: planes = y
@@ -769,7 +795,9 @@ int build_green(Plan& p, double h, const Medium& m, int prec_mask, const c128* t
     ca.in_ls = ca.out_ls = long(p.LY) * p.LX;
     ca.rows_in = ca.rows_out = p.LZ;
     {
-      auto f = [&]() -> int { IE_LEN_CASES(ColL, double, p.LZ, 0, b, b, ca, p.LY, 1, false, s, tw64); };
+      auto f = [&]() -> int {
+        IE_LEN_CASES(ColL, double, p.LZ, 0, b, b, ca, p.LY, 1, false, false, s, tw64);
+      };
       IE_TRY(f());
     }
   }

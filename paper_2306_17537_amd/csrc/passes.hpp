@@ -141,7 +141,10 @@ __device__ __forceinline__ void tensor_apply(const T m[6], const cx<T> v[3], cx<
 // ---------------------------------------------------------------------------------------
 // Column FFT along a strided axis.  Plane q of nplanes: comp c = q / nzp, index zq = z0 + q % nzp;
 // in element (row r, col x) of plane q at in[c*in_cs + zq*in_zs + r*in_ls + x]; rows >= rows_in
-// are zero on input; rows < rows_out are written.  Block: W columns x TL threads.
+// are zero on input; rows < rows_out are written.  Block: W columns x TL threads.  HALF: the
+// convolution's half-size lines (forward: rows_in <= L/2, the transform skips the zero upper
+// half; inverse: rows_out <= L/2, only the lower half is computed); the twiddles of the length
+// are then staged in LDS.
 // ---------------------------------------------------------------------------------------
 struct ColArgs {
   int ncols, nzp, z0;
@@ -152,15 +155,19 @@ struct ColArgs {
   int active_bs;
 };
 
-template <typename T, int L, bool INV, int V>
+template <typename T, int L, bool INV, int V, bool HALF>
 __global__ void __launch_bounds__((Geo<T, L, V>::W * Geo<T, L, V>::TL))
     k_colfft(const cx<T>* in, cx<T>* out, const ColArgs a,
              const cx<T>* __restrict__ tw) {
   using G = Geo<T, L, V>;
   constexpr int E = G::E, TL = G::TL, W = G::W;
+  constexpr int ME = HALF ? E / 2 : E;  // registers read (forward) or written (inverse)
   __shared__ cx<T> lds[W * L];
+  __shared__ cx<T> twl[HALF ? L : 1];
   const int b = blockIdx.z;
   if (a.active != nullptr && a.active[b * a.active_bs] == 0) return;
+  TwStage<T, HALF ? L : 1, W * TL> tws;
+  if constexpr (HALF) tws.load(tw, threadIdx.x);
   const int w = threadIdx.x % W;
   const int t = threadIdx.x / W;
   const int col = blockIdx.x * W + w;
@@ -174,12 +181,18 @@ __global__ void __launch_bounds__((Geo<T, L, V>::W * Geo<T, L, V>::TL))
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int r = t + m * TL;
-    v[m] = (live && r < a.rows_in) ? src[r * a.in_ls] : cx<T>{0, 0};
+    v[m] = ((INV || m < ME) && live && r < a.rows_in) ? src[r * a.in_ls] : cx<T>{0, 0};
   }
-  fft_line<T, L, E, INV>(v, lds, LdsInterleaved{W, w}, t, tw);
+  if constexpr (HALF) {
+    tws.store(twl, threadIdx.x);
+    __syncthreads();
+    fft_line<T, L, E, INV, !INV, L>(v, lds, LdsInterleaved{W, w}, t, twl);
+  } else {
+    fft_line<T, L, E, INV>(v, lds, LdsInterleaved{W, w}, t, tw);
+  }
   if (live) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
+    for (int m = 0; m < (INV ? ME : E); ++m) {
       const int r = t + m * TL;
       if (r < a.rows_out) store_stream(&dst[r * a.out_ls], v[m]);
     }
@@ -230,8 +243,11 @@ __global__ void __launch_bounds__((GeoC<T, LZ, V>::THREADS)) k_zfwd(const MvArgs
   using G = GeoC<T, LZ, V>;
   constexpr int E = G::E, TL = G::TL, W = G::W;
   __shared__ cx<T> lds[W * LZ];
+  __shared__ cx<T> twl[LZ];
   const int b = blockIdx.z;
   if (retired(a, b)) return;
+  TwStage<T, LZ, G::THREADS> tws;
+  tws.load(a.tw, threadIdx.x);
   const int w = threadIdx.x % W;
   const int t = threadIdx.x / W;
   const long plane = long(a.ny) * a.nx;
@@ -241,8 +257,13 @@ __global__ void __launch_bounds__((GeoC<T, LZ, V>::THREADS)) k_zfwd(const MvArgs
   const T* M = a.M ? a.M + b * a.M_bs + col : nullptr;
   const T xs = a.xscale ? T(a.xscale[b * a.xscale_bs]) : T(1);
   cx<T> v[3][E];
+  // the nz <= LZ/2 planes sit in the lower half of the line
 #pragma unroll
-  for (int m = 0; m < E; ++m) {
+  for (int m = E / 2; m < E; ++m)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c][m] = cx<T>{0, 0};
+#pragma unroll
+  for (int m = 0; m < E / 2; ++m) {
     const int z = t + m * TL;
     cx<T> xv[3] = {{0, 0}, {0, 0}, {0, 0}};
     const bool on = live && source_plane(a, z);
@@ -263,7 +284,9 @@ __global__ void __launch_bounds__((GeoC<T, LZ, V>::THREADS)) k_zfwd(const MvArgs
       for (int c = 0; c < 3; ++c) v[c][m] = xv[c];
     }
   }
-  fft_lines<T, LZ, E, false, 3>(v, lds, LdsInterleaved{W, w}, t, a.tw);
+  tws.store(twl, threadIdx.x);
+  __syncthreads();
+  fft_lines<T, LZ, E, false, 3, true, LZ>(v, lds, LdsInterleaved{W, w}, t, twl);
   if (live) {
     cx<T>* out = a.T1 + b * a.T1_bs + col;
     const long cs = long(LZ) * plane;
@@ -281,8 +304,11 @@ __global__ void __launch_bounds__((GeoC<T, LZ, V>::THREADS)) k_zinv(const MvArgs
   using G = GeoC<T, LZ, V>;
   constexpr int E = G::E, TL = G::TL, W = G::W;
   __shared__ cx<T> lds[W * LZ];
+  __shared__ cx<T> twl[LZ];
   const int b = blockIdx.z;
   if (retired(a, b)) return;
+  TwStage<T, LZ, G::THREADS> tws;
+  tws.load(a.tw, threadIdx.x);
   const int w = threadIdx.x % W;
   const int t = threadIdx.x / W;
   const long plane = long(a.ny) * a.nx;
@@ -296,15 +322,18 @@ __global__ void __launch_bounds__((GeoC<T, LZ, V>::THREADS)) k_zinv(const MvArgs
 #pragma unroll
     for (int m = 0; m < E; ++m)
       v[c][m] = live ? in[c * cs + long(t + m * TL) * plane] : cx<T>{0, 0};
-  fft_lines<T, LZ, E, true, 3>(v, lds, LdsInterleaved{W, w}, t, a.tw);
+  tws.store(twl, threadIdx.x);
+  __syncthreads();
+  fft_lines<T, LZ, E, true, 3, false, LZ>(v, lds, LdsInterleaved{W, w}, t, twl);
   if (!live) return;
   cx<T>* y = a.y + b * a.y_bs + col;
   const cx<T>* x = a.x ? a.x + b * a.x_bs + col : nullptr;
   const cx<T>* e = a.e ? a.e + b * a.e_bs + col : nullptr;
   const T* M = (a.M && a.a_m != T(0)) ? a.M + b * a.M_bs + col : nullptr;
   const T xs = a.xscale ? T(a.xscale[b * a.xscale_bs]) : T(1);
+  // the output planes (< nz <= LZ/2) sit in the lower half of the line
 #pragma unroll
-  for (int m = 0; m < E; ++m) {
+  for (int m = 0; m < E / 2; ++m) {
     const int z = t + m * TL;
     if (z < a.out_z0 || z >= a.out_z1) continue;
     cx<T> r[3];
@@ -359,8 +388,11 @@ __global__ void __launch_bounds__((GeoX<T, LX, V>::THREADS)) k_xconv(const MvArg
   using G = Geo<T, LX, V>;
   constexpr int E = G::ER, TL = G::TLR, NP = GeoX<T, LX, V>::NP;
   __shared__ cx<T> lds[2 * NP * G::LP];
+  __shared__ cx<T> twl[LX];
   const int b = blockIdx.z;
   if (retired(a, b)) return;
+  TwStage<T, LX, GeoX<T, LX, V>::THREADS> tws;
+  tws.load(a.tw, threadIdx.x);
   const int hx = LX / 2, hy = a.LY / 2, hz = a.LZ / 2;
   const int t = threadIdx.x % TL;
   const int rr = threadIdx.x / TL;  // row of the block: pair rr / 2, member rr % 2
@@ -378,15 +410,19 @@ __global__ void __launch_bounds__((GeoX<T, LX, V>::THREADS)) k_xconv(const MvArg
   const long cs = long(a.LZ) * rs;    // per component
   cx<T>* row = a.T2 + b * a.T2_bs + long(kz) * rs + long(ky) * a.nx;
   cx<T> v[3][E];
+  // the nx <= LX/2 cells sit in the lower half of the line
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int i = t + m * TL;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) v[c][m] = (live && i < a.nx) ? row[c * cs + i] : cx<T>{0, 0};
+    for (int c = 0; c < 3; ++c)
+      v[c][m] = (m < E / 2 && live && i < a.nx) ? row[c * cs + i] : cx<T>{0, 0};
   }
   const typename G::RowLds addr{rr * G::LP};
-  // the three lines in lockstep: each stage's twiddles are loaded once
-  fft_lines<T, LX, E, false, 3>(v, lds, addr, t, a.tw);
+  tws.store(twl, threadIdx.x);
+  __syncthreads();
+  // the three lines in lockstep: each stage's twiddles are read once
+  fft_lines<T, LX, E, false, 3, true, LX>(v, lds, addr, t, twl);
   const long gys = hx + 1;
   const long gzs = long(hy + 1) * gys;
   const long gcs = long(hz + 1) * gzs;
@@ -406,15 +442,144 @@ __global__ void __launch_bounds__((GeoX<T, LX, V>::THREADS)) k_xconv(const MvArg
     v[1][m] = gxy * j0 + gyy * j1 + gyz * j2;
     v[2][m] = gxz * j0 + gyz * j1 + gzz * j2;
   }
-  fft_lines<T, LX, E, true, 3>(v, lds, addr, t, a.tw);
+  fft_lines<T, LX, E, true, 3, false, LX>(v, lds, addr, t, twl);
   if (live) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
+    for (int m = 0; m < E / 2; ++m) {
       const int i = t + m * TL;
       if (i < a.nx) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) store_stream(&row[c * cs + i], v[c][m]);
       }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// xconv, one line per thread group: the same operation as k_xconv with each of the six lines of
+// a row pair (two rows x three components) transformed by its own TL threads, so that a thread
+// holds one line (E values) instead of three and more waves fit on a CU.  The spectra meet in
+// LDS for the tensor multiply, which the whole block does with one work item per (row pair,
+// kx): the six stored spectrum components are loaded once for both rows of the pair.  The
+// forward transforms skip the zero upper half of the padded lines, the inverse ones compute
+// only the kept lower half.  V & 1: 16 values per thread instead of 8; V & 2: two row pairs per
+// block.  Used where the block's LDS (six padded lines per pair and the twiddles) fits in the
+// 160 KB of a CU.
+// ---------------------------------------------------------------------------------------
+template <typename T, int LX, int V>
+struct GeoX2 {
+  static constexpr int E0 = (V & 1) ? 16 : 8;
+  static constexpr int E = LX % 3 == 0 ? reg_width(LX, 0) : (LX < E0 ? LX : E0);
+  static constexpr int TL = LX / E;
+  static constexpr int NP0 = (V & 2) ? 2 : 1;
+  static constexpr int NPW = (64 + 6 * TL - 1) / (6 * TL);  // at least one wavefront
+  static constexpr int NP1 = NP0 > NPW ? NP0 : NPW;
+  static constexpr int NPM = 1024 / (6 * TL) < 1 ? 1 : 1024 / (6 * TL);
+  static constexpr int NP = NP1 < NPM ? NP1 : NPM;
+  static constexpr int THREADS = 6 * NP * TL;
+  static constexpr int LP = LdsPadded::padded_len(LX);
+  static constexpr bool FITS = (6 * NP * LP + LX) * int(sizeof(cx<T>)) <= 160 * 1024 &&
+                               THREADS <= 1024;
+  static constexpr int ITEMS = (NP * LX + THREADS - 1) / THREADS;  // multiply items per thread
+};
+
+template <typename T, int LX, int V>
+__global__ void __launch_bounds__((GeoX2<T, LX, V>::THREADS)) k_xconv2(const MvArgs<T> a) {
+  using G = GeoX2<T, LX, V>;
+  constexpr int E = G::E, TL = G::TL, NP = G::NP;
+  __shared__ cx<T> lds[6 * NP * G::LP];
+  __shared__ cx<T> twl[LX];  // exp(-2 pi i k / LX), k < LX
+  const int b = blockIdx.z;
+  if (retired(a, b)) return;
+  // every global read of the block is issued up front (twiddles, the lines, the spectrum values
+  // of the multiply), so that their latencies overlap instead of adding up stage by stage
+  TwStage<T, LX, G::THREADS> tws;
+  tws.load(a.tw, threadIdx.x);
+  const int hx = LX / 2, hy = a.LY / 2, hz = a.LZ / 2;
+  const int t = threadIdx.x % TL;
+  const int line = threadIdx.x / TL;  // pair line / 6, row (line / 3) % 2, component line % 3
+  const int pr = line / 6, r = (line / 3) & 1, c = line % 3;
+  const int oy = blockIdx.x * NP + pr;  // stored y row; rows beyond LY/2 pad the grid
+  const bool live = oy <= hy && (r == 0 || (oy != 0 && oy != hy));
+  const int ky = r == 0 ? oy : a.LY - oy;
+  const int bz = blockIdx.y;
+  const int kz = bz < 2 ? bz * hz : ((bz & 1) ? a.LZ - (bz >> 1) : (bz >> 1));
+  const int oz = kz > hz ? a.LZ - kz : kz;
+  const T sz = kz > hz ? T(-1) : T(1);
+  const long rs = long(a.LY) * a.nx;  // per kz
+  const long cs = long(a.LZ) * rs;    // per component
+  cx<T>* row = a.T2 + b * a.T2_bs + long(c) * cs + long(kz) * rs + long(live ? ky : 0) * a.nx;
+  const LdsPadded addr{line * G::LP};
+  cx<T> v[E];
+  // the nx <= LX/2 cells sit in the lower half of the line
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int i = t + m * TL;
+    v[m] = (m < E / 2 && live && i < a.nx) ? row[i] : cx<T>{0, 0};
+  }
+  // spectrum values of the multiply items (pair, kx) of this thread
+  const long gys = hx + 1;
+  const long gzs = long(hy + 1) * gys;
+  const long gcs = long(hz + 1) * gzs;
+  const cx<T>* gz0 = a.ghat + b * a.ghat_bs + long(oz) * gzs;
+  cx<T> gv[G::ITEMS][6];
+#pragma unroll
+  for (int q = 0; q < G::ITEMS; ++q) {
+    const int it = threadIdx.x + q * G::THREADS;
+    const int p = it / LX, kx = it % LX;
+    const int py = blockIdx.x * NP + p;
+    const bool ok = p < NP && py <= hy;
+    const int ox = kx > hx ? LX - kx : kx;
+    const cx<T>* g = gz0 + long(ok ? py : 0) * gys + ox;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) gv[q][k] = ok ? g[k * gcs] : cx<T>{0, 0};
+  }
+  tws.store(twl, threadIdx.x);
+  __syncthreads();  // the twiddle table
+  fft_line<T, LX, E, false, true, LX>(v, lds, addr, t, twl);
+  // the last stage ran in registers after every thread's last LDS read of this line
+#pragma unroll
+  for (int m = 0; m < E; ++m) lds[addr(t + m * TL)] = v[m];
+  __syncthreads();
+  // tensor multiply: item (pair, kx), both rows of the pair
+#pragma unroll
+  for (int q = 0; q < G::ITEMS; ++q) {
+    const int it = threadIdx.x + q * G::THREADS;
+    const int p = it / LX, kx = it % LX;
+    const int py = blockIdx.x * NP + p;
+    if (p < NP && py <= hy) {
+      const T sx = kx > hx ? T(-1) : T(1);
+      const cx<T> gxx = gv[q][0], gyy = gv[q][1], gzz = gv[q][2];
+      const cx<T> gxy = sx * gv[q][3];
+      const cx<T> gxz = (sx * sz) * gv[q][4];
+      const cx<T> gyz = sz * gv[q][5];
+      const int nr = (py != 0 && py != hy) ? 2 : 1;
+#pragma unroll
+      for (int rr = 0; rr < 2; ++rr) {
+        if (rr < nr) {
+          const T sy = rr == 0 ? T(1) : T(-1);
+          const int base = (p * 6 + rr * 3) * G::LP;
+          const int i0 = LdsPadded{base}(kx), i1 = LdsPadded{base + G::LP}(kx),
+                    i2 = LdsPadded{base + 2 * G::LP}(kx);
+          const cx<T> j0 = lds[i0], j1 = lds[i1], j2 = lds[i2];
+          const cx<T> gxys = sy * gxy, gyzs = sy * gyz;
+          lds[i0] = gxx * j0 + gxys * j1 + gxz * j2;
+          lds[i1] = gxys * j0 + gyy * j1 + gyzs * j2;
+          lds[i2] = gxz * j0 + gyzs * j1 + gzz * j2;
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < E; ++m) v[m] = lds[addr(t + m * TL)];
+  __syncthreads();  // every read of the line done before its first inverse stage writes
+  fft_line<T, LX, E, true, false, LX>(v, lds, addr, t, twl);
+  if (live) {
+#pragma unroll
+    for (int m = 0; m < E / 2; ++m) {
+      const int i = t + m * TL;
+      if (i < a.nx) store_stream(&row[i], v[m]);
     }
   }
 }
