@@ -51,6 +51,15 @@ LARGE_WORKLOAD = ("128x128x256 cells of 0.25 m (12.6 M complex unknowns), six ti
                   "dipole at the centre")
 
 
+# launch variants measured by the autotuner on this GPU for every grid the benchmark sets up
+# (written by a run with --tuning none --save-tuning), so that repeated runs and the profiler
+# runs time the same kernels
+DEFAULT_TUNING = os.path.join(ROOT, "paper_2306_17537_amd", "tuning_gfx950.json")
+# kernel-trace summary of the timed solves alone (the dominant kernel also serves other grids in
+# a default run)
+HEADLINE_TRACE = "large_grid_fp64_and_mixed_solves_trace.md"
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +80,10 @@ def parse():
     ap.add_argument("--no-ex1", action="store_true",
                     help="skip the isolated sub-domains example (128^3, DD vs full domain)")
     ap.add_argument("--no-small", action="store_true", help="skip the 64^3 model legs")
+    ap.add_argument("--tuning", default=DEFAULT_TUNING,
+                    help="launch-variant file to load before any setup ('none': tune every grid)")
+    ap.add_argument("--save-tuning", default=None,
+                    help="write the launch-variant cache of this run here at the end")
     return ap.parse_args()
 
 
@@ -102,6 +115,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     ie.lib()
+    tuning_file = None
+    if args.tuning != "none" and os.path.exists(args.tuning):
+        ie.ie_tuning_load(args.tuning)
+        tuning_file = os.path.relpath(args.tuning, ROOT)
     if args.pmc_calibration:
         from paper_2306_17537_amd import traffic
         traffic.calibrate()
@@ -165,7 +182,7 @@ def main():
         hit = traffic.lookup(dom_kernel)
         if hit is not None:
             traffic_bytes, traffic_src = hit[0], os.path.relpath(hit[2], ROOT)
-        tr = traffic.trace_lookup(dom_kernel)
+        tr = traffic.trace_lookup(dom_kernel, summary=HEADLINE_TRACE)
         if tr is not None:
             rocprof = dict(avg_us=tr[0], calls=tr[1], source=os.path.relpath(tr[2], ROOT),
                            achieved=round(dom["bytes_per_launch"] / (tr[0] * 1e-6) / 1e9, 1),
@@ -266,10 +283,13 @@ def main():
         "batch": batch,
         "autotune_full_grid": {f"{r['precision']} {r['pass']}": r["variant"] for r in tuning
                                if r["grid"] == list(p.n)},
+        "tuning_file": tuning_file,
         "accuracy": acc,
     }
     print(json.dumps(out))
     ie.ie_ctx_destroy(ctx)
+    if args.save_tuning:
+        ie.ie_tuning_save(args.save_tuning)
 
 
 def config1_legs(ie, torch, args, acc):
@@ -411,23 +431,14 @@ PASS_NAMES = {"zfwd": "k_zfwd", "zinv": "k_zinv", "xconv": "k_xconv", "yfwd": "k
 
 def template_name(prof_name, tuning, grid):
     """Kernel template name (as rocprofv3 prints it) of a library profiler entry on the full
-    grid, with the launch variant the autotuner chose, e.g. 'k_xconv<double, 256, 0>'."""
+    grid, with the launch variant the autotuner chose, e.g. 'k_xconv2<double, 256, 0>'."""
     parts = prof_name.split()
     if len(parts) < 3 or parts[0] not in PASS_NAMES:
         return None
     prec = parts[1]
     m = [r for r in tuning if r["grid"] == list(grid) and r["precision"] == prec
          and r["pass"] == parts[0]]
-    if not m:
-        return None
-    t = "float" if prec == "c64" else "double"
-    dims = parts[2][1:].split("x")
-    if parts[0] in ("yfwd", "yinv"):
-        L = int(dims[0])
-        inv = "true" if parts[0] == "yinv" else "false"
-        return f"k_colfft<{t}, {L}, {inv}, {m[0]['variant']}>"
-    L = int(dims[0]) if parts[0] == "xconv" else int(dims[2])
-    return f"{PASS_NAMES[parts[0]]}<{t}, {L}, {m[0]['variant']}>"
+    return m[0]["kernel"] if m else None
 
 
 def measured_traffic(passes, tuning, grid):

@@ -409,9 +409,9 @@ int ie_set_option(int32_t option, int32_t value);
  * The autotuner's decisions for a context as JSON text in buf (HOST, len bytes): one object per
  * (grid, precision, pass) with the grid's FFT lengths ("fft": [LX, LY, LZ]), the operator
  * microseconds of the shortest and the power-of-two lengths when IE_OPT_FFT_LENGTHS = 2 chose
- * between them ("lengths_us", zeros otherwise), the chosen variant and, per variant of that
- * pass, the measured microseconds of one whole operator application with the pass at that
- * variant.
+ * between them ("lengths_us", zeros otherwise), the chosen variant, the template name of the
+ * kernel that runs the pass ("kernel", as profilers print it) and, per variant of that pass,
+ * the measured microseconds of one whole operator application with the pass at that variant.
  * IE_EINVAL if buf is too small.
  */
 int ie_ctx_tuning(const ie_ctx* ctx, char* buf, int32_t len);

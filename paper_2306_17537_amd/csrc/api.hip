@@ -279,16 +279,16 @@ int ie_ctx_tuning(const ie_ctx* ctx, char* buf, int32_t len) {
     for (int pi = 0; pi < 2; ++pi) {
       if (!(ctx->prec_mask & (pi == 0 ? IE_FP64 : IE_MIXED))) continue;
       for (int q = 0; q < 5; ++q) {
-        char t[384];
+        char t[512];
         const float* u = p.tune_us[pi][q];
         snprintf(t, sizeof(t),
                  "%s{\"grid\": [%d, %d, %d], \"fft\": [%d, %d, %d], "
                  "\"lengths_us\": [%.2f, %.2f], \"precision\": \"%s\", "
-                 "\"pass\": \"%s\", \"variant\": %d, "
+                 "\"pass\": \"%s\", \"variant\": %d, \"kernel\": \"%s\", "
                  "\"us\": [%.2f, %.2f, %.2f, %.2f, %.2f, %.2f, %.2f, %.2f]}",
                  o.size() > 1 ? ", " : "", p.nx, p.ny, p.nz, p.LX, p.LY, p.LZ, p.len_us[0],
-                 p.len_us[1], pi == 0 ? "c128" : "c64", pass_names[q], p.var[pi][q], u[0], u[1],
-                 u[2], u[3], u[4], u[5], u[6], u[7]);
+                 p.len_us[1], pi == 0 ? "c128" : "c64", pass_names[q], p.var[pi][q],
+                 pass_kernel(p, pi, q).c_str(), u[0], u[1], u[2], u[3], u[4], u[5], u[6], u[7]);
         o += t;
       }
     }

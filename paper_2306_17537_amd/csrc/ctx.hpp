@@ -4,6 +4,7 @@
 
 #include <map>
 #include <memory>
+#include <string>
 #include <vector>
 
 #include "common.hpp"
@@ -95,6 +96,8 @@ int autotune(Plan& p, int prec_mask, const c128* tw64, const c64* tw32, hipStrea
 // summed).
 int operator_us(Plan& p, int prec_mask, const c128* tw64, const c64* tw32, hipStream_t s,
                 float& us);
+// Template name of the kernel that runs pass q of plan p at precision pi (0 float64, 1 complex64).
+std::string pass_kernel(const Plan& p, int pi, int q);
 // The autotuner's cache as a JSON file (host only).
 int tuning_save(const char* path);
 int tuning_load(const char* path);

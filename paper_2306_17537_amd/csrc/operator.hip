@@ -459,6 +459,44 @@ int autotune(Plan& p, int prec_mask, const c128* tw64, const c64* tw32, hipStrea
   return IE_OK;
 }
 
+// Template name of the kernel that runs pass q (0 zfwd, 1 yfwd, 2 xconv, 3 yinv, 4 zinv) of the
+// plan at precision pi (0 float64, 1 complex64) with its current variant, as profilers print it.
+namespace {
+template <typename T, int L>
+struct X2Fits {
+  static int run(int v) {
+    switch (v & 3) {
+      case 1: return GeoX2<T, L, 1>::FITS ? 1 : 0;
+      case 2: return GeoX2<T, L, 2>::FITS ? 1 : 0;
+      case 3: return GeoX2<T, L, 3>::FITS ? 1 : 0;
+      default: return GeoX2<T, L, 0>::FITS ? 1 : 0;
+    }
+  }
+};
+template <typename T>
+int x2_fits(int L, int v) {
+  IE_LEN_CASES(X2Fits, T, L, v);
+}
+}  // namespace
+
+std::string pass_kernel(const Plan& p, int pi, int q) {
+  const char* t = pi == 0 ? "double" : "float";
+  const int v = p.var[pi][q];
+  char b[96];
+  if (q == 0 || q == 4) {
+    snprintf(b, sizeof(b), "%s<%s, %d, %d>", q == 0 ? "k_zfwd" : "k_zinv", t, p.LZ, v & 3);
+  } else if (q == 1 || q == 3) {
+    snprintf(b, sizeof(b), "k_colfft<%s, %d, %s, %d, true>", t, p.LY, q == 3 ? "true" : "false",
+             p.LY < 16 ? 0 : v & 3);
+  } else if (p.LX < 16) {
+    snprintf(b, sizeof(b), "k_xconv<%s, %d, 0>", t, p.LX);
+  } else {
+    const bool two = v >= 4 && (pi == 0 ? x2_fits<double>(p.LX, v) : x2_fits<float>(p.LX, v)) == 1;
+    snprintf(b, sizeof(b), "%s<%s, %d, %d>", two ? "k_xconv2" : "k_xconv", t, p.LX, v & 3);
+  }
+  return b;
+}
+
 int operator_us(Plan& p, int prec_mask, const c128* tw64, const c64* tw32, hipStream_t s,
                 float& us) {
   us = 0;

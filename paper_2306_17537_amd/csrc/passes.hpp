@@ -202,9 +202,10 @@ __global__ void __launch_bounds__((Geo<T, L, V>::W * Geo<T, L, V>::TL))
 // ---------------------------------------------------------------------------------------
 // z column passes: all three components of W adjacent columns (y, x) of the xy plane, so that
 // the per-cell tensors apply on load (zfwd) and on store (zinv).  Variants: V & 1 doubles the
-// values per thread (4 -> 8 complex128, 8 -> 16 complex64); V & 2 doubles the columns per block
-// (256-byte row segments).  The three lines go through the FFT stages in lockstep (twiddles
-// loaded once per stage) and through LDS one after the other.
+// values per thread (4 -> 8 complex128, 8 -> 16 complex64); V & 2 caps the registers so that
+// four waves fit per SIMD (two blocks of the largest lengths per CU instead of one).  The three
+// lines go through the FFT stages in lockstep (twiddles read once per stage) and through LDS
+// one after the other.
 // ---------------------------------------------------------------------------------------
 template <typename T, int L, int V = 0>
 struct GeoC {
@@ -212,7 +213,8 @@ struct GeoC {
   static constexpr int E1 = (V & 1) ? 2 * Esm : Esm;
   static constexpr int E = reg_width(L, E1);
   static constexpr int TL = L / E;
-  static constexpr int Wc = (128 / int(sizeof(cx<T>))) * ((V & 2) ? 2 : 1);
+  static constexpr int WPE = (V & 2) ? 4 : 1;  // minimum waves per SIMD the registers allow
+  static constexpr int Wc = 128 / int(sizeof(cx<T>));
   static constexpr int Wm = (64 / TL) > Wc ? (64 / TL) : Wc;
   static constexpr int Wl = (65536 / int(L * sizeof(cx<T>))) < 1 ? 1 : (65536 / int(L * sizeof(cx<T>)));
   static constexpr int Wt = (1024 / TL) < 1 ? 1 : (1024 / TL);
@@ -239,7 +241,8 @@ __device__ __forceinline__ bool source_plane(const MvArgs<T>& a, int z) {
 
 // zfwd: J = M x on the source planes (zero elsewhere), zero-padded to LZ, FFT along z.
 template <typename T, int LZ, int V>
-__global__ void __launch_bounds__((GeoC<T, LZ, V>::THREADS)) k_zfwd(const MvArgs<T> a) {
+__global__ void __launch_bounds__((GeoC<T, LZ, V>::THREADS))
+    __attribute__((amdgpu_waves_per_eu(GeoC<T, LZ, V>::WPE, 8))) k_zfwd(const MvArgs<T> a) {
   using G = GeoC<T, LZ, V>;
   constexpr int E = G::E, TL = G::TL, W = G::W;
   __shared__ cx<T> lds[W * LZ];
@@ -300,7 +303,8 @@ __global__ void __launch_bounds__((GeoC<T, LZ, V>::THREADS)) k_zfwd(const MvArgs
 // zinv: inverse FFT along z, keep the output planes [out_z0, out_z1), combine
 // y = a_e e + a_x x - a_m (M x) + a_s S.
 template <typename T, int LZ, int V>
-__global__ void __launch_bounds__((GeoC<T, LZ, V>::THREADS)) k_zinv(const MvArgs<T> a) {
+__global__ void __launch_bounds__((GeoC<T, LZ, V>::THREADS))
+    __attribute__((amdgpu_waves_per_eu(GeoC<T, LZ, V>::WPE, 8))) k_zinv(const MvArgs<T> a) {
   using G = GeoC<T, LZ, V>;
   constexpr int E = G::E, TL = G::TL, W = G::W;
   __shared__ cx<T> lds[W * LZ];
@@ -388,11 +392,8 @@ __global__ void __launch_bounds__((GeoX<T, LX, V>::THREADS)) k_xconv(const MvArg
   using G = Geo<T, LX, V>;
   constexpr int E = G::ER, TL = G::TLR, NP = GeoX<T, LX, V>::NP;
   __shared__ cx<T> lds[2 * NP * G::LP];
-  __shared__ cx<T> twl[LX];
   const int b = blockIdx.z;
   if (retired(a, b)) return;
-  TwStage<T, LX, GeoX<T, LX, V>::THREADS> tws;
-  tws.load(a.tw, threadIdx.x);
   const int hx = LX / 2, hy = a.LY / 2, hz = a.LZ / 2;
   const int t = threadIdx.x % TL;
   const int rr = threadIdx.x / TL;  // row of the block: pair rr / 2, member rr % 2
@@ -419,10 +420,9 @@ __global__ void __launch_bounds__((GeoX<T, LX, V>::THREADS)) k_xconv(const MvArg
       v[c][m] = (m < E / 2 && live && i < a.nx) ? row[c * cs + i] : cx<T>{0, 0};
   }
   const typename G::RowLds addr{rr * G::LP};
-  tws.store(twl, threadIdx.x);
-  __syncthreads();
-  // the three lines in lockstep: each stage's twiddles are read once
-  fft_lines<T, LX, E, false, 3, true, LX>(v, lds, addr, t, twl);
+  // the three lines in lockstep: each stage's twiddles are read once (from the global table: a
+  // copy in LDS measured slower here, the block being one or two wavefronts)
+  fft_lines<T, LX, E, false, 3, true>(v, lds, addr, t, a.tw);
   const long gys = hx + 1;
   const long gzs = long(hy + 1) * gys;
   const long gcs = long(hz + 1) * gzs;
@@ -442,7 +442,7 @@ __global__ void __launch_bounds__((GeoX<T, LX, V>::THREADS)) k_xconv(const MvArg
     v[1][m] = gxy * j0 + gyy * j1 + gyz * j2;
     v[2][m] = gxz * j0 + gyz * j1 + gzz * j2;
   }
-  fft_lines<T, LX, E, true, 3, false, LX>(v, lds, addr, t, twl);
+  fft_lines<T, LX, E, true, 3>(v, lds, addr, t, a.tw);
   if (live) {
 #pragma unroll
     for (int m = 0; m < E / 2; ++m) {
@@ -462,16 +462,17 @@ __global__ void __launch_bounds__((GeoX<T, LX, V>::THREADS)) k_xconv(const MvArg
 // LDS for the tensor multiply, which the whole block does with one work item per (row pair,
 // kx): the six stored spectrum components are loaded once for both rows of the pair.  The
 // forward transforms skip the zero upper half of the padded lines, the inverse ones compute
-// only the kept lower half.  V & 1: 16 values per thread instead of 8; V & 2: two row pairs per
-// block.  Used where the block's LDS (six padded lines per pair and the twiddles) fits in the
-// 160 KB of a CU.
+// only the kept lower half.  V: 0 eight values per thread, 1 sixteen, 2 eight with the
+// registers capped for four waves per SIMD, 3 sixteen with two row pairs per block.  Used where
+// the block's LDS (six padded lines per pair and the twiddles) fits in the 160 KB of a CU.
 // ---------------------------------------------------------------------------------------
 template <typename T, int LX, int V>
 struct GeoX2 {
   static constexpr int E0 = (V & 1) ? 16 : 8;
   static constexpr int E = LX % 3 == 0 ? reg_width(LX, 0) : (LX < E0 ? LX : E0);
   static constexpr int TL = LX / E;
-  static constexpr int NP0 = (V & 2) ? 2 : 1;
+  static constexpr int WPE = V == 2 ? 4 : 1;  // minimum waves per SIMD the registers allow
+  static constexpr int NP0 = V == 3 ? 2 : 1;
   static constexpr int NPW = (64 + 6 * TL - 1) / (6 * TL);  // at least one wavefront
   static constexpr int NP1 = NP0 > NPW ? NP0 : NPW;
   static constexpr int NPM = 1024 / (6 * TL) < 1 ? 1 : 1024 / (6 * TL);
@@ -484,7 +485,8 @@ struct GeoX2 {
 };
 
 template <typename T, int LX, int V>
-__global__ void __launch_bounds__((GeoX2<T, LX, V>::THREADS)) k_xconv2(const MvArgs<T> a) {
+__global__ void __launch_bounds__((GeoX2<T, LX, V>::THREADS))
+    __attribute__((amdgpu_waves_per_eu(GeoX2<T, LX, V>::WPE, 8))) k_xconv2(const MvArgs<T> a) {
   using G = GeoX2<T, LX, V>;
   constexpr int E = G::E, TL = G::TL, NP = G::NP;
   __shared__ cx<T> lds[6 * NP * G::LP];

@@ -131,12 +131,14 @@ def lookup(kernel, profiles_dir=None):
     return None
 
 
-def trace_lookup(kernel, profiles_dir=None):
+def trace_lookup(kernel, profiles_dir=None, summary=None):
     """(average microseconds, calls, summary path) of `kernel` (exact template name) in the
-    committed kernel-trace summaries measured on the current kernel sources, or None."""
+    committed kernel-trace summaries measured on the current kernel sources (only the file
+    named `summary` if given: one kernel can serve several grids in a run), or None."""
     profiles_dir = profiles_dir or os.path.join(ROOT, "profiles")
     src = sources_hash()
-    for path in sorted(glob.glob(os.path.join(profiles_dir, "*.md"))):
+    pattern = summary if summary else "*.md"
+    for path in sorted(glob.glob(os.path.join(profiles_dir, pattern))):
         with open(path) as f:
             for line in f:
                 if not line.startswith("trace-json: "):

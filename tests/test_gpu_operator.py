@@ -287,6 +287,9 @@ def test_every_launch_variant_matches_oracle(torch, variant, n, pow2):
         assert all(r["variant"] == (variant if r["pass"] == "xconv" else variant & 3)
                    for r in tun)
         assert all(r["fft"] == [_fft_len(m, pow2) for m in n] for r in tun)
+        # the x pass runs one line per thread group from variant 4 on (its LDS always fits here)
+        xk = [r["kernel"] for r in tun if r["pass"] == "xconv"]
+        assert all(k.startswith("k_xconv2<" if variant >= 4 else "k_xconv<") for k in xk), xk
     finally:
         ie.ie_ctx_destroy(ctx)
 
