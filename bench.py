@@ -28,6 +28,7 @@ Printed: one JSON line with the contract fields plus
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -622,6 +623,7 @@ def learned_bench(ie, torch, ctx, s6, p, ref):
             out[name] = dict(s=round(float(np.median(ts)), 5), its=int(its), Ea_rel_err=err)
             if name == "learned":
                 out[name]["learned_start_won_judge"] = int(used)
+        out["gemm_roofline"] = nn_gemm_roofline(ie, torch, ctx, nn, s6, E0)
     finally:
         ie.ie_nn_destroy(nn)
     out["network"] = "3-D encoder-decoder, 4 levels, base 32 channels, BF16 MFMA (weights in " \
@@ -629,6 +631,38 @@ def learned_bench(ie, torch, ctx, s6, p, ref):
     out["gain"] = round(out["zero"]["s"] / out["learned"]["s"], 3)
     log(f"learned guess: {out}")
     return out
+
+
+def nn_gemm_roofline(ie, torch, ctx, nn, s6, E0):
+    """The network's convolution GEMMs (BF16 16x16x32 MFMA) in one inference on the 64^3 model,
+    timed with HIP events per launch: dense flops (2 M N K per launch) per second against the
+    2.5 PFLOP/s dense BF16 peak, and the share of the inference spent in im2col."""
+    from paper_2306_17537_amd import guess
+    x = torch.zeros_like(E0)
+    ie.ie_profile_begin()
+    guess.solve_learned_start(ctx, nn, s6, E0, x, restart=CHOSEN_RESTART)
+    prof = ie.ie_profile_end()
+    gem = [k for k in prof if k["name"].startswith("nn_gemm")]
+    if not gem:
+        return None
+    flops = 0.0
+    for k in gem:
+        m = re.search(r"M(\d+)xN(\d+)xK(\d+)", k["name"])
+        flops += 2.0 * int(m.group(1)) * int(m.group(2)) * int(m.group(3)) * k["launches"]
+    t = sum(k["total_ms"] for k in gem) * 1e-3
+    nn_t = sum(k["total_ms"] for k in prof if k["name"].startswith("nn_")) * 1e-3
+    im2col = sum(k["total_ms"] for k in prof if k["name"].startswith("nn_im2col")) * 1e-3
+    byts = sum(k["bytes_per_launch"] * k["launches"] for k in gem)
+    big = max(gem, key=lambda k: k["total_ms"])
+    # the materialised im2col operand (M x 27 C_in BF16) makes these GEMMs HBM-bound: their
+    # arithmetic intensity (flops / operand bytes) is far below the BF16 ridge (2.5e15 / 8e12)
+    return {"bound": "mfma", "achieved": round(flops / t / 1e12, 2), "peak": 2500.0,
+            "unit": "TFLOP/s", "frac": round(flops / t / 1e12 / 2500.0, 4),
+            "flop_per_byte": round(flops / byts, 1),
+            "hbm_achieved_gbs": round(byts / t / 1e9, 1),
+            "hbm_frac": round(byts / t / 1e9 / HBM_PEAK_GBS, 4),
+            "gemm_launches": sum(k["launches"] for k in gem), "gemm_ms": round(1e3 * t, 3),
+            "largest": big["name"], "im2col_share_of_network": round(im2col / nn_t, 3)}
 
 
 def batch_bench(ie, torch):

@@ -1,6 +1,6 @@
 // Learned initial guess: a 3-D convolutional encoder-decoder trained and run with hand-written
 // kernels.  Convolutions are im2col + a BF16 MFMA GEMM with float32 accumulation
-// (v_mfma_f32_16x16x16_bf16); backward passes use the same GEMM (data gradient through the
+// (v_mfma_f32_16x16x32_bf16); backward passes use the same GEMM (data gradient through the
 // transposed weights, weight gradient with split K) and gather-form col2im (no atomics).
 // Activations are channels-last BF16; master weights, gradients and Adam moments are float32.
 //
@@ -26,7 +26,7 @@ using u16 = uint16_t;
 namespace ie {
 namespace nn {
 
-typedef short s4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 __host__ __device__ inline float bf2f(u16 h) {
@@ -53,17 +53,18 @@ __host__ __device__ inline u16 f2bf(float f) {  // round to nearest even
 // A(m, k) = A[m sam + k sak], B(k, n) = B[k sbk + n sbn]; out of range reads are zero.
 // blockIdx.z handles K range [z kchunk, (z+1) kchunk).  Output: float32 partials
 // Cf[z cpart + m scm + n scn] (split K) or, with Cb, BF16 with optional bias and ReLU.
-// Tile 64 x 64 x 32, four wavefronts each owning a 32 x 32 quarter (2 x 2 MFMA tiles).
+// Tile 64 x 64 x 32, four wavefronts each owning a 32 x 32 quarter (2 x 2 MFMA tiles of
+// 16 x 16 x 32: lane l supplies row (or column) l % 16 at k = 8 (l / 16) .. 8 (l / 16) + 7).
 // ---------------------------------------------------------------------------------------
-constexpr int GBM = 64, GBN = 64, GBK = 32, GPAD = 4;
+constexpr int GBM = 64, GBN = 64, GBK = 32, GPAD = 8;  // rows of 80 bytes: 16-byte aligned reads
 
 template <bool A_KC, bool B_NC>
 __global__ void __launch_bounds__(256)
     k_gemm(const u16* __restrict__ A, long sam, long sak, const u16* __restrict__ B, long sbk,
            long sbn, int M, int N, int K, int kchunk, float* __restrict__ Cf, long scm, long scn,
            long cpart, u16* __restrict__ Cb, const float* __restrict__ bias, int relu) {
-  __shared__ u16 As[GBM][GBK + GPAD];
-  __shared__ u16 Bs[GBN][GBK + GPAD];
+  __shared__ __align__(16) u16 As[GBM][GBK + GPAD];
+  __shared__ __align__(16) u16 Bs[GBN][GBK + GPAD];
   const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
   const int kb = blockIdx.z * kchunk;
   const int ke = min(K, kb + kchunk);
@@ -104,20 +105,18 @@ __global__ void __launch_bounds__(256)
       Bs[nn][kk] = (gn < N && gk < ke) ? B[long(gk) * sbk + long(gn) * sbn] : u16(0);
     }
     __syncthreads();
+    static_assert(GBK == 32, "one 16x16x32 MFMA per K tile");
+    bf8 a[2], b[2];
 #pragma unroll
-    for (int ks = 0; ks < GBK; ks += 16) {
-      s4 a[2], b[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        a[i] = *reinterpret_cast<const s4*>(&As[wm + i * 16 + (lane & 15)][ks + 4 * (lane >> 4)]);
-        b[i] = *reinterpret_cast<const s4*>(&Bs[wn + i * 16 + (lane & 15)][ks + 4 * (lane >> 4)]);
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+    for (int i = 0; i < 2; ++i) {
+      a[i] = *reinterpret_cast<const bf8*>(&As[wm + i * 16 + (lane & 15)][8 * (lane >> 4)]);
+      b[i] = *reinterpret_cast<const bf8*>(&Bs[wn + i * 16 + (lane & 15)][8 * (lane >> 4)]);
     }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     __syncthreads();
   }
   // D layout of the 16x16 tile: lane l holds rows 4 (l / 16) + e, e = 0..3, column l % 16
@@ -454,7 +453,9 @@ int gemm(hipStream_t s, bool akc, bool bnc, const u16* A, long sam, long sak, co
   const int kchunk = ((K + splits - 1) / splits + GBK - 1) / GBK * GBK;
   const int z = (K + kchunk - 1) / kchunk;
   dim3 grid(ceil_div(M, GBM), ceil_div(N, GBN), z);
-  ProfScope ps(s, "nn_gemm", "bf16", 2.0 * (double(M) * K + double(K) * N) + 4.0 * double(M) * N);
+  char tag[64];  // the shape, from which a profile derives the flops (2 M N K)
+  snprintf(tag, sizeof(tag), "bf16 M%dxN%dxK%d", M, N, K);
+  ProfScope ps(s, "nn_gemm", tag, 2.0 * (double(M) * K + double(K) * N) + 4.0 * double(M) * N);
 #define IE_GEMM(AK, BN)                                                                          \
   hipLaunchKernelGGL((k_gemm<AK, BN>), grid, dim3(256), 0, s, A, sam, sak, B, sbk, sbn, M, N, K, \
                      kchunk, Cf, scm, scn, cpart, Cb, bias, relu)
