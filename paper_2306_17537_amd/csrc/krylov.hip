@@ -19,15 +19,16 @@ constexpr int PWD = 2 * MAXM + 1;  // doubles per block partial (at most 2 MAXM 
 
 enum Fin { FIN_NONE = 0, FIN_H = 1, FIN_GIVENS = 2, FIN_CYCLE = 3, FIN_BNORM = 4, FIN_HG = 5 };
 
-// Blocks of a reduction pass: about eight elements per thread, at most RED_MAX blocks (two per
-// CU).  Few blocks keep the per-block reduction tail small; the passes unroll their element
+// Blocks of a reduction pass: about eight elements per thread, at most RED_MAX blocks (four per
+// CU, so that the register-heavy passes of the long restarts still have waves to switch
+// between).  Few blocks keep the per-block reduction tail small; the passes unroll their element
 // loop so that a wave still has many loads in flight.  The finalisation sums at most RED_MAX
-// partials per slot.
-constexpr int RED_MAX = 512;
-int red_grid(long n) {
+// partials per slot.  The plain update pass (no reduction) takes at most UPD_MAX blocks.
+constexpr int RED_MAX = 1024, UPD_MAX = 512;
+int red_grid(long n, int cap = RED_MAX) {
   long g = (n + RB * 8 - 1) / (RB * 8);
   if (g < 1) g = 1;
-  if (g > RED_MAX) g = RED_MAX;
+  if (g > cap) g = cap;
   return int(g);
 }
 
@@ -244,8 +245,14 @@ __global__ void __launch_bounds__(RB)
   for (int k = 0; k < NV; ++k) acc[k] = 0;
   // U elements per thread and loop pass, all their loads issued before any is used, so that
   // each wave keeps U (count + 1) loads in flight; indices past n are clamped to a valid
-  // element, their results masked and their stores skipped.
-  constexpr int U = (sizeof(TA) == 4 && sizeof(TW) == 4) ? 4 : 2;
+  // element, their results masked and their stores skipped.  A reduction pass takes U as large
+  // as keeps the loaded values within about 96 registers (its accumulators need the rest); the
+  // plain update pass takes 2 (complex128) or 4 (complex64), measured faster at the lower
+  // occupancy that costs for the long restarts.
+  constexpr int VG = int(sizeof(cx<TA>)) / 4;  // registers per loaded value
+  constexpr int U0 = 96 / (VG * (CM + 1));
+  constexpr int UR = U0 < 1 ? 1 : (U0 > 4 ? 4 : U0);
+  constexpr int U = (UPD && !DOTS && !NRM) ? (VG == 2 ? 4 : 2) : UR;
   const long stride = long(gridDim.x) * RB;
   for (long e0 = long(blockIdx.x) * RB + threadIdx.x; e0 < n; e0 += U * stride) {
     long ec[U];
@@ -638,6 +645,7 @@ static int gmres_impl(Plan& p, const OpDesc& op, const c128* rhs, c128* x, int b
   const int act_bs = int(sizeof(GmState) / sizeof(int));
   const long nv_bs = long(sizeof(GmState) / sizeof(double));
   const dim3 vgrid(G, 1, batch);
+  const dim3 ugrid(red_grid(n, UPD_MAX), 1, batch);  // plain update passes
   for (int b = 0; b < batch; ++b) res[b] = GmResult{};
   char tgb[96];
   snprintf(tgb, sizeof(tgb), "%s n%ld b%d", sizeof(TA) == 4 ? "c64" : "c128", n, batch);
@@ -712,7 +720,7 @@ static int gmres_impl(Plan& p, const OpDesc& op, const c128* rhs, c128* x, int b
             "orth_dots_norm", tg, nb * sa * (j + 2), vgrid, s, V, n, vbs, w1, vbs, n, j + 1, j, 1,
             st, part, flags, batch, 0.0, 0)));
         IE_TRY((launch_orth<TA, TA, true, false, false, FIN_NONE>(
-            "orth_upd", tg, nb * sa * (j + 3), vgrid, s, V, n, vbs, w1, vbs, n, j + 1, j, 0, st,
+            "orth_upd", tg, nb * sa * (j + 3), ugrid, s, V, n, vbs, w1, vbs, n, j + 1, j, 0, st,
             part, flags, batch, 0.0, 0)));
       } else {
         // CGS2: h = V^H w (+ H column); w -= V h with the second pass's dots added to the
