@@ -634,15 +634,16 @@ def learned_bench(ie, torch, ctx, s6, p, ref):
 
 
 def nn_gemm_roofline(ie, torch, ctx, nn, s6, E0):
-    """The network's convolution GEMMs (BF16 16x16x32 MFMA) in one inference on the 64^3 model,
-    timed with HIP events per launch: dense flops (2 M N K per launch) per second against the
-    2.5 PFLOP/s dense BF16 peak, and the share of the inference spent in im2col."""
+    """The network's convolutions (BF16 16x16x32 MFMA; implicit GEMMs where the channel counts
+    allow, else im2col + GEMM) in one inference on the 64^3 model, timed with HIP events per
+    launch: dense flops (2 M N K per launch) per second against the 2.5 PFLOP/s dense BF16 peak,
+    and the share of the inference spent in im2col."""
     from paper_2306_17537_amd import guess
     x = torch.zeros_like(E0)
     ie.ie_profile_begin()
     guess.solve_learned_start(ctx, nn, s6, E0, x, restart=CHOSEN_RESTART)
     prof = ie.ie_profile_end()
-    gem = [k for k in prof if k["name"].startswith("nn_gemm")]
+    gem = [k for k in prof if k["name"].startswith(("nn_gemm", "nn_conv"))]
     if not gem:
         return None
     flops = 0.0
@@ -654,8 +655,8 @@ def nn_gemm_roofline(ie, torch, ctx, nn, s6, E0):
     im2col = sum(k["total_ms"] for k in prof if k["name"].startswith("nn_im2col")) * 1e-3
     byts = sum(k["bytes_per_launch"] * k["launches"] for k in gem)
     big = max(gem, key=lambda k: k["total_ms"])
-    # the materialised im2col operand (M x 27 C_in BF16) makes these GEMMs HBM-bound: their
-    # arithmetic intensity (flops / operand bytes) is far below the BF16 ridge (2.5e15 / 8e12)
+    # bytes: the operands as read from memory (the activations once for an implicit GEMM, the
+    # materialised M x 27 C_in matrix otherwise), weights and output
     return {"bound": "mfma", "achieved": round(flops / t / 1e12, 2), "peak": 2500.0,
             "unit": "TFLOP/s", "frac": round(flops / t / 1e12 / 2500.0, 4),
             "flop_per_byte": round(flops / byts, 1),

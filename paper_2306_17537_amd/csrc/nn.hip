@@ -140,6 +140,132 @@ __global__ void __launch_bounds__(256)
       }
 }
 
+// ---------------------------------------------------------------------------------------
+// Convolution as an implicit GEMM (inference): out(m, n) = sum_k A(m, k) W(k, n) with A(m, k)
+// the im2col value of k_im2col below, gathered while the A tile is loaded instead of being
+// written to memory first.  k = tap C + ch with C = c1 + c2 channels (ch < c1 from in1, read at
+// half resolution when up1; the rest from in2); each thread loads eight consecutive channels of
+// one tap as one 16-byte read, so c1 and c2 must be multiples of 8.  W is [K][co] BF16 (as the
+// weights are stored).  Same tile, MFMA and epilogue as k_gemm (BF16 output with bias and ReLU,
+// or float32).  blockIdx.z splits K into chunks of kchunk (a multiple of the K tile): with
+// more than one split every block writes float32 partials to Cp[z][m][n] instead, summed by
+// k_splitk_out (the deep layers have few voxels and long K).
+// ---------------------------------------------------------------------------------------
+template <int TAPS>
+__global__ void __launch_bounds__(256)
+    k_conv_igemm(const u16* __restrict__ in1, int c1, int up1, const u16* __restrict__ in2,
+                 int c2, int nb, int Z, int Y, int X, const u16* __restrict__ W, int co,
+                 int kchunk, float* __restrict__ Cp, float* __restrict__ Cf,
+                 u16* __restrict__ Cb, const float* __restrict__ bias, int relu) {
+  __shared__ __align__(16) u16 As[GBM][GBK + GPAD];
+  __shared__ __align__(16) u16 Bs[GBN][GBK + GPAD];
+  const int C = c1 + c2, K = TAPS * C;
+  const long M = long(nb) * Z * Y * X;
+  const long m0 = long(blockIdx.x) * GBM;
+  const int n0 = blockIdx.y * GBN;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  // this thread's A chunk: row mm of the tile, channels 8 kc .. 8 kc + 7 of each K tile
+  const int mm = t >> 2, kc = t & 3;
+  const long m = m0 + mm;
+  const bool mok = m < M;
+  const long mc = mok ? m : 0;
+  const int x = int(mc % X), y = int((mc / X) % Y), z = int((mc / (long(X) * Y)) % Z);
+  const int b = int(mc / (long(X) * Y * Z));
+  const int kb = blockIdx.z * kchunk;
+  const int ke = min(K, kb + kchunk);
+  f4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = kb; k0 < ke; k0 += GBK) {
+    {
+      const int k = k0 + 8 * kc;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (mok && k < ke) {
+        const int tap = k / C, ch = k % C;
+        int zz = z, yy = y, xx = x;
+        if (TAPS == 27) {
+          zz += tap / 9 - 1;
+          yy += (tap / 3) % 3 - 1;
+          xx += tap % 3 - 1;
+        }
+        if (zz >= 0 && zz < Z && yy >= 0 && yy < Y && xx >= 0 && xx < X) {
+          const u16* src;
+          if (ch < c1)
+            src = up1 ? in1 + (((long(b) * (Z / 2) + zz / 2) * (Y / 2) + yy / 2) * (X / 2) +
+                               xx / 2) * c1 + ch
+                      : in1 + (((long(b) * Z + zz) * Y + yy) * X + xx) * c1 + ch;
+          else
+            src = in2 + (((long(b) * Z + zz) * Y + yy) * X + xx) * c2 + (ch - c1);
+          v = *reinterpret_cast<const uint4*>(src);
+        }
+      }
+      *reinterpret_cast<uint4*>(&As[mm][8 * kc]) = v;
+    }
+#pragma unroll
+    for (int i = 0; i < (GBN * GBK) / 256; ++i) {
+      const int idx = t + i * 256;
+      const int kk = idx / GBN, nn = idx % GBN;
+      const int gn = n0 + nn, gk = k0 + kk;
+      Bs[nn][kk] = (gn < co && gk < ke) ? W[long(gk) * co + gn] : u16(0);
+    }
+    __syncthreads();
+    bf8 a[2], bv[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      a[i] = *reinterpret_cast<const bf8*>(&As[wm + i * 16 + (lane & 15)][8 * (lane >> 4)]);
+      bv[i] = *reinterpret_cast<const bf8*>(&Bs[wn + i * 16 + (lane & 15)][8 * (lane >> 4)]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bv[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const long mo = m0 + wm + i * 16 + 4 * (lane >> 4) + e;
+        const int n = n0 + wn + j * 16 + (lane & 15);
+        if (mo >= M || n >= co) continue;
+        float v = acc[i][j][e];
+        if (Cp != nullptr) {
+          Cp[(long(blockIdx.z) * M + mo) * co + n] = v;
+        } else if (Cb != nullptr) {
+          if (bias) v += bias[n];
+          if (relu) v = fmaxf(v, 0.f);
+          Cb[mo * co + n] = f2bf(v);
+        } else {
+          Cf[mo * co + n] = v;
+        }
+      }
+}
+
+// out = sum_z part[z] (fixed order) for n values of co columns, then bias and ReLU and BF16
+// (Cb) or float32 as is (Cf)
+__global__ void k_splitk_out(const float* __restrict__ part, int splits, long n, int co,
+                             float* __restrict__ Cf, u16* __restrict__ Cb,
+                             const float* __restrict__ bias, int relu) {
+  for (long i = long(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += long(gridDim.x) * blockDim.x) {
+    float v = 0.f;
+    for (int z = 0; z < splits; ++z) v += part[z * n + i];
+    if (Cb != nullptr) {
+      if (bias) v += bias[i % co];
+      if (relu) v = fmaxf(v, 0.f);
+      Cb[i] = f2bf(v);
+    } else {
+      Cf[i] = v;
+    }
+  }
+}
+
 // out[i] (+)= sum_z part[z][i], fixed order
 __global__ void k_splitk_sum(const float* __restrict__ part, long cpart, int splits, long n,
                              float* __restrict__ out, int accumulate) {
@@ -509,18 +635,54 @@ int conv_fwd(ie_nn* n, NnLayer& y, const u16* in1, int c1, int up1, const u16* i
   y.X = X;
   y.M = long(n->nb) * Z * Y * X;
   const long K = long(y.taps) * (c1 + c2);
+  const u16* W = n->p16.as<u16>() + y.w_off;
+  const float* bias = n->p32.as<float>() + y.b_off;
+  if (!out32) IE_TRY(y.out.ensure(sizeof(u16) * y.M * y.co));
+  if (!n->keep_cols && c1 % 8 == 0 && c2 % 8 == 0 && (y.taps == 27 || y.taps == 1)) {
+    // inference: implicit GEMM, no im2col buffer
+    char tag[64];
+    snprintf(tag, sizeof(tag), "bf16 M%ldxN%dxK%ld", y.M, y.co, K);
+    ProfScope ps(s, "nn_conv", tag, 2.0 * (double(y.M) * (c1 + c2) + double(K) * y.co) +
+                                        (out32 ? 4.0 : 2.0) * double(y.M) * y.co);
+    // split K until about 1024 blocks run, keeping at least four K tiles per split
+    const long tiles = long(ceil_div(y.M, GBM)) * ceil_div(y.co, GBN);
+    const int ktiles = ceil_div(K, GBK);
+    int splits = int(std::min<long>(std::max<long>(1, (1024 + tiles - 1) / tiles), ktiles / 4));
+    splits = std::max(1, std::min(splits, 16));
+    const int kchunk = ceil_div(ktiles, splits) * GBK;
+    splits = ceil_div(K, kchunk);
+    float* part = nullptr;
+    if (splits > 1) {
+      IE_TRY(n->part.ensure(sizeof(float) * splits * y.M * y.co));
+      part = n->part.as<float>();
+    }
+    u16* o16 = out32 ? nullptr : y.out.as<u16>();
+    const float* bo = out32 ? nullptr : bias;
+    const int ro = out32 ? 0 : y.relu;
+    dim3 grid(unsigned(ceil_div(y.M, GBM)), unsigned(ceil_div(y.co, GBN)), unsigned(splits));
+    if (y.taps == 27)
+      hipLaunchKernelGGL(k_conv_igemm<27>, grid, dim3(256), 0, s, in1, c1, up1, in2, c2, n->nb, Z,
+                         Y, X, W, y.co, kchunk, part, out32, o16, bo, ro);
+    else
+      hipLaunchKernelGGL(k_conv_igemm<1>, grid, dim3(256), 0, s, in1, c1, up1, in2, c2, n->nb, Z,
+                         Y, X, W, y.co, kchunk, part, out32, o16, bo, ro);
+    IE_LAUNCH_CHECK();
+    if (splits > 1) {
+      hipLaunchKernelGGL(k_splitk_out, dim3(grid1(y.M * y.co)), dim3(256), 0, s, part, splits,
+                         y.M * y.co, y.co, out32, o16, bo, ro);
+      IE_LAUNCH_CHECK();
+    }
+    return IE_OK;
+  }
   DevBuf& colb = n->keep_cols ? y.col : n->icol;
   IE_TRY(colb.ensure(sizeof(u16) * y.M * K));
   u16* col = colb.as<u16>();
-  if (!out32) IE_TRY(y.out.ensure(sizeof(u16) * y.M * y.co));
   {
     ProfScope ps(s, "nn_im2col", "", 2.0 * y.M * K);
     hipLaunchKernelGGL(k_im2col, dim3(grid1(y.M * K)), dim3(256), 0, s, in1, c1, up1, in2, c2,
                        n->nb, Z, Y, X, y.taps, col);
     IE_LAUNCH_CHECK();
   }
-  const u16* W = n->p16.as<u16>() + y.w_off;
-  const float* bias = n->p32.as<float>() + y.b_off;
   if (out32) {  // head: float32 output, bias added by the caller
     gemm(s, true, true, col, K, 1, W, y.co, 1, int(y.M), y.co, int(K), 1, out32, y.co, 1, 0,
          nullptr, nullptr, 0);
