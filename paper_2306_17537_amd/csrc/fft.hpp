@@ -185,13 +185,6 @@ struct LdsPadded {  // line-major, one pad slot every 16 positions (conflict-fre
   __device__ __forceinline__ int operator()(int p) const { return base + p + (p >> 4); }
   static constexpr __host__ __device__ int padded_len(int L) { return L + L / 16; }
 };
-// line-major, one pad slot every 4 positions (stride-4 writes of a radix-4 first stage land on
-// distinct banks), lines offset by half a bank row more
-struct LdsPadded4 {
-  int base;
-  __device__ __forceinline__ int operator()(int p) const { return base + p + (p >> 2); }
-  static constexpr __host__ __device__ int padded_len(int L) { return L + L / 4 + 16; }
-};
 
 // ZIN: the positions L/2 .. L-1 are zero on entry (registers E/2 .. E-1), so the first stage
 // takes the zero upper half of each butterfly's inputs into account.  TWL: length of the

@@ -116,7 +116,12 @@ struct ZfwdL {
     const double by = double(batch) * (double(source_planes(a)) * plane *
                                        (3 * cs + (a.M ? 6 * rs : 0)) + double(L) * plane * 3 * cs);
     ProfScope ps(s, "zfwd", shape_tag(int(cs), a.LX, a.LY, a.LZ, a.nz, batch).c_str(), by);
-    hipLaunchKernelGGL((k_zfwd<T, L, V>), grid, dim3(G::THREADS), 0, s, a);
+    if constexpr ((V & 2) != 0) {  // one component per block
+      dim3 grid3(3 * grid.x, 1, batch);
+      hipLaunchKernelGGL((k_zfwd1<T, L, V>), grid3, dim3(G::THREADS), 0, s, a);
+    } else {
+      hipLaunchKernelGGL((k_zfwd<T, L, V>), grid, dim3(G::THREADS), 0, s, a);
+    }
     IE_LAUNCH_CHECK();
     return IE_OK;
   }
@@ -138,7 +143,12 @@ struct ZinvL {
     const double by = double(batch) * (double(L) * plane * 3 * cs +
                                        double(a.out_z1 - a.out_z0) * plane * per);
     ProfScope ps(s, "zinv", shape_tag(int(cs), a.LX, a.LY, a.LZ, a.nz, batch).c_str(), by);
-    hipLaunchKernelGGL((k_zinv<T, L, V>), grid, dim3(G::THREADS), 0, s, a);
+    if constexpr ((V & 2) != 0) {  // one component per block
+      dim3 grid3(3 * grid.x, 1, batch);
+      hipLaunchKernelGGL((k_zinv1<T, L, V>), grid3, dim3(G::THREADS), 0, s, a);
+    } else {
+      hipLaunchKernelGGL((k_zinv<T, L, V>), grid, dim3(G::THREADS), 0, s, a);
+    }
     IE_LAUNCH_CHECK();
     return IE_OK;
   }
@@ -484,7 +494,8 @@ std::string pass_kernel(const Plan& p, int pi, int q) {
   const int v = p.var[pi][q];
   char b[96];
   if (q == 0 || q == 4) {
-    snprintf(b, sizeof(b), "%s<%s, %d, %d>", q == 0 ? "k_zfwd" : "k_zinv", t, p.LZ, v & 3);
+    snprintf(b, sizeof(b), "%s%s<%s, %d, %d>", q == 0 ? "k_zfwd" : "k_zinv", (v & 2) ? "1" : "",
+             t, p.LZ, v & 3);
   } else if (q == 1 || q == 3) {
     snprintf(b, sizeof(b), "k_colfft<%s, %d, %s, %d, true>", t, p.LY, q == 3 ? "true" : "false",
              p.LY < 16 ? 0 : v & 3);
