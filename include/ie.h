@@ -384,8 +384,9 @@ int ie_receivers(ie_ctx* ctx, const double* sigma6, const ie_source* src, int32_
  *                  grid for the process); 0 uses the default variant.  Affects contexts set up
  *                  afterwards.
  *   IE_OPT_FORCE_VARIANT: -1 (default) leaves the choice to the autotuner; 0 .. 7 puts every
- *                  pass of contexts set up afterwards on that variant (the column passes, which
- *                  have four variants, take it modulo 4): for tests that cover every variant.
+ *                  pass of contexts set up afterwards on that variant (the y passes, which have
+ *                  four variants, take it modulo 4, the z passes, which have two, modulo 2): for
+ *                  tests that cover every variant.
  *   IE_OPT_GROUP_THREADS: 1 (default) lets ie_dd_solve advance the problems of different
  *                  contexts at the same time (one host thread and one stream per context, joined
  *                  to the caller's stream); 0 solves the groups one after the other.  Results are

@@ -134,10 +134,12 @@ bool g_autotune = true;
 int g_force_variant = -1;
 int g_fft_lengths = 0;  // 0 shortest, 1 powers of two, 2 the faster of the two by timing
 
-// every pass of the plan on one variant (the x pass has eight, the column passes four)
+// every pass of the plan on one variant (the x pass has eight, the y passes four, the z passes
+// two)
 void force_variant(Plan& p, int v) {
   for (int pi = 0; pi < 2; ++pi)
-    for (int q = 0; q < 5; ++q) p.var[pi][q] = int8_t(q == 2 ? v : (v & 3));
+    for (int q = 0; q < 5; ++q)
+      p.var[pi][q] = int8_t(q == 2 ? v : (q == 1 || q == 3 ? (v & 3) : (v & 1)));
 }
 
 // Plan of one grid shape with its Green spectrum and launch variants, at the FFT lengths the

@@ -87,12 +87,10 @@ int fft_len(int n, bool pow2) {
     }                                                                    \
   }
 
-// Calls F<T, L>::template go<V>(args...) for the plan's variant v of a pass with four.
-#define IE_COL_VARIANTS(v, ...)                                          \
-  switch (v & 3) {                                                       \
+// Calls F<T, L>::template go<V>(args...) for the plan's variant v of a z pass (two variants).
+#define IE_Z_VARIANTS(v, ...)                                            \
+  switch (v & 1) {                                                       \
     case 1: return go<1>(__VA_ARGS__);                                   \
-    case 2: return go<2>(__VA_ARGS__);                                   \
-    case 3: return go<3>(__VA_ARGS__);                                   \
     default: return go<0>(__VA_ARGS__);                                  \
   }
 
@@ -116,17 +114,12 @@ struct ZfwdL {
     const double by = double(batch) * (double(source_planes(a)) * plane *
                                        (3 * cs + (a.M ? 6 * rs : 0)) + double(L) * plane * 3 * cs);
     ProfScope ps(s, "zfwd", shape_tag(int(cs), a.LX, a.LY, a.LZ, a.nz, batch).c_str(), by);
-    if constexpr ((V & 2) != 0) {  // one component per block
-      dim3 grid3(3 * grid.x, 1, batch);
-      hipLaunchKernelGGL((k_zfwd1<T, L, V>), grid3, dim3(G::THREADS), 0, s, a);
-    } else {
-      hipLaunchKernelGGL((k_zfwd<T, L, V>), grid, dim3(G::THREADS), 0, s, a);
-    }
+    hipLaunchKernelGGL((k_zfwd<T, L, V>), grid, dim3(G::THREADS), 0, s, a);
     IE_LAUNCH_CHECK();
     return IE_OK;
   }
   static int run(int v, const MvArgs<T>& a, int batch, hipStream_t s) {
-    IE_COL_VARIANTS(v, a, batch, s);
+    IE_Z_VARIANTS(v, a, batch, s);
   }
 };
 template <typename T, int L>
@@ -143,17 +136,12 @@ struct ZinvL {
     const double by = double(batch) * (double(L) * plane * 3 * cs +
                                        double(a.out_z1 - a.out_z0) * plane * per);
     ProfScope ps(s, "zinv", shape_tag(int(cs), a.LX, a.LY, a.LZ, a.nz, batch).c_str(), by);
-    if constexpr ((V & 2) != 0) {  // one component per block
-      dim3 grid3(3 * grid.x, 1, batch);
-      hipLaunchKernelGGL((k_zinv1<T, L, V>), grid3, dim3(G::THREADS), 0, s, a);
-    } else {
-      hipLaunchKernelGGL((k_zinv<T, L, V>), grid, dim3(G::THREADS), 0, s, a);
-    }
+    hipLaunchKernelGGL((k_zinv<T, L, V>), grid, dim3(G::THREADS), 0, s, a);
     IE_LAUNCH_CHECK();
     return IE_OK;
   }
   static int run(int v, const MvArgs<T>& a, int batch, hipStream_t s) {
-    IE_COL_VARIANTS(v, a, batch, s);
+    IE_Z_VARIANTS(v, a, batch, s);
   }
 };
 template <typename T, int L>
@@ -425,7 +413,7 @@ static int tune_one(Plan& p, const cx<T>* tw, hipStream_t s, int8_t var[5],
   for (int pass = 0; pass < 5; ++pass) {
     float best = 0;
     int8_t keep = 0;
-    const int nv = pass == 2 ? kRowVariants : kVariants;
+    const int nv = pass == 2 ? kRowVariants : (pass == 1 || pass == 3 ? kVariants : kZVariants);
     for (int v = 0; v < nv; ++v) {
       pv[pass] = int8_t(v);
       IE_TRY(tm.time(us[pass][v]));
@@ -494,8 +482,7 @@ std::string pass_kernel(const Plan& p, int pi, int q) {
   const int v = p.var[pi][q];
   char b[96];
   if (q == 0 || q == 4) {
-    snprintf(b, sizeof(b), "%s%s<%s, %d, %d>", q == 0 ? "k_zfwd" : "k_zinv", (v & 2) ? "1" : "",
-             t, p.LZ, v & 3);
+    snprintf(b, sizeof(b), "%s<%s, %d, %d>", q == 0 ? "k_zfwd" : "k_zinv", t, p.LZ, v & 1);
   } else if (q == 1 || q == 3) {
     snprintf(b, sizeof(b), "k_colfft<%s, %d, %s, %d, true>", t, p.LY, q == 3 ? "true" : "false",
              p.LY < 16 ? 0 : v & 3);
@@ -683,7 +670,7 @@ int tuning_load(const char* path) {
       if (grid[a] < 1 || grid[a] > 512 || !valid_len(grid[a], fft[a]))
         return fail(IE_EINVAL, "%s: entry %zu: grid or FFT length out of range", path, entries.size());
     for (int q = 0; q < 5; ++q) {
-      if (var[q] < 0 || var[q] >= (q == 2 ? kRowVariants : kVariants))
+      if (var[q] < 0 || var[q] >= (q == 2 ? kRowVariants : (q == 1 || q == 3 ? kVariants : kZVariants)))
         return fail(IE_EINVAL, "%s: entry %zu: variant out of range", path, entries.size());
       e.var[q] = int8_t(var[q]);
     }

@@ -97,7 +97,8 @@ constexpr int reg_width(int L, int e2) {
   return L % 3 == 0 ? (L < 12 ? L : 12) : (L < e2 ? L : e2);
 }
 
-constexpr int kVariants = 4;
+constexpr int kVariants = 4;   // y passes
+constexpr int kZVariants = 2;  // z passes
 constexpr int kRowVariants = 8;
 
 template <typename T, int L, int V = 0>
@@ -198,8 +199,7 @@ __global__ void __launch_bounds__((Geo<T, L, V>::W * Geo<T, L, V>::TL))
 // ---------------------------------------------------------------------------------------
 // z column passes: all three components of W adjacent columns (y, x) of the xy plane, so that
 // the per-cell tensors apply on load (zfwd) and on store (zinv).  Variants: V & 1 doubles the
-// values per thread (4 -> 8 complex128, 8 -> 16 complex64).  V & 2 selects the
-// one-component form (k_zfwd1, k_zinv1 below); otherwise the three lines go through the FFT
+// values per thread (4 -> 8 complex128, 8 -> 16 complex64).  The three lines go through the FFT
 // stages in lockstep (twiddles read once per stage) and through LDS one after the other.
 // ---------------------------------------------------------------------------------------
 template <typename T, int L, int V = 0>
@@ -358,142 +358,6 @@ __global__ void __launch_bounds__((GeoC<T, LZ, V>::THREADS)) k_zinv(const MvArgs
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) store_stream(&y[c * a.y_cs + long(z - a.y_zoff) * plane], r[c]);
-  }
-}
-
-// ---------------------------------------------------------------------------------------
-// One-component z passes: a block transforms one component's lines of W adjacent columns, so a
-// thread holds one line instead of three and the registers allow twice the waves per CU.  The
-// per-cell tensor work needs every component of x: zfwd forms J_c = sum_q M_cq x_q, zinv
-// (M x)_c, so the three blocks of a column group read the same x and M values; their launch
-// slots are 8 apart (blocks are dealt to the eight XCDs in turn), so one XCD's L2 serves the
-// second and third reads.  The slots of a partial last group of eight column groups follow in
-// order.
-// ---------------------------------------------------------------------------------------
-__device__ __forceinline__ void zcomp_block(int p, int ngroups, int& g, int& c) {
-  const int full = ngroups / 8 * 8;
-  if (p < 3 * full) {
-    g = (p / 24) * 8 + p % 8;
-    c = (p % 24) / 8;
-  } else {
-    const int q = p - 3 * full, r = ngroups - full;
-    g = full + q % r;
-    c = q / r;
-  }
-}
-
-// row c of the symmetric tensor stored as (xx, yy, zz, xy, xz, yz)
-__device__ __forceinline__ void tensor_row(int c, int& i0, int& i1, int& i2) {
-  i0 = c == 0 ? 0 : (c == 1 ? 3 : 4);
-  i1 = c == 0 ? 3 : (c == 1 ? 1 : 5);
-  i2 = c == 0 ? 4 : (c == 1 ? 5 : 2);
-}
-
-template <typename T, int LZ, int V>
-__global__ void __launch_bounds__((GeoC<T, LZ, V>::THREADS)) k_zfwd1(const MvArgs<T> a) {
-  using G = GeoC<T, LZ, V>;
-  constexpr int E = G::E, TL = G::TL, W = G::W;
-  __shared__ cx<T> lds[W * LZ];
-  __shared__ cx<T> twl[LZ];
-  const int b = blockIdx.z;
-  if (retired(a, b)) return;
-  TwStage<T, LZ, G::THREADS> tws;
-  tws.load(a.tw, threadIdx.x);
-  int g, c;
-  zcomp_block(blockIdx.x, gridDim.x / 3, g, c);
-  const int w = threadIdx.x % W;
-  const int t = threadIdx.x / W;
-  const long plane = long(a.ny) * a.nx;
-  const long col = long(g) * W + w;
-  const bool live = col < plane;
-  const cx<T>* x = a.x + b * a.x_bs + col;
-  const T* M = a.M ? a.M + b * a.M_bs + col : nullptr;
-  const T xs = a.xscale ? T(a.xscale[b * a.xscale_bs]) : T(1);
-  int i0, i1, i2;
-  tensor_row(c, i0, i1, i2);
-  cx<T> v[E];
-#pragma unroll
-  for (int m = E / 2; m < E; ++m) v[m] = cx<T>{0, 0};
-  // the nz <= LZ/2 planes sit in the lower half of the line
-#pragma unroll
-  for (int m = 0; m < E / 2; ++m) {
-    const int z = t + m * TL;
-    cx<T> j{0, 0};
-    if (live && source_plane(a, z)) {
-      const long zo = long(z - a.x_zoff) * plane;
-      if (M != nullptr) {
-        const long mo = long(z - a.M_zoff) * plane;
-        const cx<T> x0 = x[zo], x1 = x[a.x_cs + zo], x2 = x[2 * a.x_cs + zo];
-        const T m0 = M[i0 * a.M_cs + mo], m1 = M[i1 * a.M_cs + mo], m2 = M[i2 * a.M_cs + mo];
-        j = xs * cx<T>{m0 * x0.re + m1 * x1.re + m2 * x2.re, m0 * x0.im + m1 * x1.im + m2 * x2.im};
-      } else {
-        j = xs * x[c * a.x_cs + zo];
-      }
-    }
-    v[m] = j;
-  }
-  tws.store(twl, threadIdx.x);
-  __syncthreads();
-  fft_line<T, LZ, E, false, true, LZ>(v, lds, LdsInterleaved{W, w}, t, twl);
-  if (live) {
-    cx<T>* out = a.T1 + b * a.T1_bs + long(c) * LZ * plane + col;
-#pragma unroll
-    for (int m = 0; m < E; ++m) store_stream(&out[long(t + m * TL) * plane], v[m]);
-  }
-}
-
-template <typename T, int LZ, int V>
-__global__ void __launch_bounds__((GeoC<T, LZ, V>::THREADS)) k_zinv1(const MvArgs<T> a) {
-  using G = GeoC<T, LZ, V>;
-  constexpr int E = G::E, TL = G::TL, W = G::W;
-  __shared__ cx<T> lds[W * LZ];
-  __shared__ cx<T> twl[LZ];
-  const int b = blockIdx.z;
-  if (retired(a, b)) return;
-  TwStage<T, LZ, G::THREADS> tws;
-  tws.load(a.tw, threadIdx.x);
-  int g, c;
-  zcomp_block(blockIdx.x, gridDim.x / 3, g, c);
-  const int w = threadIdx.x % W;
-  const int t = threadIdx.x / W;
-  const long plane = long(a.ny) * a.nx;
-  const long col = long(g) * W + w;
-  const bool live = col < plane;
-  const cx<T>* in = a.T1 + b * a.T1_bs + long(c) * LZ * plane + (live ? col : 0);
-  cx<T> v[E];
-#pragma unroll
-  for (int m = 0; m < E; ++m) v[m] = live ? in[long(t + m * TL) * plane] : cx<T>{0, 0};
-  tws.store(twl, threadIdx.x);
-  __syncthreads();
-  fft_line<T, LZ, E, true, false, LZ>(v, lds, LdsInterleaved{W, w}, t, twl);
-  if (!live) return;
-  cx<T>* y = a.y + b * a.y_bs + c * a.y_cs + col;
-  const cx<T>* x = a.x ? a.x + b * a.x_bs + col : nullptr;
-  const cx<T>* e = a.e ? a.e + b * a.e_bs + c * a.e_cs + col : nullptr;
-  const T* M = (a.M && a.a_m != T(0)) ? a.M + b * a.M_bs + col : nullptr;
-  const T xs = a.xscale ? T(a.xscale[b * a.xscale_bs]) : T(1);
-  int i0, i1, i2;
-  tensor_row(c, i0, i1, i2);
-  // the output planes (< nz <= LZ/2) sit in the lower half of the line
-#pragma unroll
-  for (int m = 0; m < E / 2; ++m) {
-    const int z = t + m * TL;
-    if (z < a.out_z0 || z >= a.out_z1) continue;
-    cx<T> r = a.a_s * v[m];
-    if (x != nullptr && (a.a_x != T(0) || M != nullptr)) {
-      const long zo = long(z - a.x_zoff) * plane;
-      const cx<T> xc = xs * x[c * a.x_cs + zo];
-      r = r + a.a_x * xc;
-      if (M != nullptr) {
-        const long mo = long(z - a.M_zoff) * plane;
-        const cx<T> x0 = xs * x[zo], x1 = xs * x[a.x_cs + zo], x2 = xs * x[2 * a.x_cs + zo];
-        const T m0 = M[i0 * a.M_cs + mo], m1 = M[i1 * a.M_cs + mo], m2 = M[i2 * a.M_cs + mo];
-        const cx<T> mx{m0 * x0.re + m1 * x1.re + m2 * x2.re, m0 * x0.im + m1 * x1.im + m2 * x2.im};
-        r = r - a.a_m * mx;
-      }
-    }
-    if (e != nullptr) r = r + a.a_e * e[long(z - a.e_zoff) * plane];
-    store_stream(&y[long(z - a.y_zoff) * plane], r);
   }
 }
 

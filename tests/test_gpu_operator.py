@@ -256,7 +256,7 @@ def test_fft_length_modes_give_the_same_operator(torch):
 @pytest.mark.parametrize("n", [(33, 20, 17), (64, 48, 40), (100, 30, 12)])
 def test_every_launch_variant_matches_oracle(torch, variant, n, pow2):
     """Every launch variant the autotuner can pick, forced on all passes (the x pass has eight,
-    the column passes four), on shapes whose FFT lengths span 24..256: with the default lengths
+    the y passes four, the z passes two), on shapes whose FFT lengths span 24..256: with the default lengths
     (96, 48, 48 / 128, 96, 96 / 256, 64, 24) and with powers of two only (32..256)."""
     from paper_2306_17537_amd import ie
     banner(f"matvec variant={variant} n={n} pow2={pow2}")
@@ -284,8 +284,9 @@ def test_every_launch_variant_matches_oracle(torch, variant, n, pow2):
         assert rel(host(yd), want) < 1e-12
         assert rel(host(y32).astype(np.complex128), want) < 2e-6
         tun = ie.ie_ctx_tuning(ctx)
-        assert all(r["variant"] == (variant if r["pass"] == "xconv" else variant & 3)
-                   for r in tun)
+        want = {"xconv": variant, "yfwd": variant & 3, "yinv": variant & 3, "zfwd": variant & 1,
+                "zinv": variant & 1}
+        assert all(r["variant"] == want[r["pass"]] for r in tun)
         assert all(r["fft"] == [_fft_len(m, pow2) for m in n] for r in tun)
         # the x pass runs one line per thread group from variant 4 on (its LDS always fits here)
         xk = [r["kernel"] for r in tun if r["pass"] == "xconv"]
@@ -312,7 +313,8 @@ def test_tuning_file_sets_the_variants_of_later_contexts(torch, tmp_path):
     assert sorted(e["precision"] for e in mine) == ["c128", "c64"]
     for e in mine:
         assert e["variant"] == [tun[e["precision"], q] for q in names]
-        e["variant"] = [(v + 3) % 8 if q == 2 else (v + 1) % 4 for q, v in enumerate(e["variant"])]
+        e["variant"] = [(v + 3) % 8 if q == 2 else ((v + 1) % 4 if q in (1, 3) else (v + 1) % 2)
+                        for q, v in enumerate(e["variant"])]
     edited = tmp_path / "edited.json"
     edited.write_text(json.dumps(mine))
     ie.ie_tuning_load(str(edited))

@@ -22,8 +22,8 @@ def _ours(entries):
 
 
 def test_load_then_save_round_trip(tmp_path):
-    want = [_entry(), _entry(prec="c64", var=(0, 3, 7, 1, 2)),
-            _entry(grid=(48, 48, 64), fft=(128, 128, 128), var=(3, 3, 4, 0, 1))]
+    want = [_entry(), _entry(prec="c64", var=(0, 3, 7, 1, 1)),
+            _entry(grid=(48, 48, 64), fft=(128, 128, 128), var=(1, 3, 4, 0, 1))]
     src = tmp_path / "in.json"
     src.write_text(json.dumps(want, indent=2))
     ie.ie_tuning_load(str(src))
@@ -36,7 +36,8 @@ def test_load_then_save_round_trip(tmp_path):
 @pytest.mark.parametrize("bad", [
     lambda e: e.pop("variant"),
     lambda e: e.__setitem__("variant", [0, 0, 8, 0, 0]),     # x pass has variants 0..7
-    lambda e: e.__setitem__("variant", [4, 0, 0, 0, 0]),     # column passes 0..3
+    lambda e: e.__setitem__("variant", [0, 4, 0, 0, 0]),     # y passes 0..3
+    lambda e: e.__setitem__("variant", [2, 0, 0, 0, 0]),     # z passes 0..1
     lambda e: e.__setitem__("fft", [64, 48, 48]),            # 64 < 2 * 33 - 1
     lambda e: e.__setitem__("fft", [192, 48, 48]),           # not a length the library picks
     lambda e: e.__setitem__("precision", "bf16"),
