@@ -454,17 +454,19 @@ __global__ void __launch_bounds__((GeoX<T, LX, V>::THREADS)) k_xconv(const MvArg
 // LDS for the tensor multiply, which the whole block does with one work item per (row pair,
 // kx): the six stored spectrum components are loaded once for both rows of the pair.  The
 // forward transforms skip the zero upper half of the padded lines, the inverse ones compute
-// only the kept lower half.  V: 0 eight values per thread, 1 sixteen, 2 eight with the
-// registers capped for four waves per SIMD, 3 sixteen with two row pairs per block.  Used where
-// the block's LDS (six padded lines per pair and the twiddles) fits in the 160 KB of a CU.
+// only the kept lower half.  V: 0 eight values per thread, 1 sixteen, 2 sixteen with two row
+// pairs per block, each reading the spectrum values when it multiplies; 3 as 2 with the spectrum
+// values fetched before the forward transforms, so that their latency overlaps that of the
+// lines (more registers).  Used where the block's LDS (six padded lines per pair and the
+// twiddles) fits in the 160 KB of a CU.
 // ---------------------------------------------------------------------------------------
 template <typename T, int LX, int V>
 struct GeoX2 {
-  static constexpr int E0 = (V & 1) ? 16 : 8;
+  static constexpr int E0 = V == 0 ? 8 : 16;
   static constexpr int E = LX % 3 == 0 ? reg_width(LX, 0) : (LX < E0 ? LX : E0);
   static constexpr int TL = LX / E;
-  static constexpr int WPE = V == 2 ? 4 : 1;  // minimum waves per SIMD the registers allow
-  static constexpr int NP0 = V == 3 ? 2 : 1;
+  static constexpr bool PRE = V == 3;  // spectrum values fetched before the forward transforms
+  static constexpr int NP0 = V >= 2 ? 2 : 1;
   static constexpr int NPW = (64 + 6 * TL - 1) / (6 * TL);  // at least one wavefront
   static constexpr int NP1 = NP0 > NPW ? NP0 : NPW;
   static constexpr int NPM = 1024 / (6 * TL) < 1 ? 1 : 1024 / (6 * TL);
@@ -477,16 +479,15 @@ struct GeoX2 {
 };
 
 template <typename T, int LX, int V>
-__global__ void __launch_bounds__((GeoX2<T, LX, V>::THREADS))
-    __attribute__((amdgpu_waves_per_eu(GeoX2<T, LX, V>::WPE, 8))) k_xconv2(const MvArgs<T> a) {
+__global__ void __launch_bounds__((GeoX2<T, LX, V>::THREADS)) k_xconv2(const MvArgs<T> a) {
   using G = GeoX2<T, LX, V>;
   constexpr int E = G::E, TL = G::TL, NP = G::NP;
   __shared__ cx<T> lds[6 * NP * G::LP];
   __shared__ cx<T> twl[LX];  // exp(-2 pi i k / LX), k < LX
   const int b = blockIdx.z;
   if (retired(a, b)) return;
-  // every global read of the block is issued up front (twiddles, the lines, the spectrum values
-  // of the multiply), so that their latencies overlap instead of adding up stage by stage
+  // the global reads of the block are issued up front (twiddles, the lines and, with PRE, the
+  // spectrum values of the multiply), so that their latencies overlap
   TwStage<T, LX, G::THREADS> tws;
   tws.load(a.tw, threadIdx.x);
   const int hx = LX / 2, hy = a.LY / 2, hz = a.LZ / 2;
@@ -516,9 +517,7 @@ __global__ void __launch_bounds__((GeoX2<T, LX, V>::THREADS))
   const long gzs = long(hy + 1) * gys;
   const long gcs = long(hz + 1) * gzs;
   const cx<T>* gz0 = a.ghat + b * a.ghat_bs + long(oz) * gzs;
-  cx<T> gv[G::ITEMS][6];
-#pragma unroll
-  for (int q = 0; q < G::ITEMS; ++q) {
+  auto fetch = [&](int q, cx<T>(&g6)[6]) {
     const int it = threadIdx.x + q * G::THREADS;
     const int p = it / LX, kx = it % LX;
     const int py = blockIdx.x * NP + p;
@@ -526,7 +525,12 @@ __global__ void __launch_bounds__((GeoX2<T, LX, V>::THREADS))
     const int ox = kx > hx ? LX - kx : kx;
     const cx<T>* g = gz0 + long(ok ? py : 0) * gys + ox;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) gv[q][k] = ok ? g[k * gcs] : cx<T>{0, 0};
+    for (int k = 0; k < 6; ++k) g6[k] = ok ? g[k * gcs] : cx<T>{0, 0};
+  };
+  cx<T> gv[G::PRE ? G::ITEMS : 1][6];
+  if constexpr (G::PRE) {
+#pragma unroll
+    for (int q = 0; q < G::ITEMS; ++q) fetch(q, gv[q]);
   }
   tws.store(twl, threadIdx.x);
   __syncthreads();  // the twiddle table
@@ -543,10 +547,17 @@ __global__ void __launch_bounds__((GeoX2<T, LX, V>::THREADS))
     const int py = blockIdx.x * NP + p;
     if (p < NP && py <= hy) {
       const T sx = kx > hx ? T(-1) : T(1);
-      const cx<T> gxx = gv[q][0], gyy = gv[q][1], gzz = gv[q][2];
-      const cx<T> gxy = sx * gv[q][3];
-      const cx<T> gxz = (sx * sz) * gv[q][4];
-      const cx<T> gyz = sz * gv[q][5];
+      cx<T> g6[6];
+      if constexpr (G::PRE) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) g6[k] = gv[q][k];
+      } else {
+        fetch(q, g6);
+      }
+      const cx<T> gxx = g6[0], gyy = g6[1], gzz = g6[2];
+      const cx<T> gxy = sx * g6[3];
+      const cx<T> gxz = (sx * sz) * g6[4];
+      const cx<T> gyz = sz * g6[5];
       const int nr = (py != 0 && py != hy) ? 2 : 1;
 #pragma unroll
       for (int rr = 0; rr < 2; ++rr) {
