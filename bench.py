@@ -457,6 +457,24 @@ def measured_traffic(passes, tuning, grid):
     return tot
 
 
+def rocprof_operator(passes, tuning, grid, byts):
+    """One operator application timed as the sum of the rocprofv3 kernel-trace averages of its
+    five passes (the chosen variants, from the committed trace of the timed solves: pure kernel
+    time, no launch gaps), with its HBM fraction; None unless every pass has an entry for the
+    current kernel sources."""
+    from paper_2306_17537_amd import traffic
+    us = 0.0
+    for k in passes.values():
+        tn = template_name(k["name"], tuning, grid)
+        hit = traffic.trace_lookup(tn, summary=HEADLINE_TRACE) if tn else None
+        if hit is None:
+            return None
+        us += hit[0]
+    gbs = byts / (us * 1e-6) / 1e9
+    return {"us": round(us, 1), "gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "source": "profiles/" + HEADLINE_TRACE}
+
+
 def solve_large(ie, torch, ctx, g, s6, p, acc):
     """The block forms on the 128x128x256 grid (four z slabs of 64), each from a zero start to
     e <= 1e-6: the Krylov outer iteration over one block GS or block Jacobi sweep (mixed, blocks
@@ -513,7 +531,8 @@ def matvec_large(ie, torch, ctx, s6, p):
         t_ms = sum(k["total_ms"] for k in passes.values()) / reps
         byts = sum(k["bytes_per_launch"] * k["launches"] for k in passes.values()) / reps
         tr = measured_traffic(passes, tuning, p.n)
-        out[nm] = dict(us=round(1e3 * t_ms, 1), algorithmic_bytes=int(byts),
+        rp = rocprof_operator(passes, tuning, p.n, byts)
+        out[nm] = dict(us=round(1e3 * t_ms, 1), algorithmic_bytes=int(byts), rocprof=rp,
                        cache_resident=False,
                        gbs=round(byts / (t_ms * 1e-3) / 1e9, 1),
                        frac=round(byts / (t_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
