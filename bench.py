@@ -398,6 +398,17 @@ def config1_legs(ie, torch, args, acc):
                       passes_us={k["name"].split()[0]: round(1e3 * k["total_ms"] / k["launches"], 1)
                                  for k in passes})
     out["matvec"] = mv
+    # one Arnoldi step of the chosen form: the chosen solve's time per iteration (restart work
+    # included), and the algorithmic bytes of one step (operator, then the dots-and-norm pass
+    # over j + 1 basis vectors and w and the update pass over j + 1 vectors, w read and written,
+    # averaged over a restart cycle of CHOSEN_RESTART steps)
+    vec = 3 * p.n[0] * p.n[1] * p.n[2] * 8.0
+    gs = sum((j + 2) * vec + (j + 3) * vec for j in range(CHOSEN_RESTART)) / CHOSEN_RESTART
+    step_bytes = mv["c64"]["algorithmic_bytes"] + gs
+    step_us = 1e6 * t_c / st_c.its
+    out["arnoldi_step"] = dict(us=round(step_us, 1), algorithmic_bytes=int(step_bytes),
+                               gbs=round(step_bytes / (step_us * 1e-6) / 1e9, 1),
+                               operator_us=round(1e3 * mv["c64"]["ms"], 1))
     if not args.no_nn:
         out["learned_guess"] = learned_bench(ie, torch, ctx, s6, p, ref)
     ie.ie_ctx_destroy(ctx)
