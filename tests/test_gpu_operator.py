@@ -253,11 +253,12 @@ def test_fft_length_modes_give_the_same_operator(torch):
 
 @pytest.mark.parametrize("pow2", [0, 1])
 @pytest.mark.parametrize("variant", range(8))
-@pytest.mark.parametrize("n", [(33, 20, 17), (64, 48, 40), (100, 30, 12)])
+@pytest.mark.parametrize("n", [(33, 20, 17), (64, 48, 40), (100, 30, 12), (12, 9, 20)])
 def test_every_launch_variant_matches_oracle(torch, variant, n, pow2):
     """Every launch variant the autotuner can pick, forced on all passes (the x pass has eight,
-    the y passes four, the z passes two), on shapes whose FFT lengths span 24..256: with the default lengths
-    (96, 48, 48 / 128, 96, 96 / 256, 64, 24) and with powers of two only (32..256)."""
+    the y passes four, the z passes two), on shapes whose FFT lengths span 24..256: with the
+    default lengths (96, 48, 48 / 128, 96, 96 / 256, 64, 24 / 24, 24, 48) and with powers of two
+    only (16..256)."""
     from paper_2306_17537_amd import ie
     banner(f"matvec variant={variant} n={n} pow2={pow2}")
     p = synth.random_problem(n, seed=sum(n) + variant, freq=2.0e6, contrast=3.0)
