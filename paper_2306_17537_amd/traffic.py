@@ -18,6 +18,8 @@ Usage (from the repository root, after the profiler runs):
         --kernel 'k_xconv<float, 128' --out profiles/NAME.md --command '...'
     python -m paper_2306_17537_amd.traffic stats --dir DIR --out profiles/NAME.md \\
         --command '...' [--top 20] [--extra TEXT]
+    python -m paper_2306_17537_amd.traffic counters --dir DIR --kernel REGEX \\
+        --out profiles/NAME.md --command '...' (any --pmc counters, median per launch)
 """
 from __future__ import annotations
 
@@ -181,6 +183,38 @@ def write_stats_markdown(rows, path, command, title, extra=""):
         f.write("\n".join(lines) + "\n")
 
 
+def counters(directory, kernel):
+    """Median value per launch of every counter of a --pmc run, per kernel whose name matches
+    the regular expression `kernel`: {kernel: {counter: (median, launches)}}."""
+    per = {}
+    for k, c, v in _rows(directory):
+        if not re.search(kernel, k):
+            continue
+        m = re.search(r"(k_\w+<[^>]*>)", k)
+        per.setdefault(m.group(1) if m else k, {}).setdefault(c, []).append(v)
+    return {k: {c: (statistics.median(vs), len(vs)) for c, vs in d.items()}
+            for k, d in per.items()}
+
+
+def write_counters_markdown(res, path, command, title, extra=""):
+    names = sorted({c for d in res.values() for c in d})
+    lines = [f"# {title}", "", "Command (from /tmp with TMPDIR=/tmp, repository at $R):", "",
+             "```", command, "```", "",
+             "Median per launch over the launches of each kernel (counters as rocprofv3 reports "
+             "them, summed over the GPU's instances).", "",
+             "| kernel | launches | " + " | ".join(names) + " |",
+             "|---|---|" + "---|" * len(names)]
+    for k in sorted(res):
+        d = res[k]
+        n = max(v[1] for v in d.values())
+        lines.append(f"| `{k}` | {n} | " + " | ".join(
+            f"{d[c][0]:.4g}" if c in d else "" for c in names) + " |")
+    if extra:
+        lines += ["", extra]
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -198,7 +232,17 @@ def main(argv=None):
     k.add_argument("--title", default="Kernel trace statistics")
     k.add_argument("--top", type=int, default=20)
     k.add_argument("--extra", default="")
+    c = sub.add_parser("counters")
+    c.add_argument("--dir", required=True)
+    c.add_argument("--kernel", required=True, help="regular expression on the kernel name")
+    c.add_argument("--out", required=True)
+    c.add_argument("--command", required=True)
+    c.add_argument("--title", default="Counters per launch")
+    c.add_argument("--extra", default="")
     a = ap.parse_args(argv)
+    if a.cmd == "counters":
+        write_counters_markdown(counters(a.dir, a.kernel), a.out, a.command, a.title, a.extra)
+        return 0
     if a.cmd == "stats":
         write_stats_markdown(kernel_stats(a.dir, a.top), a.out, a.command, a.title, a.extra)
         return 0
