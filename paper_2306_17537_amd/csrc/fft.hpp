@@ -173,12 +173,58 @@ constexpr int stage_ns(int s) {  // product of the radices before stage s
   return ns;
 }
 
+// Stage-major twiddle table (the layout of the LDS copies): stage s (Ns > 1, radix R) holds
+// W_{Ns R}^{r k} at tw_stage_off(s) + (r - 1) Ns + k for r = 1 .. R-1, k < Ns, so that the lanes
+// of a stage, whose k = j mod Ns are consecutive, read consecutive entries (a table indexed by
+// r k Ns R / L would put lanes 16 or 32 bytes x r k apart: LDS bank conflicts).  The stages
+// hold sum (R - 1) Ns = L - R_0 < L entries in all.
+constexpr int kTwStaged = -1;  // TWL value that selects this layout
+template <int L, int E>
+constexpr int tw_stage_off(int S) {
+  int off = 0;
+  for (int s = 0; s < S; ++s) {
+    const int ns = stage_ns<L, E>(s);
+    if (ns > 1) off += (stage_radix<L, E>(s) - 1) * ns;
+  }
+  return off;
+}
+template <int L, int E>
+constexpr int tw_staged_size() {
+  return tw_stage_off<L, E>(num_stages<L, E>());
+}
+// exponent e of W_L^e stored at index i of the stage-major table
+template <int L, int E>
+__device__ __forceinline__ int tw_staged_exp(int i) {
+  int off = 0;
+  for (int s = 1; s < num_stages<L, E>(); ++s) {
+    const int ns = stage_ns<L, E>(s), R = stage_radix<L, E>(s);
+    const int n = (R - 1) * ns;
+    if (i < off + n) {
+      const int q = i - off;
+      return (q / ns + 1) * (q % ns) * (L / (ns * R));
+    }
+    off += n;
+  }
+  return 0;
+}
+
 // LDS addressing of one line: position p of line `line` in a buffer whose lines are either
 // interleaved (stride 1 between lines, LINES lines) or contiguous with padding.
 struct LdsInterleaved {
   int lines;  // number of interleaved lines
   int line;
   __device__ __forceinline__ int operator()(int p) const { return p * lines + line; }
+};
+// line-major without padding, for 16-byte elements: bits 0-3 of a position are XOR-permuted by
+// bits 4-7 and 5-6, which spreads the strided accesses of the FFT stages over the LDS banks better
+// than a pad slot every 16 positions; only bits 0-3 change, so every aligned group of 16 positions
+// maps onto itself (a bijection of 0 .. L-1 for L = 24 and every multiple of 16)
+struct LdsSwz {
+  int base;
+  __device__ __forceinline__ int operator()(int p) const {
+    return base + (p ^ ((p >> 4) & 15) ^ ((p >> 5) & 3));
+  }
+  static constexpr __host__ __device__ int padded_len(int L) { return L; }
 };
 struct LdsPadded {  // line-major, one pad slot every 16 positions (conflict-free strided access)
   int base;
@@ -207,9 +253,15 @@ __device__ __forceinline__ void fft_stage(cx<T> (&v)[E], cx<T>* __restrict__ lds
 #pragma unroll
     for (int r = 0; r < R; ++r) u[r] = v[b + r * NB];
     if constexpr (NS > 1) {
-      constexpr int step = TWL / (NS * R);
+      if constexpr (TWL == kTwStaged) {
+        constexpr int off = tw_stage_off<L, E>(S);
 #pragma unroll
-      for (int r = 1; r < R; ++r) u[r] = u[r] * twiddle<T, INV>(tw, r * k * step);
+        for (int r = 1; r < R; ++r) u[r] = u[r] * twiddle<T, INV>(tw, off + (r - 1) * NS + k);
+      } else {
+        constexpr int step = TWL / (NS * R);
+#pragma unroll
+        for (int r = 1; r < R; ++r) u[r] = u[r] * twiddle<T, INV>(tw, r * k * step);
+      }
     }
     if constexpr (ZIN && S == 0 && R % 2 == 0)
       DftHalfIn<T, R, INV>::run(u);
@@ -250,7 +302,8 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], cx<T>* lds, Addr addr,
 template <typename T, int L, int E, bool INV, bool ZIN = false, int TWL = TW_N, typename Addr>
 __device__ __forceinline__ void fft_line(cx<T> (&v)[E], cx<T>* lds, Addr addr, int t,
                                          const cx<T>* __restrict__ tw) {
-  static_assert(L % E == 0 && L <= MAX_FFT_LEN && TWL % L == 0, "bad FFT length");
+  static_assert(L % E == 0 && L <= MAX_FFT_LEN && (TWL == kTwStaged || TWL % L == 0),
+                "bad FFT length");
   fft_stages<T, L, E, INV, ZIN, TWL>(v, lds, addr, t, tw,
                                      std::make_integer_sequence<int, num_stages<L, E>()>{});
 }
@@ -270,12 +323,18 @@ __device__ __forceinline__ void fft_stage_multi(cx<T> (&v)[NC][E], cx<T>* __rest
   static_assert(E % R == 0, "radix must divide the register width");
   cx<T> w[NB][R];
   if constexpr (NS > 1) {
-    constexpr int step = TWL / (NS * R);
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       const int k = (t + b * TL) % NS;
+      if constexpr (TWL == kTwStaged) {
+        constexpr int off = tw_stage_off<L, E>(S);
 #pragma unroll
-      for (int r = 1; r < R; ++r) w[b][r] = twiddle<T, INV>(tw, r * k * step);
+        for (int r = 1; r < R; ++r) w[b][r] = twiddle<T, INV>(tw, off + (r - 1) * NS + k);
+      } else {
+        constexpr int step = TWL / (NS * R);
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[b][r] = twiddle<T, INV>(tw, r * k * step);
+      }
     }
   }
 #pragma unroll
@@ -330,31 +389,34 @@ template <typename T, int L, int E, bool INV, int NC, bool ZIN = false, int TWL 
           typename Addr>
 __device__ __forceinline__ void fft_lines(cx<T> (&v)[NC][E], cx<T>* lds, Addr addr, int t,
                                           const cx<T>* __restrict__ tw) {
-  static_assert(L % E == 0 && L <= MAX_FFT_LEN && TWL % L == 0, "bad FFT length");
+  static_assert(L % E == 0 && L <= MAX_FFT_LEN && (TWL == kTwStaged || TWL % L == 0),
+                "bad FFT length");
   fft_stages_multi<T, L, E, INV, NC, ZIN, TWL>(
       v, lds, addr, t, tw, std::make_integer_sequence<int, num_stages<L, E>()>{});
 }
 
-// The L twiddles exp(-2 pi i k / L) of one length, copied from the global table into LDS by the
-// NT threads of a block in two steps: load() issues the global reads into registers (call it
-// before the block's other global reads, so that waiting for these leaves those in flight),
-// store() writes them to LDS; a barrier must follow before the table is read.
-template <typename T, int L, int NT>
+// The stage-major twiddle table of length L and register width E (tw_stage_off above), copied
+// from the global table into LDS by the NT threads of a block in two steps: load() issues the
+// global reads into registers (call it before the block's other global reads, so that waiting
+// for these leaves those in flight), store() writes them to LDS; a barrier must follow before
+// the table is read.  The LDS table needs tw_staged_size<L, E>() < L entries.
+template <typename T, int L, int E, int NT>
 struct TwStage {
-  static constexpr int K = (L + NT - 1) / NT;
-  cx<T> r[K];
+  static constexpr int N = tw_staged_size<L, E>();
+  static constexpr int K = N > 0 ? (N + NT - 1) / NT : 0;
+  cx<T> r[K > 0 ? K : 1];
   __device__ __forceinline__ void load(const cx<T>* __restrict__ tw, int tid) {
 #pragma unroll
     for (int i = 0; i < K; ++i) {
       const int k = tid + i * NT;
-      r[i] = k < L ? tw[k * (TW_N / L)] : cx<T>{0, 0};
+      r[i] = k < N ? tw[tw_staged_exp<L, E>(k) * (TW_N / L)] : cx<T>{0, 0};
     }
   }
   __device__ __forceinline__ void store(cx<T>* tab, int tid) const {
 #pragma unroll
     for (int i = 0; i < K; ++i) {
       const int k = tid + i * NT;
-      if (k < L) tab[k] = r[i];
+      if (k < N) tab[k] = r[i];
     }
   }
 };

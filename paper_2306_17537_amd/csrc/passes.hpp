@@ -21,6 +21,8 @@
 // advance by their batch stride.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "fft.hpp"
 
@@ -163,7 +165,7 @@ __global__ void __launch_bounds__((Geo<T, L, V>::W * Geo<T, L, V>::TL))
   __shared__ cx<T> twl[HALF ? L : 1];
   const int b = blockIdx.z;
   if (a.active != nullptr && a.active[b * a.active_bs] == 0) return;
-  TwStage<T, HALF ? L : 1, W * TL> tws;
+  TwStage<T, HALF ? L : 2, HALF ? E : 2, W * TL> tws;
   if constexpr (HALF) tws.load(tw, threadIdx.x);
   const int w = threadIdx.x % W;
   const int t = threadIdx.x / W;
@@ -183,7 +185,7 @@ __global__ void __launch_bounds__((Geo<T, L, V>::W * Geo<T, L, V>::TL))
   if constexpr (HALF) {
     tws.store(twl, threadIdx.x);
     __syncthreads();
-    fft_line<T, L, E, INV, !INV, L>(v, lds, LdsInterleaved{W, w}, t, twl);
+    fft_line<T, L, E, INV, !INV, kTwStaged>(v, lds, LdsInterleaved{W, w}, t, twl);
   } else {
     fft_line<T, L, E, INV>(v, lds, LdsInterleaved{W, w}, t, tw);
   }
@@ -242,7 +244,7 @@ __global__ void __launch_bounds__((GeoC<T, LZ, V>::THREADS)) k_zfwd(const MvArgs
   __shared__ cx<T> twl[LZ];
   const int b = blockIdx.z;
   if (retired(a, b)) return;
-  TwStage<T, LZ, G::THREADS> tws;
+  TwStage<T, LZ, E, G::THREADS> tws;
   tws.load(a.tw, threadIdx.x);
   const int w = threadIdx.x % W;
   const int t = threadIdx.x / W;
@@ -282,7 +284,7 @@ __global__ void __launch_bounds__((GeoC<T, LZ, V>::THREADS)) k_zfwd(const MvArgs
   }
   tws.store(twl, threadIdx.x);
   __syncthreads();
-  fft_lines<T, LZ, E, false, 3, true, LZ>(v, lds, LdsInterleaved{W, w}, t, twl);
+  fft_lines<T, LZ, E, false, 3, true, kTwStaged>(v, lds, LdsInterleaved{W, w}, t, twl);
   if (live) {
     cx<T>* out = a.T1 + b * a.T1_bs + col;
     const long cs = long(LZ) * plane;
@@ -303,7 +305,7 @@ __global__ void __launch_bounds__((GeoC<T, LZ, V>::THREADS)) k_zinv(const MvArgs
   __shared__ cx<T> twl[LZ];
   const int b = blockIdx.z;
   if (retired(a, b)) return;
-  TwStage<T, LZ, G::THREADS> tws;
+  TwStage<T, LZ, E, G::THREADS> tws;
   tws.load(a.tw, threadIdx.x);
   const int w = threadIdx.x % W;
   const int t = threadIdx.x / W;
@@ -320,7 +322,7 @@ __global__ void __launch_bounds__((GeoC<T, LZ, V>::THREADS)) k_zinv(const MvArgs
       v[c][m] = live ? in[c * cs + long(t + m * TL) * plane] : cx<T>{0, 0};
   tws.store(twl, threadIdx.x);
   __syncthreads();
-  fft_lines<T, LZ, E, true, 3, false, LZ>(v, lds, LdsInterleaved{W, w}, t, twl);
+  fft_lines<T, LZ, E, true, 3, false, kTwStaged>(v, lds, LdsInterleaved{W, w}, t, twl);
   if (!live) return;
   cx<T>* y = a.y + b * a.y_bs + col;
   const cx<T>* x = a.x ? a.x + b * a.x_bs + col : nullptr;
@@ -472,7 +474,10 @@ struct GeoX2 {
   static constexpr int NPM = 1024 / (6 * TL) < 1 ? 1 : 1024 / (6 * TL);
   static constexpr int NP = NP1 < NPM ? NP1 : NPM;
   static constexpr int THREADS = 6 * NP * TL;
-  static constexpr int LP = LdsPadded::padded_len(LX);
+  // float64 lines: swizzled (measured bank conflicts 2.7e7 cycles per launch at LX = 256,
+  // against 6.6e7 padded); float32 lines: padded
+  using Lds = typename std::conditional<sizeof(T) == 8, LdsSwz, LdsPadded>::type;
+  static constexpr int LP = Lds::padded_len(LX);
   static constexpr bool FITS = (6 * NP * LP + LX) * int(sizeof(cx<T>)) <= 160 * 1024 &&
                                THREADS <= 1024;
   static constexpr int ITEMS = (NP * LX + THREADS - 1) / THREADS;  // multiply items per thread
@@ -483,12 +488,12 @@ __global__ void __launch_bounds__((GeoX2<T, LX, V>::THREADS)) k_xconv2(const MvA
   using G = GeoX2<T, LX, V>;
   constexpr int E = G::E, TL = G::TL, NP = G::NP;
   __shared__ cx<T> lds[6 * NP * G::LP];
-  __shared__ cx<T> twl[LX];  // exp(-2 pi i k / LX), k < LX
+  __shared__ cx<T> twl[LX];  // the stage-major twiddle table (fewer than LX entries)
   const int b = blockIdx.z;
   if (retired(a, b)) return;
   // the global reads of the block are issued up front (twiddles, the lines and, with PRE, the
   // spectrum values of the multiply), so that their latencies overlap
-  TwStage<T, LX, G::THREADS> tws;
+  TwStage<T, LX, E, G::THREADS> tws;
   tws.load(a.tw, threadIdx.x);
   const int hx = LX / 2, hy = a.LY / 2, hz = a.LZ / 2;
   const int t = threadIdx.x % TL;
@@ -504,7 +509,7 @@ __global__ void __launch_bounds__((GeoX2<T, LX, V>::THREADS)) k_xconv2(const MvA
   const long rs = long(a.LY) * a.nx;  // per kz
   const long cs = long(a.LZ) * rs;    // per component
   cx<T>* row = a.T2 + b * a.T2_bs + long(c) * cs + long(kz) * rs + long(live ? ky : 0) * a.nx;
-  const LdsPadded addr{line * G::LP};
+  const typename G::Lds addr{line * G::LP};
   cx<T> v[E];
   // the nx <= LX/2 cells sit in the lower half of the line
 #pragma unroll
@@ -534,7 +539,7 @@ __global__ void __launch_bounds__((GeoX2<T, LX, V>::THREADS)) k_xconv2(const MvA
   }
   tws.store(twl, threadIdx.x);
   __syncthreads();  // the twiddle table
-  fft_line<T, LX, E, false, true, LX>(v, lds, addr, t, twl);
+  fft_line<T, LX, E, false, true, kTwStaged>(v, lds, addr, t, twl);
   // the last stage ran in registers after every thread's last LDS read of this line
 #pragma unroll
   for (int m = 0; m < E; ++m) lds[addr(t + m * TL)] = v[m];
@@ -564,8 +569,8 @@ __global__ void __launch_bounds__((GeoX2<T, LX, V>::THREADS)) k_xconv2(const MvA
         if (rr < nr) {
           const T sy = rr == 0 ? T(1) : T(-1);
           const int base = (p * 6 + rr * 3) * G::LP;
-          const int i0 = LdsPadded{base}(kx), i1 = LdsPadded{base + G::LP}(kx),
-                    i2 = LdsPadded{base + 2 * G::LP}(kx);
+          const int i0 = typename G::Lds{base}(kx), i1 = typename G::Lds{base + G::LP}(kx),
+                    i2 = typename G::Lds{base + 2 * G::LP}(kx);
           const cx<T> j0 = lds[i0], j1 = lds[i1], j2 = lds[i2];
           const cx<T> gxys = sy * gxy, gyzs = sy * gyz;
           lds[i0] = gxx * j0 + gxys * j1 + gxz * j2;
@@ -579,7 +584,7 @@ __global__ void __launch_bounds__((GeoX2<T, LX, V>::THREADS)) k_xconv2(const MvA
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = lds[addr(t + m * TL)];
   __syncthreads();  // every read of the line done before its first inverse stage writes
-  fft_line<T, LX, E, true, false, LX>(v, lds, addr, t, twl);
+  fft_line<T, LX, E, true, false, kTwStaged>(v, lds, addr, t, twl);
   if (live) {
 #pragma unroll
     for (int m = 0; m < E / 2; ++m) {
