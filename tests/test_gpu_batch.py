@@ -50,10 +50,18 @@ def _solve_and_compare(torch, probs, opts, ctxs, grids, expect_converged):
     return pairs, stats
 
 
+def _oracle_relres(p, E):
+    """Relative residual of eq. (8) for the field E of problem p, by the oracle."""
+    st = solve.setup(p)
+    return operator.relres(st.Ghat, st.dsig, E, st.E0, p.n)
+
+
 @pytest.mark.parametrize("scheme,prec", [("gs", "mixed"), ("jacobi", "fp64")])
 def test_batched_dd_members_equal_standalone_solves(torch, scheme, prec):
     """2 MHz members of the logging run (three grid shapes, two and three z slabs) in one call:
-    every member is bit-identical to its own standalone call."""
+    every member is bit-identical to its own standalone call.  Block GS reaches the tolerance
+    (oracle residual); block Jacobi returns either a converged field or, stopped, the iterate of
+    smallest recorded residual, and the oracle's residual of the returned field is that one."""
     from paper_2306_17537_amd import ie
     probs = [p for p in synth.config2()[:12] if p.freq == 2.0e6]
     banner(f"batch of {len(probs)} {scheme} {prec}: shapes {sorted(set(p.n for p in probs))}")
@@ -63,12 +71,20 @@ def test_batched_dd_members_equal_standalone_solves(torch, scheme, prec):
                       precision=ie.IE_MIXED if prec == "mixed" else ie.IE_FP64)
     try:
         pairs, stats = _solve_and_compare(torch, probs, opts, ctxs, grids, expect_converged=gs)
-        if gs:
-            for k in (0, len(probs) - 1):
-                p = probs[k]
-                st = solve.setup(p)
-                E = host(pairs[k][1]["E_total"])
-                assert operator.relres(st.Ghat, st.dsig, E, st.E0, p.n) <= 1.01e-6
+        for k in (0, len(probs) - 1):
+            got = _oracle_relres(probs[k], host(pairs[k][1]["E_total"]))
+            s = stats[k]
+            hist = list(s.relres[1:s.sweeps + 1])
+            banner(f"member {k}: {s.sweeps} sweeps, best {s.best_sweep}, oracle relres {got:.3e}")
+            if gs:
+                assert got <= 1.01e-6
+                continue
+            if hist[-1] <= 1e-6:
+                want = hist[-1]
+            else:
+                assert s.relres[s.best_sweep] == min(s.relres[:s.sweeps + 1])
+                want = s.relres[s.best_sweep]
+            assert abs(got - want) <= 1e-6 * want, (got, want)
     finally:
         for c in ctxs.values():
             ie.ie_ctx_destroy(c)
@@ -76,7 +92,8 @@ def test_batched_dd_members_equal_standalone_solves(torch, scheme, prec):
 
 def test_batched_single_block_members_converge_and_equal_standalone(torch):
     """All members (400 kHz and 2 MHz) with one block each, i.e. batched full-domain
-    mixed-precision GMRES: converged, bit-identical to standalone calls, oracle residual."""
+    mixed-precision GMRES: converged, bit-identical to standalone calls, and the oracle residual
+    of one member of each of the six (grid, frequency) groups at the tolerance."""
     from paper_2306_17537_amd import ie
     import dataclasses
     probs = [dataclasses.replace(p, z_bounds=(0, p.n[2])) for p in synth.config2()[:8]]
@@ -86,10 +103,13 @@ def test_batched_single_block_members_converge_and_equal_standalone(torch):
     try:
         pairs, stats = _solve_and_compare(torch, probs, opts, ctxs, grids, expect_converged=True)
         assert all(s.sweeps == 1 for s in stats)
-        p = probs[0]
-        st = solve.setup(p)
-        E = host(pairs[0][1]["E_total"])
-        assert operator.relres(st.Ghat, st.dsig, E, st.E0, p.n) <= 1.01e-6
+        first = {}
+        for k, p in enumerate(probs):
+            first.setdefault((p.n, p.freq), k)
+        assert len(first) == 6
+        for (n, f), k in sorted(first.items()):
+            got = _oracle_relres(probs[k], host(pairs[k][1]["E_total"]))
+            assert got <= 1.01e-6, (n, f, got)
     finally:
         for c in ctxs.values():
             ie.ie_ctx_destroy(c)
