@@ -234,7 +234,8 @@ struct LdsPadded {  // line-major, one pad slot every 16 positions (conflict-fre
 
 // ZIN: the positions L/2 .. L-1 are zero on entry (registers E/2 .. E-1), so the first stage
 // takes the zero upper half of each butterfly's inputs into account.  TWL: length of the
-// twiddle table tw (entries exp(-2 pi i k / TWL); a multiple of L).
+// twiddle table tw (entries exp(-2 pi i k / TWL); a multiple of L), or kTwStaged for the
+// stage-major table of this length and register width.
 template <typename T, int L, int E, int S, bool INV, bool ZIN, int TWL, typename Addr>
 __device__ __forceinline__ void fft_stage(cx<T> (&v)[E], cx<T>* __restrict__ lds, Addr addr,
                                           int t, const cx<T>* __restrict__ tw) {
@@ -298,7 +299,8 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], cx<T>* lds, Addr addr,
 // Full length-L FFT of the line held in v (natural positions t + m L/E on entry and exit).
 // Every thread of the block must call it (it contains __syncthreads when L > E).  ZIN: the upper
 // half of the line is zero on entry (v[E/2 ..] are not read).  TWL: length of the twiddle table
-// (the global table of TW_N entries, or a copy of the L entries of this length in LDS).
+// (the global table of TW_N entries), or kTwStaged for the stage-major table of this length in
+// LDS (TwStage).
 template <typename T, int L, int E, bool INV, bool ZIN = false, int TWL = TW_N, typename Addr>
 __device__ __forceinline__ void fft_line(cx<T> (&v)[E], cx<T>* lds, Addr addr, int t,
                                          const cx<T>* __restrict__ tw) {

@@ -38,11 +38,19 @@ CAL_BYTES = 1 << 30
 KERNEL_SOURCES = ("csrc/passes.hpp", "csrc/fft.hpp", "csrc/operator.hip")
 
 
+def _code_only(text):
+    """Source text without comments and blank lines (a comment edit changes no kernel)."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = (re.sub(r"//.*", "", ln).rstrip() for ln in text.splitlines())
+    return "\n".join(ln for ln in lines if ln)
+
+
 def sources_hash():
+    """Hash of the kernel sources the operator passes are built from, comments excluded."""
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(_HERE, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(_HERE, rel), encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 
