@@ -11,10 +11,14 @@ integral equation method and domain decomposition preconditioning", GJI):
 * ``operator`` - the FFT convolution of eq. (10) with 2x zero padding and the
                  operator (I - G dsigma) of eq. (8); the contraction form;
 * ``dense``    - brute-force dense assembly of the same operator (no FFT);
-* ``gmres``    - restarted GMRES (Saad & Schultz) with modified Gram-Schmidt;
+* ``gmres``    - restarted GMRES (Saad & Schultz) with modified Gram-Schmidt,
+                 and flexible GMRES (right preconditioner that may change);
 * ``solve``    - full-domain solves and the relative residual of eq. (9);
 * ``dd``       - Alg. 1: block Gauss-Seidel / Jacobi sweeps (eqs. 19-24)
-                 with fixed or adaptive inner tolerance;
+                 with fixed or adaptive inner tolerance, and the Krylov outer
+                 iteration over one sweep from zero;
+* ``receivers``- magnetic field at receiver points (eqs. 4 and 6) by direct
+                 summation over the cell currents;
 * ``cnn``      - plain CPU reference of the learned-initial-guess network.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s CPU-baseline leg
