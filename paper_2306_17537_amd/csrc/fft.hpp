@@ -192,7 +192,36 @@ template <int L, int E>
 constexpr int tw_staged_size() {
   return tw_stage_off<L, E>(num_stages<L, E>());
 }
-// exponent e of W_L^e stored at index i of the stage-major table
+// First-twiddle table: stage s (Ns > 1) holds only W_{Ns R}^k at tw_first_off(s) + k, k < Ns,
+// and the stage forms W^{r k}, r = 2 .. R-1, as successive powers of it (R - 2 complex
+// products, a few float64 roundings).  It takes sum Ns entries instead of sum (R - 1) Ns, which
+// is what lets one more block of the float64 x pass share a CU's LDS.
+constexpr int kTwFirst = -2;  // TWL value that selects this layout
+template <int L, int E>
+constexpr int tw_first_off(int S) {
+  int off = 0;
+  for (int s = 0; s < S; ++s) {
+    const int ns = stage_ns<L, E>(s);
+    if (ns > 1) off += ns;
+  }
+  return off;
+}
+template <int L, int E>
+constexpr int tw_first_size() {
+  return tw_first_off<L, E>(num_stages<L, E>());
+}
+template <int L, int E>
+__device__ __forceinline__ int tw_first_exp(int i) {
+  int off = 0;
+  for (int s = 1; s < num_stages<L, E>(); ++s) {
+    const int ns = stage_ns<L, E>(s), R = stage_radix<L, E>(s);
+    if (i < off + ns) return (i - off) * (L / (ns * R));
+    off += ns;
+  }
+  return 0;
+}
+// exponent e of W_L^e stored at index i of the stage-major table (tw_first_exp: of the
+// first-twiddle table)
 template <int L, int E>
 __device__ __forceinline__ int tw_staged_exp(int i) {
   int off = 0;
@@ -234,8 +263,8 @@ struct LdsPadded {  // line-major, one pad slot every 16 positions (conflict-fre
 
 // ZIN: the positions L/2 .. L-1 are zero on entry (registers E/2 .. E-1), so the first stage
 // takes the zero upper half of each butterfly's inputs into account.  TWL: length of the
-// twiddle table tw (entries exp(-2 pi i k / TWL); a multiple of L), or kTwStaged for the
-// stage-major table of this length and register width.
+// twiddle table tw (entries exp(-2 pi i k / TWL); a multiple of L), or kTwStaged / kTwFirst for
+// the stage-major or first-twiddle table of this length and register width.
 template <typename T, int L, int E, int S, bool INV, bool ZIN, int TWL, typename Addr>
 __device__ __forceinline__ void fft_stage(cx<T> (&v)[E], cx<T>* __restrict__ lds, Addr addr,
                                           int t, const cx<T>* __restrict__ tw) {
@@ -254,7 +283,16 @@ __device__ __forceinline__ void fft_stage(cx<T> (&v)[E], cx<T>* __restrict__ lds
 #pragma unroll
     for (int r = 0; r < R; ++r) u[r] = v[b + r * NB];
     if constexpr (NS > 1) {
-      if constexpr (TWL == kTwStaged) {
+      if constexpr (TWL == kTwFirst) {
+        const cx<T> w1 = twiddle<T, INV>(tw, tw_first_off<L, E>(S) + k);
+        cx<T> wr = w1;
+        u[1] = u[1] * w1;
+#pragma unroll
+        for (int r = 2; r < R; ++r) {
+          wr = wr * w1;
+          u[r] = u[r] * wr;
+        }
+      } else if constexpr (TWL == kTwStaged) {
         constexpr int off = tw_stage_off<L, E>(S);
 #pragma unroll
         for (int r = 1; r < R; ++r) u[r] = u[r] * twiddle<T, INV>(tw, off + (r - 1) * NS + k);
@@ -299,12 +337,13 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], cx<T>* lds, Addr addr,
 // Full length-L FFT of the line held in v (natural positions t + m L/E on entry and exit).
 // Every thread of the block must call it (it contains __syncthreads when L > E).  ZIN: the upper
 // half of the line is zero on entry (v[E/2 ..] are not read).  TWL: length of the twiddle table
-// (the global table of TW_N entries), or kTwStaged for the stage-major table of this length in
-// LDS (TwStage).
+// (the global table of TW_N entries), or kTwStaged / kTwFirst for the stage-major or
+// first-twiddle table of this length in LDS (TwStage).
 template <typename T, int L, int E, bool INV, bool ZIN = false, int TWL = TW_N, typename Addr>
 __device__ __forceinline__ void fft_line(cx<T> (&v)[E], cx<T>* lds, Addr addr, int t,
                                          const cx<T>* __restrict__ tw) {
-  static_assert(L % E == 0 && L <= MAX_FFT_LEN && (TWL == kTwStaged || TWL % L == 0),
+  static_assert(L % E == 0 && L <= MAX_FFT_LEN &&
+                    (TWL == kTwStaged || TWL == kTwFirst || TWL % L == 0),
                 "bad FFT length");
   fft_stages<T, L, E, INV, ZIN, TWL>(v, lds, addr, t, tw,
                                      std::make_integer_sequence<int, num_stages<L, E>()>{});
@@ -401,17 +440,19 @@ __device__ __forceinline__ void fft_lines(cx<T> (&v)[NC][E], cx<T>* lds, Addr ad
 // from the global table into LDS by the NT threads of a block in two steps: load() issues the
 // global reads into registers (call it before the block's other global reads, so that waiting
 // for these leaves those in flight), store() writes them to LDS; a barrier must follow before
-// the table is read.  The LDS table needs tw_staged_size<L, E>() < L entries.
-template <typename T, int L, int E, int NT>
+// the table is read.  The LDS table needs tw_staged_size<L, E>() < L entries (FIRST: the
+// first-twiddle table, tw_first_size<L, E>() entries).
+template <typename T, int L, int E, int NT, bool FIRST = false>
 struct TwStage {
-  static constexpr int N = tw_staged_size<L, E>();
+  static constexpr int N = FIRST ? tw_first_size<L, E>() : tw_staged_size<L, E>();
   static constexpr int K = N > 0 ? (N + NT - 1) / NT : 0;
   cx<T> r[K > 0 ? K : 1];
   __device__ __forceinline__ void load(const cx<T>* __restrict__ tw, int tid) {
 #pragma unroll
     for (int i = 0; i < K; ++i) {
       const int k = tid + i * NT;
-      r[i] = k < N ? tw[tw_staged_exp<L, E>(k) * (TW_N / L)] : cx<T>{0, 0};
+      const int e = FIRST ? tw_first_exp<L, E>(k) : tw_staged_exp<L, E>(k);
+      r[i] = k < N ? tw[e * (TW_N / L)] : cx<T>{0, 0};
     }
   }
   __device__ __forceinline__ void store(cx<T>* tab, int tid) const {

@@ -478,7 +478,13 @@ struct GeoX2 {
   // against 6.6e7 padded); float32 lines: padded
   using Lds = typename std::conditional<sizeof(T) == 8, LdsSwz, LdsPadded>::type;
   static constexpr int LP = Lds::padded_len(LX);
-  static constexpr bool FITS = (6 * NP * LP + LX) * int(sizeof(cx<T>)) <= 160 * 1024 &&
+  // float64: the first-twiddle table (72 entries at LX = 256 instead of 248), so that six
+  // one-row-pair blocks fit a CU's LDS instead of five; float32 keeps the stage-major table
+  // (its x pass is bound by vector issue, and powers of a float32 twiddle lose accuracy)
+  static constexpr bool TFIRST = sizeof(T) == 8;
+  static constexpr int TWN = TFIRST ? tw_first_size<LX, E>() : LX;
+  static constexpr int TWL = TFIRST ? kTwFirst : kTwStaged;
+  static constexpr bool FITS = (6 * NP * LP + TWN) * int(sizeof(cx<T>)) <= 160 * 1024 &&
                                THREADS <= 1024;
   static constexpr int ITEMS = (NP * LX + THREADS - 1) / THREADS;  // multiply items per thread
 };
@@ -488,12 +494,12 @@ __global__ void __launch_bounds__((GeoX2<T, LX, V>::THREADS)) k_xconv2(const MvA
   using G = GeoX2<T, LX, V>;
   constexpr int E = G::E, TL = G::TL, NP = G::NP;
   __shared__ cx<T> lds[6 * NP * G::LP];
-  __shared__ cx<T> twl[LX];  // the stage-major twiddle table (fewer than LX entries)
+  __shared__ cx<T> twl[G::TWN > 0 ? G::TWN : 1];
   const int b = blockIdx.z;
   if (retired(a, b)) return;
   // the global reads of the block are issued up front (twiddles, the lines and, with PRE, the
   // spectrum values of the multiply), so that their latencies overlap
-  TwStage<T, LX, E, G::THREADS> tws;
+  TwStage<T, LX, E, G::THREADS, G::TFIRST> tws;
   tws.load(a.tw, threadIdx.x);
   const int hx = LX / 2, hy = a.LY / 2, hz = a.LZ / 2;
   const int t = threadIdx.x % TL;
@@ -539,7 +545,7 @@ __global__ void __launch_bounds__((GeoX2<T, LX, V>::THREADS)) k_xconv2(const MvA
   }
   tws.store(twl, threadIdx.x);
   __syncthreads();  // the twiddle table
-  fft_line<T, LX, E, false, true, kTwStaged>(v, lds, addr, t, twl);
+  fft_line<T, LX, E, false, true, G::TWL>(v, lds, addr, t, twl);
   // the last stage ran in registers after every thread's last LDS read of this line
 #pragma unroll
   for (int m = 0; m < E; ++m) lds[addr(t + m * TL)] = v[m];
@@ -584,7 +590,7 @@ __global__ void __launch_bounds__((GeoX2<T, LX, V>::THREADS)) k_xconv2(const MvA
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = lds[addr(t + m * TL)];
   __syncthreads();  // every read of the line done before its first inverse stage writes
-  fft_line<T, LX, E, true, false, kTwStaged>(v, lds, addr, t, twl);
+  fft_line<T, LX, E, true, false, G::TWL>(v, lds, addr, t, twl);
   if (live) {
 #pragma unroll
     for (int m = 0; m < E / 2; ++m) {
