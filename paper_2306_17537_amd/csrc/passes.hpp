@@ -28,6 +28,20 @@
 
 namespace ie {
 
+// Load of a pass input that the previous pass wrote and nothing reads again (the column-pass
+// inputs, the z inverse's input, the x pass's rows), with the non-temporal hint: these arrays
+// are several times the last-level cache, and keeping them out of it lets the contrast tensor
+// and the operator's input x, which the first and the last pass both read, survive in between
+// (measured: float64 GMRES(10) solve of the 128x128x256 model 1.6 % faster, mixed GMRES(16)
+// 2.5 %).  The stored spectrum is read with plain loads: the blocks of kz and LZ - kz share it
+// through the L2.
+template <typename T>
+__device__ __forceinline__ cx<T> load_stream(const cx<T>* p) {
+  typedef T V2 __attribute__((ext_vector_type(2)));
+  const V2 r = __builtin_nontemporal_load(reinterpret_cast<const V2*>(p));
+  return cx<T>{r.x, r.y};
+}
+
 // Store of one pass output value.  complex64 outputs use one 8-byte store with the non-temporal
 // hint (they are read by the next pass only; measured 5-15 % faster per pass on the 64^3 grid);
 // complex128 outputs use a plain store (the hint made the float64 z pass slower).
@@ -180,7 +194,7 @@ __global__ void __launch_bounds__((Geo<T, L, V>::W * Geo<T, L, V>::TL))
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int r = t + m * TL;
-    v[m] = ((INV || m < ME) && live && r < a.rows_in) ? src[r * a.in_ls] : cx<T>{0, 0};
+    v[m] = ((INV || m < ME) && live && r < a.rows_in) ? load_stream(&src[r * a.in_ls]) : cx<T>{0, 0};
   }
   if constexpr (HALF) {
     tws.store(twl, threadIdx.x);
@@ -319,7 +333,7 @@ __global__ void __launch_bounds__((GeoC<T, LZ, V>::THREADS)) k_zinv(const MvArgs
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int m = 0; m < E; ++m)
-      v[c][m] = live ? in[c * cs + long(t + m * TL) * plane] : cx<T>{0, 0};
+      v[c][m] = live ? load_stream(&in[c * cs + long(t + m * TL) * plane]) : cx<T>{0, 0};
   tws.store(twl, threadIdx.x);
   __syncthreads();
   fft_lines<T, LZ, E, true, 3, false, kTwStaged>(v, lds, LdsInterleaved{W, w}, t, twl);
@@ -521,7 +535,7 @@ __global__ void __launch_bounds__((GeoX2<T, LX, V>::THREADS)) k_xconv2(const MvA
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int i = t + m * TL;
-    v[m] = (m < E / 2 && live && i < a.nx) ? row[i] : cx<T>{0, 0};
+    v[m] = (m < E / 2 && live && i < a.nx) ? load_stream(&row[i]) : cx<T>{0, 0};
   }
   // spectrum values of the multiply items (pair, kx) of this thread
   const long gys = hx + 1;
